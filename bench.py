@@ -1,0 +1,161 @@
+"""Benchmark of the partitioner's hot path on one MI355X.
+
+One step = one complete partitioning of the synthetic 65,536-node random
+SNN-shaped hypergraph (one h-edge per node: source + 191 distinct uniform
+destinations, 12,582,912 pins, Omega = 2^10, Delta = 2^12): load from
+HBM-resident tensors (on-device validation and incidence build), every
+coarsening level, and refinement of every level with Theta = 16 repetitions.
+
+Prints one JSON line: pins/s of the whole step (input pins / step time), the
+per-level pins/s, HIP-event times of the dominant kernel family with its
+roofline, and the serial oracle's rate on a bounded sample of the same
+workload family as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rand-64k-e192")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
+    ap.add_argument("--cpu-nodes", type=int, default=4096)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kernel, levels, pi):
+    """Compulsory HBM bytes per launch family summed over one step, from the
+    level sizes (N, E, P) of the hierarchy.  Ids 4 B, offsets 8 B."""
+    tot = 0
+    for (N, E, P, _pairs) in levels:
+        if kernel == "propose":
+            # incidence (inc, inc_off, inc_nin) + h-edge CSR (he_off, he_nsrc, pins, w)
+            # + node sizes + candidates/scores written
+            tot += 4 * P + 8 * (N + 1) + 4 * N + 8 * (E + 1) + 4 * E + 4 * P + 4 * E + 4 * N + 12 * pi * N
+    return tot
+
+
+def cpu_baseline(args):
+    """Serial oracle (one host core), full coarsen + refine on a bounded
+    sample of the workload family: a random SNN-shaped hypergraph with the
+    same h-edge size 192 and the same Delta, on cpu_nodes nodes, Omega scaled
+    by the node ratio.  Rate = input pins / wall time."""
+    import oracle
+    from paper_2605_20497_amd import workloads as W
+    n = args.cpu_nodes
+    omega = max(16, (1 << 10) * n // 65536)
+    hg = W.random_snn(n, 191, seed=0)
+    g = oracle.Graph(hg)
+    t0 = time.perf_counter()
+    res = g.partition(omega, 1 << 12)
+    dt = time.perf_counter() - t0
+    return {"value": hg.n_pins / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": "rand-%d-e192 (%d nodes, %d pins, Omega=%d, Delta=4096), full coarsen+refine, %d levels, "
+                      "%.1f s on one host core" % (n, n, hg.n_pins, omega, res.nlevels, dt)}
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(sharding across GPUs is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2605_20497_amd as pkg
+    from paper_2605_20497_amd import workloads as W
+
+    hg = W.CONFIGS[args.workload]()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_he_off = torch.from_numpy(hg.he_off).to(dev)
+    t_nsrc = torch.from_numpy(hg.he_nsrc).to(dev)
+    t_pins = torch.from_numpy(hg.pins).to(dev)
+    t_hw = torch.from_numpy(hg.hedge_w).to(dev)
+    t_nw = torch.from_numpy(hg.node_w).to(dev)
+    torch.cuda.synchronize()
+
+    part = pkg.Partitioner(device=0, profile=True)
+
+    def step():
+        part.hgp_load_csr_device(hg.n_nodes, t_he_off, t_nsrc, t_pins, t_hw, t_nw)
+        part.hgp_set_limits(hg.omega, hg.delta, hg.k)
+        part.hgp_coarsen()
+        part.hgp_refine()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    part.hgp_reset_kernel_stats()
+    level_times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        level_times.append(part.hgp_level_times())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    stats = part.hgp_kernel_stats()
+    levels = part.hgp_get_levels()
+    ev = part.hgp_evaluate()
+    lt = np.median(np.stack(level_times), axis=0)
+
+    per_level = []
+    for lv, (N, E, P, pairs) in enumerate(levels.tolist()):
+        tc, tr = lt[lv] * 1e-9
+        per_level.append({"level": lv, "nodes": N, "pins": P, "coarsen_ms": round(tc * 1e3, 3),
+                          "refine_ms": round(tr * 1e3, 3),
+                          "pins_per_s": (P / (tc + tr)) if tc + tr > 0 else None})
+    # dominant kernel family by total HIP-event time over the timed steps
+    fam = {k: v for k, v in stats.items() if v[0] > 0}
+    total_ns = sum(v[1] for v in fam.values())
+    dom = max(fam, key=lambda k: fam[k][1])
+    breakdown = {k: {"launches": v[0] // args.steps, "ms_per_step": round(v[1] / args.steps * 1e-6, 3)}
+                 for k, v in sorted(fam.items(), key=lambda kv: -kv[1][1])}
+    roof = None
+    prop = fam.get("propose")
+    if prop:
+        t_launch = prop[1] / prop[0] * 1e-9
+        nbytes = algorithmic_bytes("propose", levels.tolist(), part.pi) / (prop[0] / args.steps)
+        ach = nbytes / t_launch / 1e9
+        roof = {"kernel": "propose", "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                "avg_launch_ms": round(t_launch * 1e3, 4), "algorithmic_bytes_per_launch": int(nbytes)}
+
+    out = {
+        "metric": "pins/s per coarsen+refine level & % HBM peak; batched vs plain jobs/s, p50/p99",
+        "value": hg.n_pins / dt, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "nodes": hg.n_nodes, "hedges": hg.n_hedges, "pins": hg.n_pins,
+                   "omega": hg.omega, "delta": hg.delta, "pi": part.pi, "theta": part.theta,
+                   "levels": int(levels.shape[0]), "partitions": int(ev["n_parts"]), "conn": int(ev["conn"]),
+                   "violations": int(ev["violations"])},
+        "levels": per_level,
+        "kernels": breakdown,
+        "dominant_kernel": dom,
+        "kernel_time_share": round(total_ns / args.steps * 1e-9 / dt, 4) if dt > 0 else None,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args)
+    part.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,295 @@
+"""Python binding of ``libhgp.so`` (the C ABI declared in ``include/hgp.h``).
+
+Argument marshalling only: every step of the partitioner runs in the library's
+HIP kernels.  PyTorch provides device memory (its caching allocator is handed
+to the library as the allocator callback) and the stream (the current torch
+stream).  The binding raises if the library is not built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhgp.so")
+
+HGP_OK, HGP_E_INVALID, HGP_E_INFEASIBLE, HGP_E_NOMEM, HGP_E_DEVICE, HGP_E_STATE, HGP_E_UNSUPPORTED = range(7)
+HGP_MEM_HOST, HGP_MEM_DEVICE = 0, 1
+INT64_MAX = (1 << 63) - 1
+
+_STATUS = {0: "OK", 1: "INVALID", 2: "INFEASIBLE", 3: "NOMEM", 4: "DEVICE", 5: "STATE", 6: "UNSUPPORTED"}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class hgp_options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p), ("pi", C.c_int32), ("theta", C.c_int32), ("seed", C.c_uint64),
+                ("profile", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class hgp_eval(C.Structure):
+    _fields_ = [("conn", C.c_int64), ("cutnet", C.c_int64), ("max_size", C.c_int64),
+                ("max_inbound", C.c_int64), ("violations", C.c_int64), ("n_parts", C.c_int64)]
+
+
+class HgpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Loads libhgp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhgp.so is not built; run paper_2605_20497_amd.build.build() "
+                              "(or __graft_entry__.build()) first")
+        # torch ships its own HIP runtime, requested by an unversioned name;
+        # importing torch first makes libhgp.so bind to that same runtime (its
+        # soname matches), so the process holds one runtime, not two.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "hgp_default_options": (None, [C.POINTER(hgp_options)]),
+            "hgp_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(hgp_options)]),
+            "hgp_destroy": (None, [P]),
+            "hgp_last_error": (C.c_char_p, [P]),
+            "hgp_load_csr": (C.c_int, [P, i32, i32, P, P, P, P, P, C.c_int]),
+            "hgp_set_limits": (C.c_int, [P, i64, i64, i32]),
+            "hgp_coarsen": (C.c_int, [P, C.POINTER(i32)]),
+            "hgp_refine": (C.c_int, [P]),
+            "hgp_get_levels": (C.c_int, [P, P, i64]),
+            "hgp_get_cluster_map": (C.c_int, [P, i32, P, i64]),
+            "hgp_get_proposal": (C.c_int, [P, i32, P, P, P, i64]),
+            "hgp_get_level_graph": (C.c_int, [P, i32, P, P, P, P]),
+            "hgp_get_partition": (C.c_int, [P, P, i64, C.POINTER(i32)]),
+            "hgp_get_phi": (C.c_int, [P, P, P, P, P, i64, C.POINTER(i64)]),
+            "hgp_evaluate": (C.c_int, [P, P, i32, C.POINTER(hgp_eval)]),
+            "hgp_refine_rep": (C.c_int, [P, P, i32, i32, P, P, P, P, P, P, P, P]),
+            "hgp_kernel_stats": (C.c_int, [P, C.POINTER(C.c_char_p), P, P, C.POINTER(i32)]),
+            "hgp_reset_kernel_stats": (C.c_int, [P]),
+            "hgp_level_times": (C.c_int, [P, P, i64]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
+            "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
+            "hgp_get_proposal", "hgp_get_level_graph", "hgp_get_partition", "hgp_get_phi", "hgp_evaluate",
+            "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_level_times"]
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _torch_allocator(device):
+    """Allocator callbacks backed by torch's caching allocator."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:  # noqa: BLE001 - the library turns NULL into HGP_E_NOMEM
+            return None
+
+    def _free(ptr, nbytes, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:  # noqa: BLE001 - interpreter teardown: the process frees everything
+            pass
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
+class Partitioner:
+    """One library context on one device and torch stream."""
+
+    def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
+                 use_torch: bool = True, stream=None):
+        L = lib()
+        opt = hgp_options()
+        L.hgp_default_options(C.byref(opt))
+        opt.device, opt.pi, opt.theta, opt.seed, opt.profile = device, pi, theta, seed, int(profile)
+        self._keep = []
+        self._stream = None
+        if use_torch:
+            import torch
+            torch.cuda.set_device(device)
+            if stream is None:
+                stream = torch.cuda.Stream(device)  # default priority
+            opt.stream = C.c_void_p(stream.cuda_stream)
+            self._stream = stream
+            a, f = _torch_allocator(device)
+            opt.alloc, opt.free = a, f
+            self._keep += [a, f, stream]
+        self.pi, self.theta = pi, theta
+        h = C.c_void_p()
+        st = L.hgp_create(C.byref(h), C.byref(opt))
+        if st != HGP_OK:
+            raise HgpError(st, "hgp_create failed")
+        self.h = h.value
+        self.N = self.E = self.P = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hgp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _chk(self, st):
+        if st != HGP_OK:
+            raise HgpError(st, lib().hgp_last_error(self.h).decode())
+
+    # -- calls with the C ABI's names --------------------------------------
+    def hgp_load_csr(self, n_nodes, he_off, he_nsrc, pins, hedge_w=None, node_w=None):
+        he_off = np.ascontiguousarray(he_off, np.int64)
+        he_nsrc = np.ascontiguousarray(he_nsrc, np.int32)
+        pins = np.ascontiguousarray(pins, np.int32)
+        hw = None if hedge_w is None else np.ascontiguousarray(hedge_w, np.int32)
+        nw = None if node_w is None else np.ascontiguousarray(node_w, np.int32)
+        E = he_nsrc.shape[0]
+        self._chk(lib().hgp_load_csr(self.h, int(n_nodes), int(E), _p(he_off), _p(he_nsrc), _p(pins), _p(hw),
+                                     _p(nw), HGP_MEM_HOST))
+        self.N, self.E, self.P = int(n_nodes), int(E), int(he_off[-1])
+
+    def hgp_load_csr_device(self, n_nodes, he_off, he_nsrc, pins, hedge_w=None, node_w=None):
+        """Same, from torch device tensors (int64 / int32)."""
+        import torch
+        self._stream.wait_stream(torch.cuda.current_stream())
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        self._chk(lib().hgp_load_csr(self.h, int(n_nodes), int(he_nsrc.numel()), ptr(he_off), ptr(he_nsrc),
+                                     ptr(pins), ptr(hedge_w), ptr(node_w), HGP_MEM_DEVICE))
+        self.N, self.E, self.P = int(n_nodes), int(he_nsrc.numel()), int(pins.numel())
+
+    def hgp_set_limits(self, omega, delta, k=0):
+        self._chk(lib().hgp_set_limits(self.h, int(omega), int(delta), int(k)))
+
+    def hgp_coarsen(self):
+        n = C.c_int32()
+        self._chk(lib().hgp_coarsen(self.h, C.byref(n)))
+        self.nlevels = n.value
+        return n.value
+
+    def hgp_refine(self):
+        self._chk(lib().hgp_refine(self.h))
+
+    def hgp_get_levels(self):
+        out = np.zeros(4 * self.nlevels, np.int64)
+        self._chk(lib().hgp_get_levels(self.h, _p(out), out.size))
+        return out.reshape(-1, 4)
+
+    def hgp_get_cluster_map(self, level):
+        n = int(self.hgp_get_levels()[level, 0])
+        out = np.zeros(n, np.int32)
+        self._chk(lib().hgp_get_cluster_map(self.h, level, _p(out), n))
+        return out
+
+    def hgp_get_proposal(self, level):
+        n = int(self.hgp_get_levels()[level, 0])
+        cand = np.zeros((n, self.pi), np.int32)
+        score = np.zeros((n, self.pi), np.uint64)
+        match = np.zeros(n, np.int32)
+        self._chk(lib().hgp_get_proposal(self.h, level, _p(cand), _p(score), _p(match), n))
+        return cand, score, match
+
+    def hgp_get_level_graph(self, level):
+        N, E, P, _ = (int(x) for x in self.hgp_get_levels()[level])
+        he_off = np.zeros(E + 1, np.int64)
+        nsrc = np.zeros(E, np.int32)
+        pins = np.zeros(P, np.int32)
+        nw = np.zeros(N, np.int32)
+        self._chk(lib().hgp_get_level_graph(self.h, level, _p(he_off), _p(nsrc), _p(pins), _p(nw)))
+        return he_off, nsrc, pins, nw
+
+    def hgp_get_partition(self):
+        rho = np.zeros(self.N, np.int32)
+        k = C.c_int32()
+        self._chk(lib().hgp_get_partition(self.h, _p(rho), self.N, C.byref(k)))
+        return rho, k.value
+
+    def hgp_get_phi(self):
+        need = C.c_int64()
+        self._chk(lib().hgp_get_phi(self.h, None, None, None, None, 0, C.byref(need)))
+        L = need.value
+        off = np.zeros(self.E + 1, np.int64)
+        part = np.zeros(L, np.int32)
+        cnt = np.zeros(L, np.int32)
+        cin = np.zeros(L, np.int32)
+        self._chk(lib().hgp_get_phi(self.h, _p(off), _p(part), _p(cnt), _p(cin), L, C.byref(need)))
+        return off, part, cnt, cin
+
+    def hgp_evaluate(self, rho=None, n_parts=0):
+        ev = hgp_eval()
+        r = None if rho is None else np.ascontiguousarray(rho, np.int32)
+        self._chk(lib().hgp_evaluate(self.h, _p(r), int(n_parts), C.byref(ev)))
+        return dict(conn=ev.conn, cutnet=ev.cutnet, max_size=ev.max_size, max_inbound=ev.max_inbound,
+                    violations=ev.violations, n_parts=ev.n_parts)
+
+    def hgp_refine_rep(self, rho, n_parts, rep):
+        r = np.array(rho, np.int32, copy=True)
+        N = r.shape[0]
+        info = np.zeros(4, np.int64)
+        seq = np.zeros(N, np.int32)
+        sd = np.zeros(N, np.int32)
+        gseq = np.zeros(N, np.int64)
+        Ck = np.zeros(N + 1, np.int64)
+        Vk = np.zeros(N + 1, np.int64)
+        mdst = np.zeros(N, np.int32)
+        mgain = np.zeros(N, np.int64)
+        self._chk(lib().hgp_refine_rep(self.h, _p(r), int(n_parts), int(rep), _p(info), _p(mdst), _p(mgain), _p(seq),
+                                       _p(sd), _p(gseq), _p(Ck), _p(Vk)))
+        M = int(info[0])
+        return r, dict(moves=M, kstar=int(info[1]), gain=int(info[2]), links=int(info[3]), move_dst=mdst,
+                       move_gain=mgain, seq=seq[:M],
+                       seq_pd=sd[:M], gseq=gseq[:M], C=Ck[:M + 1], V=Vk[:M + 1])
+
+    def hgp_kernel_stats(self):
+        cnt = C.c_int32()
+        self._chk(lib().hgp_kernel_stats(self.h, None, None, None, C.byref(cnt)))
+        n = cnt.value
+        names = (C.c_char_p * n)()
+        launches = np.zeros(n, np.int64)
+        ns = np.zeros(n, np.int64)
+        self._chk(lib().hgp_kernel_stats(self.h, names, _p(launches), _p(ns), C.byref(cnt)))
+        return {names[i].decode(): (int(launches[i]), int(ns[i])) for i in range(n)}
+
+    def hgp_reset_kernel_stats(self):
+        self._chk(lib().hgp_reset_kernel_stats(self.h))
+
+    def hgp_level_times(self):
+        out = np.zeros(2 * self.nlevels, np.int64)
+        self._chk(lib().hgp_level_times(self.h, _p(out), out.size))
+        return out.reshape(-1, 2)
+
+    # -- convenience -------------------------------------------------------
+    def load(self, hg):
+        self.hgp_load_csr(hg.n_nodes, hg.he_off, hg.he_nsrc, hg.pins, hg.hedge_w, hg.node_w)
+
+    def partition(self, hg, omega=None, delta=None, k=None):
+        self.load(hg)
+        self.hgp_set_limits(hg.omega if omega is None else omega, hg.delta if delta is None else delta,
+                            hg.k if k is None else k)
+        self.hgp_coarsen()
+        self.hgp_refine()
+        return self.hgp_get_partition()

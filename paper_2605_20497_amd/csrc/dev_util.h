@@ -1,0 +1,189 @@
+// Device-side helpers for gfx950 (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hgp_internal.h"
+
+namespace hgp {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        T t = __shfl_xor(v, o, kWave);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        T t = __shfl_xor(v, o, kWave);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+// Inclusive prefix sum across the wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T t = __shfl_up(v, o, kWave);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+// Comparisons that pick between two (key, id) pairs are written with bitwise
+// operators on operands already in registers, so the device compiler emits
+// selects instead of short-circuit branches: a short-circuit form, where the
+// condition guards updates of two variables, was compiled into code that lost
+// one of the updates on some lanes.
+template <typename K>
+__device__ __forceinline__ bool lex_gt(K k1, i32 i1, K k2, i32 i2) {
+    return ((int)(k1 > k2) | ((int)(k1 == k2) & (int)(i1 > i2))) != 0;
+}
+
+// (k1, i1) beats (k2, i2) where id < 0 marks an empty entry.
+template <typename K>
+__device__ __forceinline__ bool lex_better(K k1, i32 i1, K k2, i32 i2) {
+    return ((int)(i1 >= 0) & ((int)(i2 < 0) | (int)lex_gt(k1, i1, k2, i2))) != 0;
+}
+
+// Lexicographic max of (key, id) across the wave; every lane receives it.
+__device__ __forceinline__ void wave_lexmax(u64& key, i32& id) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const u64 k2 = __shfl_xor(key, o, kWave);
+        const i32 i2 = __shfl_xor(id, o, kWave);
+        const bool t = lex_gt(k2, i2, key, id);
+        key = t ? k2 : key;
+        id = t ? i2 : id;
+    }
+}
+
+// Same over signed keys with id < 0 marking an empty entry.
+__device__ __forceinline__ void wave_lexmax_i64(i64& key, i32& id) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const i64 k2 = __shfl_xor(key, o, kWave);
+        const i32 i2 = __shfl_xor(id, o, kWave);
+        const bool t = lex_better(k2, i2, key, id);
+        key = t ? k2 : key;
+        id = t ? i2 : id;
+    }
+}
+
+// Block-wide sum (blockDim.x a multiple of 64, at most 1024).  `red` is
+// shared scratch of at least 16 entries.  Every thread receives the total.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+    v = wave_sum(v);
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if (lane_id() == 0) red[wave_id()] = v;
+    __syncthreads();
+    T t = 0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// Block-wide exclusive prefix sum of one value per thread; *total receives
+// the block total.  `red` holds at least 16 entries.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* red, T* total) {
+    T inc = wave_incl_scan(v);
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if (lane_id() == kWave - 1) red[wave_id()] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave_id()) off += red[w];
+        tot += red[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Order-preserving map of a signed 64-bit value onto unsigned.
+__device__ __forceinline__ u64 enc_i64(i64 x) { return (u64)x ^ 0x8000000000000000ull; }
+__device__ __forceinline__ i64 dec_i64(u64 x) { return (i64)(x ^ 0x8000000000000000ull); }
+
+// SplitMix64 output mixing function (Steele, Lea, Flood, OOPSLA 2014).
+__device__ __forceinline__ u64 splitmix_mix(u64 z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Symmetric histogram noise of Sec. V-C: hash of the unordered pair {a, b}
+// and the seed, reduced into [0, cap].
+__device__ __forceinline__ u64 pair_noise(u64 seed, i32 a, i32 b, u64 cap) {
+    if (cap == 0) return 0;
+    const u64 lo = (u64)(u32)(a < b ? a : b);
+    const u64 hi = (u64)(u32)(a < b ? b : a);
+    return splitmix_mix(seed ^ splitmix_mix((lo << 32) | hi)) % (cap + 1);
+}
+
+// Normalised h-edge weight omega(e)/|e| in 16-bit fixed point, at least 1.
+__device__ __forceinline__ u64 norm_weight(i32 w, i64 card) {
+    const u64 t = ((u64)(u32)w << 16) / (u64)card;
+    return t ? t : 1;
+}
+
+// Bitonic sort of s[0 .. npad) in shared memory, npad a power of two; all
+// threads of the block take part.
+__device__ __forceinline__ void block_bitonic_sort_u32(u32* s, int npad) {
+    for (int k = 2; k <= npad; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const u32 a = s[i], b = s[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        s[i] = b;
+                        s[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__host__ __device__ __forceinline__ int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace hgp

@@ -1,0 +1,193 @@
+// Internal declarations shared by the library's translation units.
+// Device helpers, the context layout and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hgp.h"
+
+typedef int32_t i32;
+typedef int64_t i64;
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+namespace hgp {
+
+// ---------------------------------------------------------------------------
+// Errors: thrown inside the library, turned into hgp_status at the ABI.
+// ---------------------------------------------------------------------------
+struct Error {
+    hgp_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(hgp_status st, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define HIPC(x) ::hgp::hip_check((x), #x)
+
+// ---------------------------------------------------------------------------
+// Kernel families timed when profiling is on.
+// ---------------------------------------------------------------------------
+enum Kf {
+    KF_VALIDATE, KF_TRANSPOSE, KF_SORT, KF_SCAN, KF_LEVEL_STATS, KF_PROPOSE, KF_MATCH, KF_ISOLATED,
+    KF_GAMMA, KF_CONTRACT_EDGES, KF_PACK, KF_PHI, KF_PART_STATS, KF_GAINS, KF_MOVES, KF_CHAINS,
+    KF_RANK, KF_INSEQ, KF_EVENTS, KF_SELECT, KF_APPLY, KF_PROJECT, KF_EVAL, KF_MISC, KF_COUNT
+};
+const char* kf_name(int kf);
+
+struct Ctx;
+void prof_begin(Ctx* c, int kf);
+void prof_end(Ctx* c, int kf);
+
+#define LAUNCH(ctx, kf, kern, grid, block, shmem, ...)                                  \
+    do {                                                                                \
+        ::hgp::prof_begin((ctx), (kf));                                                 \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shmem), (ctx)->stream, __VA_ARGS__); \
+        HIPC(hipGetLastError());                                                        \
+        ::hgp::prof_end((ctx), (kf));                                                   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory.
+// ---------------------------------------------------------------------------
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// One hypergraph of the hierarchy, device resident.
+struct Level {
+    i32 N = 0, E = 0;
+    i64 P = 0;
+    i64 pairs = 0;
+    Buf b_he_off, b_he_nsrc, b_pins, b_nw, b_inc_off, b_inc_nin, b_inc, b_gamma, b_cand, b_score, b_match;
+    i64* he_off() const { return (i64*)b_he_off.p; }
+    i32* he_nsrc() const { return (i32*)b_he_nsrc.p; }
+    i32* pins() const { return (i32*)b_pins.p; }
+    i32* nw() const { return (i32*)b_nw.p; }
+    i64* inc_off() const { return (i64*)b_inc_off.p; }
+    i32* inc_nin() const { return (i32*)b_inc_nin.p; }
+    i32* inc() const { return (i32*)b_inc.p; }
+    i32* gamma() const { return (i32*)b_gamma.p; }
+};
+
+struct Prof {
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open;
+    i64 launches[KF_COUNT] = {0};
+    i64 ns[KF_COUNT] = {0};
+    size_t used = 0;
+    hipEvent_t cur_begin = nullptr;
+};
+
+struct Ctx {
+    hgp_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    int num_cu = 256;
+    std::string err;
+
+    bool loaded = false, limits_set = false, coarsened = false, refined = false;
+    i64 omega = 0, delta = 0;
+    i32 k = 0;
+    i64 total_nw = 0, total_hw = 0;
+    i32 max_card = 1;  // largest input h-edge; bounds every level
+
+    Buf b_hw;  // h-edge weights, shared by every level (h-edges keep their id)
+    std::vector<Level> levels;
+    Buf b_rho;  // partition of level 0 after refinement
+    i32 nparts = 0;
+
+    // Growable scratch, reused across levels and repetitions.
+    std::vector<Buf> ws;
+    void* ws_get(int slot, size_t bytes);
+
+    // Pinned host staging for scalars read back by the driver.
+    i64* host_scalars = nullptr;
+
+    // Profiling.
+    Prof prof;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> level_ev_coarsen, level_ev_refine;
+
+    Buf alloc(size_t bytes);
+    void release(Buf& b);
+    void free_level(Level& L);
+    void sync();
+    const i32* hw() const { return (const i32*)b_hw.p; }
+};
+
+template <typename T>
+inline T* wsp(Ctx* c, int slot, size_t count) {
+    return (T*)c->ws_get(slot, count * sizeof(T) + 16);
+}
+
+inline i64 ceil_div(i64 a, i64 b) { return (a + b - 1) / b; }
+inline int grid_for(i64 n, int block, int cap = 1 << 20) {
+    i64 g = ceil_div(n, block);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------------------
+// Primitive launchers (k_prim.hip).
+// ---------------------------------------------------------------------------
+// out[i] = sum_{j<i} in[j] for i in [0, n]; out has n+1 slots (out[n] = total).
+void scan_excl_i64(Ctx* c, const i64* in, i64* out, i64 n);
+void scan_excl_i32_to_i64(Ctx* c, const i32* in, i64* out, i64 n);
+void scan_excl_i32(Ctx* c, const i32* in, i32* out, i64 n);  // caller guarantees the total fits i32
+// Stable LSD radix sorts on the low `bits` bits of the key.
+void sort_pairs_u32(Ctx* c, const u32* kin, u32* kout, const i32* vin, i32* vout, i64 n, int bits);
+void sort_pairs_u64(Ctx* c, const u64* kin, u64* kout, const i32* vin, i32* vout, i64 n, int bits);
+void fill_i32(Ctx* c, i32* p, i32 v, i64 n);
+void fill_i64(Ctx* c, i64* p, i64 v, i64 n);
+void iota_i32(Ctx* c, i32* p, i64 n);
+void gather_i32(Ctx* c, const i32* src, const i32* idx, i32* dst, i64 n);  // dst[i] = src[idx[i]]
+// Reads `count` device i64 values into host memory (synchronises the stream).
+void read_back(Ctx* c, const void* dev, i64* host, int count, int elem_bytes);
+
+// ---------------------------------------------------------------------------
+// Hypergraph launchers (k_graph.hip).
+// ---------------------------------------------------------------------------
+// Validates the input hypergraph; *errcode receives a bit mask (0 = valid) and
+// sums[0..1] the weight totals.
+void validate_graph(Ctx* c, i32 N, i32 E, const i64* he_off, const i32* he_nsrc, const i32* pins, const i32* hw,
+                    const i32* nw, i64 P, i64* d_err_and_sums);
+// Builds the incidence (node -> h-edges, inbound first, ascending ids) of L.
+void build_incidence(Ctx* c, Level& L);
+// Coarse pins of every h-edge through gamma, deduplicated, src' = gamma(src) \ dst'.
+void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out);
+// Phi rows at the h-edge offsets: part / cnt / cnt_in, row length in len[E].
+void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len);
+
+// ---------------------------------------------------------------------------
+// Coarsening launchers (k_coarsen.hip).
+// ---------------------------------------------------------------------------
+void coarsen_level(Ctx* c, int lv);  // builds levels[lv+1] or leaves levels unchanged if no merge
+
+// ---------------------------------------------------------------------------
+// Refinement launchers (k_refine.hip).
+// ---------------------------------------------------------------------------
+struct RepInfo {
+    i64 moves = 0, kstar = 0, gain = 0, links = 0;
+};
+// Host copies of one repetition's intermediate arrays (any pointer may be NULL).
+struct RepTrace {
+    i32* move_dst = nullptr;
+    i64* move_gain = nullptr;
+    i32* seq = nullptr;
+    i32* seq_dst = nullptr;
+    i64* gseq = nullptr;
+    i64* prefix_gain = nullptr;
+    i64* prefix_viol = nullptr;
+};
+RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace = nullptr);
+void project_rho(Ctx* c, const i32* rho_coarse, const i32* gamma, i32* rho_fine, i32 N);
+void evaluate_dev(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out);
+
+}  // namespace hgp

@@ -1,0 +1,515 @@
+// Coarsening of one level (Sec. V): candidate-pair proposal with the neighbour
+// histogram, Pi rounds of exact maximum-weight matching on the proposal
+// pseudo-forest, best-effort pairing of isolated nodes, the cluster map gamma
+// and the coarse hypergraph.
+#include <algorithm>
+
+#include "dev_util.h"
+
+namespace hgp {
+
+namespace {
+
+enum {
+    WS_STATS = 30, WS_T = 31, WS_S = 32, WS_PARENT = 33, WS_J0 = 34, WS_J1 = 35, WS_D0 = 36, WS_D1 = 37,
+    WS_ACC_A = 38, WS_ACC_BV = 39, WS_ACC_BC = 40, WS_SS0 = 41, WS_SS10 = 42, WS_ISO_FLAG = 43, WS_ISO_POS = 44,
+    WS_ISO_KEYS = 45, WS_ISO_KEYS2 = 46, WS_ISO_VALS = 47, WS_ISO_VALS2 = 48, WS_REP = 49, WS_CID = 50
+};
+
+// stats: [0] max_n sum_{e in I(n)} t(e); [1] max |in(n)|; [2] sum of t(e) over
+// h-edges with >= 2 pins; [3] their count; [4] noise cap; [5] max depth;
+// [6] merged pairs; [7] scratch.
+__global__ __launch_bounds__(256) void k_node_tsum(i32 N, const i64* __restrict__ inc_off,
+                                                   const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+                                                   const i64* __restrict__ he_off, const i32* __restrict__ hw,
+                                                   unsigned long long* stats) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    unsigned long long mx = 0, mn = 0;
+    for (i64 n = (i64)blockIdx.x * wpb + wave_id(); n < N; n += (i64)gridDim.x * wpb) {
+        u64 s = 0;
+        for (i64 k = inc_off[n] + lane; k < inc_off[n + 1]; k += kWave) {
+            const i32 e = inc[k];
+            s += norm_weight(hw[e], he_off[e + 1] - he_off[e]);
+        }
+        s = wave_sum(s);
+        mx = mx > s ? mx : s;
+        const unsigned long long ni = (unsigned long long)inc_nin[n];
+        mn = mn > ni ? mn : ni;
+    }
+    if (lane == 0) {
+        atomicMax(&stats[0], mx);
+        atomicMax(&stats[1], mn);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_edge_tsum(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ hw,
+                                                   unsigned long long* stats) {
+    __shared__ unsigned long long red[16];
+    unsigned long long s = 0, c = 0;
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (i64)gridDim.x * blockDim.x) {
+        const i64 card = he_off[e + 1] - he_off[e];
+        if (card >= 2) {
+            s += norm_weight(hw[e], card);
+            c += 1;
+        }
+    }
+    s = block_sum(s, red);
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&stats[2], s);
+        atomicAdd(&stats[3], c);
+    }
+}
+
+// Noise cap: a tenth of the mean normalised weight of h-edges with >= 2 pins.
+__global__ void k_noise_cap(unsigned long long* stats) {
+    stats[4] = stats[3] ? stats[2] / (10ull * stats[3]) : 0ull;
+}
+
+// Candidate proposal (Sec. V-C): one block per node.  The block sweeps n's
+// incident h-edges and their pins and accumulates, per neighbour m, the packed
+// value (eta(n,m) << ib) + inter(n,m) in a shared-memory histogram indexed by
+// m.  Neighbour ids are split into ranges of R that fit the histogram; every
+// range is one pass over the pins.  The pins of one h-edge are distinct, and
+// h-edges run on different waves, so updates are shared-memory atomics.  After
+// each pass, the block scans the bins, adds the symmetric noise, checks
+// validity (Eq. proposal_graph: sizes, and |in(n) ∪ in(m)| through inter), and
+// keeps per thread the best PI valid neighbours by (score desc, id desc); the
+// block merges the thread lists at the end.
+template <typename BIN, int PI>
+__global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ inc_off,
+                                                 const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+                                                 const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
+                                                 const i32* __restrict__ pins, const i32* __restrict__ hw,
+                                                 const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
+                                                 const unsigned long long* __restrict__ stats, int ib, i32* cand,
+                                                 u64* score) {
+    constexpr int R = 65536 / (int)sizeof(BIN);
+    __shared__ BIN bins[R];
+    __shared__ u64 red_s[16];
+    __shared__ i32 red_m[16];
+    const u64 cap = stats[4];
+    const int npass = (int)((N + R - 1) / R);
+    const BIN imask = (((BIN)1) << ib) - 1;
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
+    __syncthreads();
+    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+        u64 bs[PI];
+        i32 bm[PI];
+#pragma unroll
+        for (int r = 0; r < PI; ++r) {
+            bs[r] = 0;
+            bm[r] = -1;
+        }
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        const i32 nin_n = inc_nin[n];
+        const i64 nw_n = nw[n];
+        for (int pass = 0; pass < npass && a < b; ++pass) {
+            const i32 lo = pass * R;
+            const i32 hi = min(N, lo + R);
+            for (i64 k = a + wv; k < b; k += nwv) {
+                const i32 e = inc[k];
+                const bool ein = (k - a) < nin_n;
+                const i64 e0 = he_off[e], e1 = he_off[e + 1];
+                const i64 d0 = e0 + he_nsrc[e];
+                const BIN add = ((BIN)norm_weight(hw[e], e1 - e0)) << ib;
+                for (i64 j = e0 + lane; j < e1; j += kWave) {
+                    const i32 m = pins[j];
+                    if ((int)(m == n) | (int)(m < lo) | (int)(m >= hi)) continue;
+                    atomicAdd(&bins[m - lo], add + (((int)ein & (int)(j >= d0)) ? (BIN)1 : (BIN)0));
+                }
+            }
+            __syncthreads();
+            const int used = hi - lo;
+            for (int sidx = threadIdx.x; sidx < used; sidx += blockDim.x) {
+                const BIN v = bins[sidx];
+                if (v == 0) continue;
+                bins[sidx] = 0;
+                const i32 m = lo + sidx;
+                const u64 eta = (u64)(v >> ib);
+                const i64 inter = (i64)(v & imask);
+                const bool full = bm[PI - 1] >= 0;
+                if ((int)full & (int)(eta + cap < bs[PI - 1])) continue;
+                const u64 sc = eta + pair_noise(seed, n, m, cap);
+                if ((int)full & (int)!lex_gt(sc, m, bs[PI - 1], bm[PI - 1])) continue;
+                const i64 nw_m = nw[m], nin_m = inc_nin[m];
+                if ((int)(nw_n + nw_m > omega) | (int)((i64)nin_n + nin_m - inter > delta)) continue;
+                u64 cs = sc;
+                i32 cm = m;
+#pragma unroll
+                for (int r = 0; r < PI; ++r) {
+                    const bool better = lex_better(cs, cm, bs[r], bm[r]);
+                    const u64 ts = bs[r];
+                    const i32 tm = bm[r];
+                    bs[r] = better ? cs : ts;
+                    bm[r] = better ? cm : tm;
+                    cs = better ? ts : cs;
+                    cm = better ? tm : cm;
+                }
+            }
+            __syncthreads();
+        }
+        // Merge the per-thread lists: PI block-wide lexicographic maxima.
+        for (int r = 0; r < PI; ++r) {
+            u64 hs = bs[0];
+            i32 hm = bm[0];
+            wave_lexmax(hs, hm);
+            if (lane == 0) {
+                red_s[wv] = hs;
+                red_m[wv] = hm;
+            }
+            __syncthreads();
+            u64 ws = red_s[0];
+            i32 wm = red_m[0];
+            for (int w = 1; w < nwv; ++w) {
+                const u64 s2 = red_s[w];
+                const i32 m2 = red_m[w];
+                const bool t = lex_gt(s2, m2, ws, wm);
+                ws = t ? s2 : ws;
+                wm = t ? m2 : wm;
+            }
+            __syncthreads();
+            if ((int)(wm >= 0) & (int)(bm[0] == wm)) {
+#pragma unroll
+                for (int q = 0; q + 1 < PI; ++q) {
+                    bs[q] = bs[q + 1];
+                    bm[q] = bm[q + 1];
+                }
+                bs[PI - 1] = 0;
+                bm[PI - 1] = -1;
+            }
+            if (threadIdx.x == 0) {
+                cand[(i64)n * PI + r] = wm;
+                score[(i64)n * PI + r] = wm >= 0 ? ws : 0;
+            }
+        }
+    }
+}
+
+// ---- matching rounds (Sec. V-D) -------------------------------------------
+// Round r's target: the r-th candidate if both ends are still unmatched
+// (t = -2 marks nodes matched in an earlier round, -1 an undefined target).
+__global__ void k_round_targets(i32 N, int Pi, int r, const i32* __restrict__ cand, const u64* __restrict__ score,
+                                const i32* __restrict__ match, i32* t, u64* s) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        if (match[n] >= 0) {
+            t[n] = -2;
+            continue;
+        }
+        const i32 c = cand[n * Pi + r];
+        const i32 mc = match[c >= 0 ? c : 0];  // in bounds either way; used only when c >= 0
+        t[n] = ((int)(c >= 0) & (int)(mc < 0)) ? c : -1;
+        s[n] = score[n * Pi + r];
+    }
+}
+
+// Parent in the pseudo-forest: the target, except inside a two-cycle (the set
+// R of the paper) and for undefined targets, whose nodes are tree roots.
+__global__ void k_round_parent(i32 N, const i32* __restrict__ t, i32* parent, i32* jump, i32* depth, i64* accA,
+                               u64* accBV, i32* accBC) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        accA[n] = 0;
+        accBV[n] = 0;
+        accBC[n] = -1;
+        const i32 tn = t[n];
+        if (tn == -2) {
+            parent[n] = -2;
+            jump[n] = -1;
+            depth[n] = -1;
+            continue;
+        }
+        const i32 tp = t[tn >= 0 ? tn : 0];
+        const i32 p = ((int)(tn >= 0) & (int)(tp == (i32)n)) ? -1 : tn;
+        parent[n] = p;
+        jump[n] = p;
+        depth[n] = p >= 0 ? 1 : 0;
+    }
+}
+
+// Pointer jumping towards the roots: depth = number of hops to the root.
+__global__ void k_jump(i32 N, const i32* __restrict__ jin, const i32* __restrict__ din, i32* jout, i32* dout) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 j = jin[n];
+        if (j >= 0) {
+            dout[n] = din[n] + din[j];
+            jout[n] = jin[j];
+        } else {
+            dout[n] = din[n];
+            jout[n] = j;
+        }
+    }
+}
+
+__global__ void k_max_i32(i32 N, const i32* __restrict__ v, unsigned long long* out) {
+    i32 m = -1;
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        m = max(m, v[n]);
+    m = wave_max(m);
+    if (lane_id() == 0 && m >= 0) atomicMax(out, (unsigned long long)m);
+}
+
+// Bottom-up at depth d: ss0 from the children's sums (Eq. ss0), the return of
+// matching with the parent ss1 - ss0, and the push of both to the parent.
+__global__ void k_up_a(i32 N, int d, const i32* __restrict__ depth, const i32* __restrict__ parent,
+                       const u64* __restrict__ s, i64* accA, u64* accBV, const i32* __restrict__ accBC, i64* ss0,
+                       i64* ss10) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        if (depth[n] != d) continue;
+        const i32 bc = accBC[n];
+        const i64 bvr = dec_i64(accBV[n]);
+        const i64 take = ((int)(bc >= 0) & (int)(bvr > 0)) ? bvr : 0;
+        const i64 v0 = accA[n] + take;
+        ss0[n] = v0;
+        const i32 p = parent[n];
+        if (p >= 0) {
+            const i64 x = (i64)s[n] - take;
+            ss10[n] = x;
+            atomicAdd((unsigned long long*)&accA[p], (unsigned long long)v0);
+            atomicMax((unsigned long long*)&accBV[p], (unsigned long long)enc_i64(x));
+        }
+    }
+}
+
+// Second half of the lexicographic (ss1 - ss0, id) maximum over children.
+__global__ void k_up_b(i32 N, int d, const i32* __restrict__ depth, const i32* __restrict__ parent,
+                       const i64* __restrict__ ss10, const u64* __restrict__ accBV, i32* accBC) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        if (depth[n] != d) continue;
+        const i32 p = parent[n];
+        const u64 bvp = accBV[p >= 0 ? p : 0];
+        if ((int)(p >= 0) & (int)(enc_i64(ss10[n]) == bvp)) atomicMax(&accBC[p], (i32)n);
+    }
+}
+
+// Two-cycle roots (Eq. ss1_roots, Eq. match_root): the pair matches iff
+// ss1 > ss0(n) + ss0(target(n)).
+__global__ void k_pairs(i32 N, const i32* __restrict__ t, const u64* __restrict__ s, const i64* __restrict__ accA,
+                        const i64* __restrict__ ss0, i32* match) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 m = t[n];
+        const i32 tm = t[m >= 0 ? m : 0];
+        if (!((int)(m >= 0) & (int)(tm == (i32)n) & (int)((i32)n < m))) continue;
+        const i64 ss1 = (i64)s[n] + accA[n] + accA[m];
+        if (ss1 > ss0[n] + ss0[m]) {
+            match[n] = m;
+            match[m] = (i32)n;
+        }
+    }
+}
+
+// Top-down at depth d (Eq. match): a node its parent did not take picks its
+// best child when that child's return is positive.
+__global__ void k_down(i32 N, int d, const i32* __restrict__ depth, const u64* __restrict__ accBV,
+                       const i32* __restrict__ accBC, i32* match) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 dn = depth[n], mn = match[n];
+        if ((int)(dn != d) | (int)(mn >= 0)) continue;
+        const i32 bc = accBC[n];
+        const i64 bv = dec_i64(accBV[n]);
+        if ((int)(bc >= 0) & (int)(bv > 0)) {
+            match[n] = bc;
+            match[bc] = (i32)n;
+        }
+    }
+}
+
+// ---- isolated pairing (Sec. V-C) --------------------------------------------
+__global__ void k_iso_flags(i32 N, int Pi, const i32* __restrict__ cand, i32* flag) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        flag[n] = cand[n * Pi] < 0 ? 1 : 0;
+}
+
+__global__ void k_iso_keys(i32 N, const i32* __restrict__ flag, const i32* __restrict__ pos,
+                           const i32* __restrict__ nw, u64* keys, i32* vals) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        if (flag[n]) {
+            keys[pos[n]] = ((u64)(u32)nw[n] << 32) | (u64)(u32)n;
+            vals[pos[n]] = (i32)n;
+        }
+}
+
+// Nodes sorted by (size, id): the smallest left pairs with the largest that
+// fits both caps, with |in| + |in| standing in for the union.  Serial by
+// nature; one thread.
+__global__ void k_iso_pair(i32 cnt, const i32* __restrict__ order, const i32* __restrict__ nw,
+                           const i32* __restrict__ nin, i64 omega, i64 delta, i32* match) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    i32 i = 0, j = cnt - 1;
+    while (i < j) {
+        const i32 a = order[i], b = order[j];
+        const i64 wa = nw[a], wb = nw[b], ia = nin[a], ib = nin[b];
+        if ((int)(wa + wb <= omega) & (int)(ia + ib <= delta)) {
+            match[a] = b;
+            match[b] = a;
+            ++i;
+            --j;
+        } else {
+            --j;
+        }
+    }
+}
+
+// ---- cluster map (Sec. V-E) ------------------------------------------------
+__global__ void k_rep_flags(i32 N, const i32* __restrict__ match, i32* rep, unsigned long long* pairs) {
+    unsigned long long c = 0;
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 m = match[n];
+        rep[n] = ((int)(m < 0) | (int)(m > (i32)n)) ? 1 : 0;
+        c += (m > (i32)n) ? 1 : 0;
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(pairs, c);
+}
+
+// gamma(n) = rank of the cluster's smallest member; sizes add up.
+__global__ void k_gamma(i32 N, const i32* __restrict__ match, const i32* __restrict__ cid,
+                        const i32* __restrict__ nw, i32* gamma, i32* nw2) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 m = match[n];
+        const int is_rep = (int)(m < 0) | (int)(m > (i32)n);
+        const i32 r = is_rep ? (i32)n : m;
+        gamma[n] = cid[r];
+        const i32 wm = nw[m >= 0 ? m : (i32)n];
+        if (is_rep) nw2[cid[n]] = nw[n] + (m >= 0 ? wm : 0);
+    }
+}
+
+int bits_for(u64 v) {
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+template <typename BIN>
+void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, i32* cand,
+                    u64* score) {
+    const int grid = std::min<i64>(L.N, (i64)c->num_cu * 4);
+#define HGP_PROP(PIV)                                                                                              \
+    case PIV:                                                                                                      \
+        LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, 256, 0, L.N, L.inc_off(), L.inc_nin(), L.inc(),       \
+               L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib,     \
+               cand, score);                                                                                       \
+        break;
+    switch (Pi) {
+        HGP_PROP(1) HGP_PROP(2) HGP_PROP(3) HGP_PROP(4) HGP_PROP(5) HGP_PROP(6) HGP_PROP(7) HGP_PROP(8)
+        default: fail(HGP_E_INVALID, "pi must be in 1..8");
+    }
+#undef HGP_PROP
+}
+
+}  // namespace
+
+void coarsen_level(Ctx* c, int lv) {
+    const Level& L = c->levels[lv];
+    const i32 N = L.N;
+    const int Pi = c->opt.pi;
+    const int nb = grid_for(N, 256, c->num_cu * 8);
+    unsigned long long* stats = wsp<unsigned long long>(c, WS_STATS, 8);
+    HIPC(hipMemsetAsync(stats, 0, 8 * sizeof(u64), c->stream));
+    LAUNCH(c, KF_LEVEL_STATS, k_node_tsum, grid_for(N, 4, c->num_cu * 16), 256, 0, N, L.inc_off(), L.inc_nin(),
+           L.inc(), L.he_off(), c->hw(), stats);
+    if (L.E > 0)
+        LAUNCH(c, KF_LEVEL_STATS, k_edge_tsum, grid_for(L.E, 256, c->num_cu * 4), 256, 0, L.E, L.he_off(), c->hw(),
+               stats);
+    LAUNCH(c, KF_LEVEL_STATS, k_noise_cap, 1, 1, 0, stats);
+    i64 st[2];
+    read_back(c, stats, st, 2, 8);
+    const u64 max_tsum = (u64)st[0], max_nin = (u64)st[1];
+
+    Level& Lm = c->levels[lv];
+    Lm.b_cand = c->alloc(sizeof(i32) * (size_t)N * Pi);
+    Lm.b_score = c->alloc(sizeof(u64) * (size_t)N * Pi);
+    Lm.b_match = c->alloc(sizeof(i32) * (size_t)N);
+    i32* cand = (i32*)Lm.b_cand.p;
+    u64* score = (u64*)Lm.b_score.p;
+    i32* match = (i32*)Lm.b_match.p;
+
+    // Histogram bins pack (eta << ib) | inter; pick the narrowest that holds both.
+    const int ib = std::max(1, bits_for(max_nin));
+    if (ib < 32 && bits_for(max_tsum) <= 32 - ib)
+        launch_propose<u32>(c, L, Pi, stats, ib, cand, score);
+    else if (bits_for(max_tsum) <= 64 - ib)
+        launch_propose<unsigned long long>(c, L, Pi, stats, ib, cand, (u64*)score);
+    else
+        fail(HGP_E_UNSUPPORTED, "histogram values exceed 64 bits");
+
+    // Pi matching rounds.
+    i32* t = wsp<i32>(c, WS_T, N);
+    u64* s = wsp<u64>(c, WS_S, N);
+    i32* parent = wsp<i32>(c, WS_PARENT, N);
+    i32* j0 = wsp<i32>(c, WS_J0, N);
+    i32* j1 = wsp<i32>(c, WS_J1, N);
+    i32* d0 = wsp<i32>(c, WS_D0, N);
+    i32* d1 = wsp<i32>(c, WS_D1, N);
+    i64* accA = wsp<i64>(c, WS_ACC_A, N);
+    u64* accBV = wsp<u64>(c, WS_ACC_BV, N);
+    i32* accBC = wsp<i32>(c, WS_ACC_BC, N);
+    i64* ss0 = wsp<i64>(c, WS_SS0, N);
+    i64* ss10 = wsp<i64>(c, WS_SS10, N);
+    fill_i32(c, match, -1, N);
+    const int jump_iters = bits_for((u64)N) + 1;
+    for (int r = 0; r < Pi; ++r) {
+        LAUNCH(c, KF_MATCH, k_round_targets, nb, 256, 0, N, Pi, r, cand, score, match, t, s);
+        LAUNCH(c, KF_MATCH, k_round_parent, nb, 256, 0, N, t, parent, j0, d0, accA, accBV, accBC);
+        i32 *ja = j0, *jb = j1, *da = d0, *db = d1;
+        for (int it = 0; it < jump_iters; ++it) {
+            LAUNCH(c, KF_MATCH, k_jump, nb, 256, 0, N, ja, da, jb, db);
+            std::swap(ja, jb);
+            std::swap(da, db);
+        }
+        HIPC(hipMemsetAsync(stats + 5, 0, sizeof(u64), c->stream));
+        LAUNCH(c, KF_MATCH, k_max_i32, nb, 256, 0, N, da, stats + 5);
+        i64 maxd = 0;
+        read_back(c, stats + 5, &maxd, 1, 8);
+        const i32* depth = da;
+        for (int d = (int)maxd; d >= 0; --d) {
+            LAUNCH(c, KF_MATCH, k_up_a, nb, 256, 0, N, d, depth, parent, s, accA, accBV, accBC, ss0, ss10);
+            LAUNCH(c, KF_MATCH, k_up_b, nb, 256, 0, N, d, depth, parent, ss10, accBV, accBC);
+        }
+        LAUNCH(c, KF_MATCH, k_pairs, nb, 256, 0, N, t, s, accA, ss0, match);
+        for (int d = 0; d <= (int)maxd; ++d)
+            LAUNCH(c, KF_MATCH, k_down, nb, 256, 0, N, d, depth, accBV, accBC, match);
+    }
+
+    // Isolated nodes.
+    i32* flag = wsp<i32>(c, WS_ISO_FLAG, N);
+    i32* pos = wsp<i32>(c, WS_ISO_POS, (size_t)N + 1);
+    LAUNCH(c, KF_ISOLATED, k_iso_flags, nb, 256, 0, N, Pi, cand, flag);
+    scan_excl_i32(c, flag, pos, N);
+    i64 niso = 0;
+    read_back(c, pos + N, &niso, 1, 4);
+    if (niso >= 2) {
+        u64* keys = wsp<u64>(c, WS_ISO_KEYS, niso);
+        u64* keys2 = wsp<u64>(c, WS_ISO_KEYS2, niso);
+        i32* vals = wsp<i32>(c, WS_ISO_VALS, niso);
+        i32* vals2 = wsp<i32>(c, WS_ISO_VALS2, niso);
+        LAUNCH(c, KF_ISOLATED, k_iso_keys, nb, 256, 0, N, flag, pos, L.nw(), keys, vals);
+        sort_pairs_u64(c, keys, keys2, vals, vals2, niso, 64);
+        LAUNCH(c, KF_ISOLATED, k_iso_pair, 1, 64, 0, (i32)niso, vals2, L.nw(), L.inc_nin(), c->omega, c->delta,
+               match);
+    }
+
+    // Cluster map.
+    i32* rep = wsp<i32>(c, WS_REP, N);
+    i32* cid = wsp<i32>(c, WS_CID, (size_t)N + 1);
+    HIPC(hipMemsetAsync(stats + 6, 0, sizeof(u64), c->stream));
+    LAUNCH(c, KF_GAMMA, k_rep_flags, nb, 256, 0, N, match, rep, stats + 6);
+    scan_excl_i32(c, rep, cid, N);
+    i64 pairs = 0;
+    read_back(c, stats + 6, &pairs, 1, 8);
+    c->levels[lv].pairs = pairs;
+    if (pairs == 0) return;
+
+    Level nl;
+    nl.N = N - (i32)pairs;
+    c->levels[lv].b_gamma = c->alloc(sizeof(i32) * (size_t)N);
+    nl.b_nw = c->alloc(sizeof(i32) * (size_t)nl.N);
+    LAUNCH(c, KF_GAMMA, k_gamma, nb, 256, 0, N, match, cid, L.nw(), c->levels[lv].gamma(), nl.nw());
+    contract_edges(c, c->levels[lv], c->levels[lv].gamma(), nl);
+    build_incidence(c, nl);
+    c->levels.push_back(nl);
+}
+
+}  // namespace hgp

@@ -1,0 +1,290 @@
+// Hypergraph structure kernels: validation of the input (Sec. II-A), the
+// node -> h-edge incidence of the dual compressed layout (Sec. IV-B), coarse
+// h-edges through the cluster map with pin deduplication (Sec. V-E), and the
+// per-h-edge rows of pins(p,e) / pins_in(p,e) (Sec. II-B, Sec. VI-B).
+#include "dev_util.h"
+
+namespace hgp {
+
+namespace {
+
+enum { WS_KEYS = 10, WS_KEYS_OUT = 11, WS_VALS = 12, WS_CNT = 13, WS_EDGE_TMP = 14, WS_CARD = 15, WS_NSRC = 16 };
+
+// Error bits reported by validation.
+enum {
+    VE_OFFSETS = 1, VE_EMPTY = 2, VE_NSRC = 4, VE_RANGE = 8, VE_ORDER = 16, VE_OVERLAP = 32, VE_WEIGHT = 64,
+    VE_TOO_BIG = 128, VE_NODE_WEIGHT = 256
+};
+constexpr int kMaxCard = 4096;
+
+// One wave per h-edge.  out[0] |= error bits, out[1] += sum of h-edge
+// weights, out[3] = max |e|.
+__global__ __launch_bounds__(256) void k_validate_edges(i32 N, i32 E, const i64* __restrict__ he_off,
+                                                        const i32* __restrict__ he_nsrc,
+                                                        const i32* __restrict__ pins, const i32* __restrict__ hw,
+                                                        i64 P, unsigned long long* out) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    unsigned long long err = 0, wsum = 0, cmax = 0;
+    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+        const i64 a = he_off[e], b = he_off[e + 1];
+        if (a < 0 || b > P || b < a) { err |= VE_OFFSETS; continue; }
+        if (e == 0 && a != 0) err |= VE_OFFSETS;
+        if (e == E - 1 && b != P) err |= VE_OFFSETS;
+        const i64 card = b - a;
+        if (card == 0) { err |= VE_EMPTY; continue; }
+        if (card > kMaxCard) err |= VE_TOO_BIG;
+        cmax = cmax > (unsigned long long)card ? cmax : (unsigned long long)card;
+        const i32 w = hw ? hw[e] : 1;
+        if (w < 1) err |= VE_WEIGHT;
+        if (lane == 0) wsum += (unsigned long long)(w > 0 ? w : 0);
+        const i32 ns = he_nsrc[e];
+        if (ns < 0 || ns > card) { err |= VE_NSRC; continue; }
+        const i64 d0 = a + ns;
+        bool bad_range = false;
+        for (i64 j = a + lane; j < b; j += kWave) {
+            const i32 m = pins[j];
+            if (m < 0 || m >= N) { bad_range = true; continue; }
+            if (j != a && j != d0) {
+                const i32 prev = pins[j - 1];
+                if (prev >= m) err |= VE_ORDER;
+            }
+        }
+        if (bad_range) err |= VE_RANGE;
+        if (__any(bad_range)) continue;
+        // src ∩ dst via binary search of each source in the destination block.
+        for (i64 j = a + lane; j < d0; j += kWave) {
+            const i32 m = pins[j];
+            i64 lo = d0, hi = b;
+            while (lo < hi) {
+                const i64 mid = (lo + hi) >> 1;
+                if (pins[mid] < m) lo = mid + 1;
+                else hi = mid;
+            }
+            const i32 at = pins[lo < b ? lo : b - 1];  // the block is non-empty: j < d0 <= b - 1 here
+            if ((int)(lo < b) & (int)(at == m)) err |= VE_OVERLAP;
+        }
+    }
+    err = wave_or(err);
+    wsum = wave_sum(wsum);
+    cmax = wave_max(cmax);
+    if (lane == 0) {
+        if (err) atomicOr(&out[0], err);
+        atomicAdd(&out[1], wsum);
+        atomicMax(&out[3], cmax);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_validate_nodes(i32 N, const i32* __restrict__ nw, unsigned long long* out) {
+    unsigned long long err = 0, s = 0;
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 w = nw ? nw[n] : 1;
+        if (w < 1) err |= VE_NODE_WEIGHT;
+        else s += (unsigned long long)w;
+    }
+    s = wave_sum(s);
+    err = wave_or(err);
+    if (lane_id() == 0) {
+        if (err) atomicOr(&out[0], err);
+        atomicAdd(&out[2], s);
+    }
+}
+
+// Incidence keys: one wave per h-edge; key = 2*node + (pin is a source),
+// value = h-edge id.  A stable sort by key then lists, per node, inbound
+// h-edges first and each block ascending (Sec. IV-B).
+__global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__ he_off,
+                                                  const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+                                                  u32* keys, i32* vals, i32* cnt, i32* nin) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+        const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
+        for (i64 j = a + lane; j < b; j += kWave) {
+            const i32 n = pins[j];
+            const bool is_src = j < d0;
+            keys[j] = ((u32)n << 1) | (is_src ? 1u : 0u);
+            vals[j] = (i32)e;
+            atomicAdd(&cnt[n], 1);
+            if (!is_src) atomicAdd(&nin[n], 1);
+        }
+    }
+}
+
+// Coarse pins of one h-edge per block (Sec. V-E): map pins through gamma,
+// sort (id, is_source) in shared memory, keep each coarse id once; an id seen
+// among destinations is a destination, otherwise a source.  Written at the
+// old offset (|e'| <= |e|); card/nsrc receive the new counts.
+__global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __restrict__ he_off,
+                                                        const i32* __restrict__ he_nsrc,
+                                                        const i32* __restrict__ pins, const i32* __restrict__ gamma,
+                                                        i32* tmp, i32* card_out, i32* nsrc_out) {
+    extern __shared__ u32 keys[];
+    __shared__ i32 red[16];
+    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
+        const int npad = next_pow2(card);
+        for (int i = threadIdx.x; i < npad; i += blockDim.x)
+            keys[i] = i < card ? (((u32)gamma[pins[a + i]] << 1) | (i < ns ? 1u : 0u)) : 0xFFFFFFFFu;
+        __syncthreads();
+        block_bitonic_sort_u32(keys, npad);
+        // count sources first, then write sources and destinations.
+        i32 nsrc_new = 0;
+        for (int base = 0; base < card; base += blockDim.x) {
+            const int i = base + threadIdx.x;
+            const int ic = i < card ? i : 0;
+            const u32 kc = keys[ic], kp = keys[ic > 0 ? ic - 1 : 0];
+            const bool head = ((int)(i < card) & ((int)(i == 0) | (int)((kc >> 1) != (kp >> 1)))) != 0;
+            nsrc_new += block_sum((i32)(head & ((kc & 1u) != 0)), red);
+        }
+        i32 run_s = 0, run_d = 0;
+        for (int base = 0; base < card; base += blockDim.x) {
+            const int i = base + threadIdx.x;
+            const int ic = i < card ? i : 0;
+            const u32 kc = keys[ic], kp = keys[ic > 0 ? ic - 1 : 0];
+            const bool head = ((int)(i < card) & ((int)(i == 0) | (int)((kc >> 1) != (kp >> 1)))) != 0;
+            const bool fs = head & ((kc & 1u) != 0), fd = head & ((kc & 1u) == 0);
+            i32 ts, td;
+            const i32 xs = block_excl_scan((i32)fs, red, &ts);
+            const i32 xd = block_excl_scan((i32)fd, red, &td);
+            if (fs) tmp[a + run_s + xs] = (i32)(kc >> 1);
+            if (fd) tmp[a + nsrc_new + run_d + xd] = (i32)(kc >> 1);
+            run_s += ts;
+            run_d += td;
+        }
+        if (threadIdx.x == 0) {
+            card_out[e] = run_s + run_d;
+            nsrc_out[e] = run_s;
+        }
+        __syncthreads();
+    }
+}
+
+// Compacts per-h-edge segments written at old offsets into the new layout.
+__global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict__ old_off,
+                                                    const i64* __restrict__ new_off, const i32* __restrict__ tmp,
+                                                    i32* out) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+        const i64 a = old_off[e], o = new_off[e], n = new_off[e + 1] - o;
+        for (i64 j = lane; j < n; j += kWave) out[o + j] = tmp[a + j];
+    }
+}
+
+// pins(p,e) and pins_in(p,e) of one h-edge per block: sort (rho(pin), is_dst)
+// in shared memory and run-length count.  Rows are written at the h-edge's pin
+// offset, ascending p; len[e] = lambda(e).
+__global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
+                                             const i32* __restrict__ pins, const i32* __restrict__ rho,
+                                             i32* part, i32* cnt, i32* cnt_in, i32* len) {
+    extern __shared__ u32 sm[];
+    __shared__ i32 red[16];
+    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
+        const int npad = next_pow2(card);
+        u32* keys = sm;
+        i32* c_all = (i32*)(sm + npad);
+        i32* c_in = c_all + npad;
+        for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+            keys[i] = i < card ? (((u32)rho[pins[a + i]] << 1) | (i >= ns ? 1u : 0u)) : 0xFFFFFFFFu;
+            c_all[i] = 0;
+            c_in[i] = 0;
+        }
+        __syncthreads();
+        block_bitonic_sort_u32(keys, npad);
+        i32 rows = 0;
+        for (int base = 0; base < card; base += blockDim.x) {
+            const int i = base + threadIdx.x;
+            const int ic = i < card ? i : 0;
+            const u32 kc = keys[ic], kp = keys[ic > 0 ? ic - 1 : 0];
+            const bool head = ((int)(i < card) & ((int)(i == 0) | (int)((kc >> 1) != (kp >> 1)))) != 0;
+            i32 tot;
+            const i32 x = block_excl_scan((i32)head, red, &tot);
+            if (i < card) {
+                const i32 r = rows + x + (head ? 1 : 0) - 1;  // row of element i
+                if (head) part[a + r] = (i32)(kc >> 1);
+                atomicAdd(&c_all[r], 1);
+                if (kc & 1u) atomicAdd(&c_in[r], 1);
+            }
+            rows += tot;
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+            cnt[a + r] = c_all[r];
+            cnt_in[a + r] = c_in[r];
+        }
+        if (threadIdx.x == 0) len[e] = rows;
+        __syncthreads();
+    }
+}
+
+int bits_for(u64 v) {
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+}  // namespace
+
+void validate_graph(Ctx* c, i32 N, i32 E, const i64* he_off, const i32* he_nsrc, const i32* pins, const i32* hw,
+                    const i32* nw, i64 P, i64* d_out) {
+    HIPC(hipMemsetAsync(d_out, 0, 4 * sizeof(i64), c->stream));
+    if (E > 0)
+        LAUNCH(c, KF_VALIDATE, k_validate_edges, grid_for(E, 4, c->num_cu * 16), 256, 0, N, E, he_off, he_nsrc,
+               pins, hw, P, (unsigned long long*)d_out);
+    LAUNCH(c, KF_VALIDATE, k_validate_nodes, grid_for(N, 256, c->num_cu * 4), 256, 0, N, nw,
+           (unsigned long long*)d_out);
+}
+
+void build_incidence(Ctx* c, Level& L) {
+    const i64 P = L.P;
+    u32* keys = wsp<u32>(c, WS_KEYS, P);
+    u32* keys_out = wsp<u32>(c, WS_KEYS_OUT, P);
+    i32* vals = wsp<i32>(c, WS_VALS, P);
+    i32* cnt = wsp<i32>(c, WS_CNT, (size_t)L.N + 1);
+    L.b_inc_nin = c->alloc(sizeof(i32) * (size_t)L.N);
+    L.b_inc_off = c->alloc(sizeof(i64) * ((size_t)L.N + 1));
+    L.b_inc = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
+    HIPC(hipMemsetAsync(cnt, 0, sizeof(i32) * (size_t)L.N, c->stream));
+    HIPC(hipMemsetAsync(L.inc_nin(), 0, sizeof(i32) * (size_t)L.N, c->stream));
+    if (L.E > 0)
+        LAUNCH(c, KF_TRANSPOSE, k_pin_keys, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(),
+               L.pins(), keys, vals, cnt, L.inc_nin());
+    sort_pairs_u32(c, keys, keys_out, vals, L.inc(), P, bits_for(2ull * (u64)L.N));
+    scan_excl_i32_to_i64(c, cnt, L.inc_off(), L.N);
+}
+
+void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
+    const i32 E = L.E;
+    out.E = E;
+    out.b_he_off = c->alloc(sizeof(i64) * ((size_t)E + 1));
+    out.b_he_nsrc = c->alloc(sizeof(i32) * (size_t)(E > 0 ? E : 1));
+    i32* tmp = wsp<i32>(c, WS_EDGE_TMP, (size_t)L.P + 1);
+    i32* card = wsp<i32>(c, WS_CARD, (size_t)E + 1);
+    if (E > 0) {
+        // the input's largest h-edge bounds every level (|e'| <= |e|)
+        const int npad = next_pow2(c->max_card);
+        LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges, grid_for(E, 1, c->num_cu * 16), 256,
+               sizeof(u32) * npad, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc());
+    }
+    scan_excl_i32_to_i64(c, card, out.he_off(), E);
+    i64 P2 = 0;
+    read_back(c, out.he_off() + E, &P2, 1, 8);
+    out.P = P2;
+    out.b_pins = c->alloc(sizeof(i32) * (size_t)(P2 > 0 ? P2 : 1));
+    if (E > 0)
+        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(E, 4, c->num_cu * 16), 256, 0, E, L.he_off(),
+               (const i64*)out.he_off(), (const i32*)tmp, out.pins());
+}
+
+void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len) {
+    if (L.E == 0) return;
+    const int npad = next_pow2(c->max_card);
+    LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * 3 * npad, L.E, L.he_off(),
+           L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len);
+}
+
+}  // namespace hgp

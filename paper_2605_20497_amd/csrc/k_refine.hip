@@ -1,0 +1,890 @@
+// One refinement repetition (Sec. VI): pins(p,e) rows, in-isolation moves and
+// gains, the moves sequence of ranked chains, in-sequence gains, event-based
+// validity of every prefix, and the application of the best valid prefix.
+#include <algorithm>
+
+#include "dev_util.h"
+
+namespace hgp {
+
+namespace {
+
+enum {
+    WS_PHI_PART = 60, WS_PHI_CNT = 61, WS_PHI_CIN = 62, WS_PHI_LEN = 63, WS_PSIZE = 64, WS_PD = 65, WS_MDST = 66,
+    WS_MGAIN = 67, WS_MFLAG = 68, WS_MPOS = 69, WS_MKEY = 70, WS_MKEY2 = 71, WS_MVAL = 72, WS_SNODE = 73,
+    WS_SPS = 74, WS_SPD = 75, WS_SG = 76, WS_SNW = 77, WS_SNIN = 78, WS_SEGB = 79, WS_SEGE = 80, WS_PRED = 81,
+    WS_SUCC = 82, WS_PL = 83, WS_PLS = 84, WS_CL = 85, WS_PROP = 86, WS_PROPG = 87, WS_ACCG = 88, WS_ACCN = 89,
+    WS_FLAGS = 90, WS_J0 = 91, WS_J1 = 92, WS_MN0 = 93, WS_MN1 = 94, WS_P0 = 95, WS_P1 = 96, WS_R0 = 97,
+    WS_R1 = 98, WS_H0 = 99, WS_H1 = 100, WS_HEAD = 101, WS_CG = 102, WS_CLEN = 103, WS_SIDX = 104,
+    WS_HF = 105, WS_HPOS = 106, WS_HKEY = 107, WS_HKEY2 = 108, WS_HVAL = 109, WS_HVAL2 = 110, WS_LR = 111,
+    WS_LRS = 112, WS_CSTART = 113, WS_SEQN = 114, WS_SEQS = 115, WS_SEQD = 116, WS_POSN = 117, WS_GSEQ = 118,
+    WS_EVK = 119, WS_EVK2 = 120, WS_EVI = 121, WS_EVI2 = 122, WS_EVDS = 123, WS_EVDD = 124, WS_ES = 125,
+    WS_ED = 126, WS_SEX = 127, WS_DEX = 128, WS_SEGST = 129, WS_DVQ = 130, WS_CEX = 131, WS_VEX = 132,
+    WS_RSTATS = 133
+};
+
+// rstats: [0] active chain rounds flag, [1] links this round, [2] total links,
+// [3] kstar, [4] applied gain, [5] initial violations, [6] chains, [7] spare
+constexpr i64 kGradeScale = 10000000;  // 10^7 x the paper's grade with alpha=1e-6, beta=1e-7
+constexpr int kWindow = 256;
+constexpr int kChainRounds = 16;
+
+__global__ void k_part_sizes(i32 N, const i32* __restrict__ rho, const i32* __restrict__ nw, i64* psize) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        atomicAdd((unsigned long long*)&psize[rho[n]], (unsigned long long)nw[n]);
+}
+
+// D(p) = |{e : pins_in(p,e) > 0}| from the rows.
+__global__ __launch_bounds__(256) void k_part_inbound(i32 E, const i64* __restrict__ he_off,
+                                                      const i32* __restrict__ part, const i32* __restrict__ cin,
+                                                      const i32* __restrict__ len, i64* pD) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+        const i64 a = he_off[e];
+        const i32 L = len[e];
+        for (int r = lane; r < L; r += kWave)
+            if (cin[a + r] > 0) atomicAdd((unsigned long long*)&pD[part[a + r]], 1ull);
+    }
+}
+
+// Violated partitions before any move.
+__global__ void k_initial_violations(i32 nparts, const i64* __restrict__ psize, const i64* __restrict__ pD,
+                                     i64 omega, i64 delta, unsigned long long* out) {
+    unsigned long long c = 0;
+    for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nparts; p += (i64)gridDim.x * blockDim.x) {
+        const i64 sz = psize[p], dd = pD[p];
+        c += ((int)(sz > omega) | (int)(dd > delta)) ? 1 : 0;
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
+// In-isolation move of each node (Eq. refinement_move_selection), one block per
+// node: conn(n,p) = sum of omega(e) over e in I(n) with pins(p,e) > 0,
+// accumulated per partition in shared memory; gain(n,p) = saving(n) -
+// (W_I(n) - conn(n,p)).  Only partitions adjacent through some h-edge can have
+// a positive gain, so only those are visited.  Partition ids are split into
+// ranges of R bins, one pass each.
+__global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __restrict__ inc_off,
+                                               const i32* __restrict__ inc, const i64* __restrict__ he_off,
+                                               const i32* __restrict__ part, const i32* __restrict__ cnt,
+                                               const i32* __restrict__ len, const i32* __restrict__ hw,
+                                               const i32* __restrict__ nw, const i32* __restrict__ rho,
+                                               const i64* __restrict__ psize, i64 omega, int size_aware,
+                                               i32* move_dst, i64* move_gain) {
+    constexpr int R = 16384;
+    __shared__ u32 bins[R];
+    __shared__ i64 red[16];
+    __shared__ i64 red_g[16];
+    __shared__ i32 red_p[16];
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    const int npass = (int)((nparts + R - 1) / R);
+    for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
+    __syncthreads();
+    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+        const i32 ps = rho[n];
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        i64 saving = 0, wi = 0;
+        i64 bg = 0;
+        i32 bp = -1;
+        for (int pass = 0; pass < npass; ++pass) {
+            const i32 lo = pass * R;
+            const i32 hi = min(nparts, lo + R);
+            for (i64 k = a + wv; k < b; k += nwv) {
+                const i32 e = inc[k];
+                const i32 w = hw[e];
+                const i64 r0 = he_off[e];
+                const i32 L = len[e];
+                wi += ((int)(pass == 0) & (int)(lane == 0)) ? w : 0;
+                for (int q = lane; q < L; q += kWave) {
+                    const i32 p = part[r0 + q];
+                    const i32 cq = cnt[r0 + q];
+                    const int own = (int)(p == ps);
+                    saving += (own & (int)(pass == 0) & (int)(cq == 1)) ? w : 0;
+                    if ((own ^ 1) & (int)(p >= lo) & (int)(p < hi)) atomicAdd(&bins[p - lo], (u32)w);
+                }
+            }
+            if (pass == 0) {
+                saving = block_sum(saving, red);
+                wi = block_sum(wi, red);
+            } else {
+                __syncthreads();
+            }
+            const int used = hi - lo;
+            for (int sidx = threadIdx.x; sidx < used; sidx += blockDim.x) {
+                const u32 v = bins[sidx];
+                if (v == 0) continue;
+                bins[sidx] = 0;
+                const i32 p = lo + sidx;
+                const i64 g = saving - (wi - (i64)v);
+                const i64 szp = psize[p];
+                const int ok = (int)(g > 0) & ((size_aware ^ 1) | (int)((i64)nw[n] + szp <= omega));
+                const bool t = (ok & (int)lex_better(g, p, bg, bp)) != 0;
+                bg = t ? g : bg;
+                bp = t ? p : bp;
+            }
+            __syncthreads();
+        }
+        wave_lexmax_i64(bg, bp);
+        if (lane == 0) {
+            red_g[wv] = bg;
+            red_p[wv] = bp;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            i64 G = red_g[0];
+            i32 Pp = red_p[0];
+            for (int w = 1; w < nwv; ++w) {
+                const i64 g2 = red_g[w];
+                const i32 p2 = red_p[w];
+                const bool t = lex_better(g2, p2, G, Pp);
+                G = t ? g2 : G;
+                Pp = t ? p2 : Pp;
+            }
+            move_dst[n] = Pp;
+            move_gain[n] = Pp >= 0 ? G : 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_move_flags(i32 N, const i32* __restrict__ move_dst, i32* flag) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        flag[n] = move_dst[n] >= 0 ? 1 : 0;
+}
+
+// Sort key (p_s asc, gain desc) (Sec. VI-C); nodes enter in id order and the
+// sort is stable, so ties keep ascending node ids.  Gains are below 2^31.
+__global__ void k_move_keys(i32 N, const i32* __restrict__ flag, const i32* __restrict__ pos,
+                            const i32* __restrict__ rho, const i64* __restrict__ gain, u64* keys, i32* vals) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        if (flag[n]) {
+            keys[pos[n]] = ((u64)(u32)rho[n] << 32) | (u64)(0x7FFFFFFFll - gain[n]);
+            vals[pos[n]] = (i32)n;
+        }
+}
+
+__global__ void k_sorted_attrs(i32 M, const i32* __restrict__ snode, const i32* __restrict__ rho,
+                               const i32* __restrict__ move_dst, const i64* __restrict__ gain,
+                               const i32* __restrict__ nw, const i32* __restrict__ nin, i32* sps, i32* spd, i64* sg,
+                               i32* snw, i32* snin, i32* sidx) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 n = snode[i];
+        sps[i] = rho[n];
+        spd[i] = move_dst[n];
+        sg[i] = gain[n];
+        snw[i] = nw[n];
+        snin[i] = nin[n];
+        sidx[n] = (i32)i;
+    }
+}
+
+// Segment [seg_b[p], seg_e[p]) of moves leaving partition p.
+__global__ void k_segments(i32 M, const i32* __restrict__ sps, i32* seg_b, i32* seg_e) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 p = sps[i];
+        const i32 prev = sps[i > 0 ? i - 1 : 0], next = sps[i + 1 < M ? i + 1 : M - 1];
+        if ((int)(i == 0) | (int)(prev != p)) seg_b[p] = (i32)i;
+        if ((int)(i == M - 1) | (int)(next != p)) seg_e[p] = (i32)(i + 1);
+    }
+}
+
+// ---- chain rounds (Sec. VI-C) ----------------------------------------------
+__global__ void k_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pred, i32* pl) {
+    if (!rs[0]) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x)
+        pl[i] = pred[i] < 0 ? 1 : 0;
+}
+
+__global__ void k_compact_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pl,
+                                   const i32* __restrict__ pls, i32* cl, u64* accG, i32* accN) {
+    if (!rs[0]) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        if (pl[i]) cl[pls[i]] = (i32)i;
+        accG[i] = 0;
+        accN[i] = -1;
+    }
+}
+
+// Every move without a successor grades the first kWindow moves without a
+// predecessor that leave its destination, and proposes the lexicographic max
+// of (grade, node id).  One wave per move.
+__global__ __launch_bounds__(256) void k_chain_propose(i32 M, const unsigned long long* __restrict__ rs,
+                                                       const i32* __restrict__ succ, const i32* __restrict__ spd,
+                                                       const i32* __restrict__ seg_b, const i32* __restrict__ seg_e,
+                                                       const i32* __restrict__ pls, const i32* __restrict__ cl,
+                                                       const i64* __restrict__ sg, const i32* __restrict__ snw,
+                                                       const i32* __restrict__ snin, const i32* __restrict__ snode,
+                                                       i32* prop, i64* propG) {
+    if (!rs[0]) return;
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 i = (i64)blockIdx.x * wpb + wave_id(); i < M; i += (i64)gridDim.x * wpb) {
+        if (succ[i] >= 0) {
+            if (lane == 0) prop[i] = -1;
+            continue;
+        }
+        const i32 p = spd[i];
+        const i32 b = seg_b[p], e = seg_e[p];
+        i64 bG = 0;
+        i32 bn = -1, bj = -1;
+        if (b < e) {
+            const i32 w0 = pls[b];
+            const i32 w1 = min(pls[e], w0 + kWindow);
+            const i64 nw_i = snw[i], nin_i = snin[i];
+            for (i32 k = w0 + lane; k < w1; k += kWave) {
+                const i32 j = cl[k];
+                const i64 ds = nw_i - snw[j], dn = nin_i - snin[j];
+                const i64 G = sg[j] * kGradeScale - (10 * (ds < 0 ? -ds : ds) + (dn < 0 ? -dn : dn));
+                const i32 nj = snode[j];
+                const bool t = lex_better(G, nj, bG, bn);
+                bG = t ? G : bG;
+                bn = t ? nj : bn;
+                bj = t ? j : bj;
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const i64 G2 = __shfl_xor(bG, o, kWave);
+            const i32 n2 = __shfl_xor(bn, o, kWave);
+            const i32 j2 = __shfl_xor(bj, o, kWave);
+            const bool t = lex_better(G2, n2, bG, bn);
+            bG = t ? G2 : bG;
+            bn = t ? n2 : bn;
+            bj = t ? j2 : bj;
+        }
+        if (lane == 0) {
+            prop[i] = bj;
+            propG[i] = bG;
+        }
+    }
+}
+
+// A successor accepts the lexicographic max of (grade, proposer node id).
+__global__ void k_chain_accept_a(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ prop,
+                                 const i64* __restrict__ propG, u64* accG) {
+    if (!rs[0]) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 j = prop[i];
+        if (j >= 0) atomicMax((unsigned long long*)&accG[j], (unsigned long long)enc_i64(propG[i]));
+    }
+}
+
+__global__ void k_chain_accept_b(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ prop,
+                                 const i64* __restrict__ propG, const u64* __restrict__ accG,
+                                 const i32* __restrict__ snode, i32* accN) {
+    if (!rs[0]) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 j = prop[i];
+        const u64 aj = accG[j >= 0 ? j : 0];
+        if ((int)(j >= 0) & (int)(enc_i64(propG[i]) == aj)) atomicMax(&accN[j], snode[i]);
+    }
+}
+
+__global__ void k_chain_link(i32 M, unsigned long long* rs, const i32* __restrict__ prop,
+                             const i64* __restrict__ propG, const u64* __restrict__ accG,
+                             const i32* __restrict__ accN, const i32* __restrict__ snode, i32* pred, i32* succ) {
+    if (!rs[0]) return;
+    unsigned long long c = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 j = prop[i];
+        const i32 jj = j >= 0 ? j : 0;
+        const u64 aj = accG[jj];
+        const i32 nj = accN[jj];
+        if ((int)(j >= 0) & (int)(enc_i64(propG[i]) == aj) & (int)(nj == snode[i])) {
+            succ[i] = j;
+            pred[j] = (i32)i;
+            c += 1;
+        }
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(&rs[1], c);
+}
+
+__global__ void k_set_flag(unsigned long long* rs) { rs[0] = 1; }
+
+__global__ void k_round_end(unsigned long long* rs) {
+    if (!rs[0]) return;
+    if (rs[1] == 0) rs[0] = 0;
+    rs[2] += rs[1];
+    rs[1] = 0;
+}
+
+// ---- chain extraction and ranking (Sec. VI-C) -------------------------------
+__global__ void k_cyc_init(i32 M, const i32* __restrict__ succ, const i32* __restrict__ snode, i32* J, i32* MN) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        J[i] = succ[i];
+        MN[i] = snode[i];
+    }
+}
+
+// Pointer doubling along successors: after enough steps a node on a cycle
+// still points somewhere and holds the smallest node id of its cycle.
+__global__ void k_cyc_step(i32 M, const i32* __restrict__ J, const i32* __restrict__ MN, i32* J2, i32* MN2) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 j = J[i];
+        if (j >= 0) {
+            MN2[i] = min(MN[i], MN[j]);
+            J2[i] = J[j];
+        } else {
+            MN2[i] = MN[i];
+            J2[i] = j;
+        }
+    }
+}
+
+// Chain heads: path heads, and the smallest node of every cycle.
+__global__ void k_heads(i32 M, const i32* __restrict__ J, const i32* __restrict__ MN, const i32* __restrict__ pred,
+                        const i32* __restrict__ snode, i32* P, i32* R, i32* H, i32* head) {
+    // Branch-free on purpose: every operand is loaded unconditionally and the
+    // condition combined with bitwise operators, so the head test and the four
+    // selects below share one predicate (a short-circuit form of this test was
+    // lowered by the device compiler into code that dropped the select for H).
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 pr = pred[i], j = J[i], sn = snode[i], mn = MN[i];
+        const int h = (int)(pr < 0) | ((int)(j >= 0) & (int)(sn == mn));
+        head[i] = h;
+        P[i] = h ? -1 : pr;
+        R[i] = h ? 0 : 1;
+        H[i] = h ? (i32)i : pr;
+    }
+}
+
+// List ranking: distance to the chain head and the head itself.
+__global__ void k_rank_step(i32 M, const i32* __restrict__ P, const i32* __restrict__ R, const i32* __restrict__ H,
+                            i32* P2, i32* R2, i32* H2) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 p = P[i];
+        if (p >= 0) {
+            R2[i] = R[i] + R[p];
+            H2[i] = H[p];
+            P2[i] = P[p];
+        } else {
+            R2[i] = R[i];
+            H2[i] = H[i];
+            P2[i] = p;
+        }
+    }
+}
+
+__global__ void k_chain_accum(i32 M, const i32* __restrict__ H, const i64* __restrict__ sg, i64* cg, i32* clen) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        atomicAdd((unsigned long long*)&cg[H[i]], (unsigned long long)sg[i]);
+        atomicAdd(&clen[H[i]], 1);
+    }
+}
+
+// Heads listed in node-id order (so a stable sort by gain breaks ties by the
+// first node's id).
+__global__ void k_head_flags(i32 N, const i32* __restrict__ sidx, const i32* __restrict__ head, i32* hf) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 i = sidx[n];
+        const i32 hd = head[i >= 0 ? i : 0];
+        hf[n] = ((int)(i >= 0) & (int)(hd != 0)) ? 1 : 0;
+    }
+}
+
+__global__ void k_head_keys(i32 N, const i32* __restrict__ hf, const i32* __restrict__ hpos,
+                            const i32* __restrict__ sidx, const i64* __restrict__ cg, u64* keys, i32* vals) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        if (hf[n]) {
+            const i32 i = sidx[n];
+            keys[hpos[n]] = (u64)(0x3FFFFFFFFFFFFFFFll - cg[i]);
+            vals[hpos[n]] = i;
+        }
+}
+
+__global__ void k_ranked_len(i32 C, const i32* __restrict__ rh, const i32* __restrict__ clen, i32* lr) {
+    for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < C; c += (i64)gridDim.x * blockDim.x)
+        lr[c] = clen[rh[c]];
+}
+
+__global__ void k_chain_start(i32 C, const i32* __restrict__ rh, const i32* __restrict__ lrs, i32* cstart) {
+    for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < C; c += (i64)gridDim.x * blockDim.x)
+        cstart[rh[c]] = lrs[c];
+}
+
+__global__ void k_positions(i32 M, const i32* __restrict__ H, const i32* __restrict__ R,
+                            const i32* __restrict__ cstart, const i32* __restrict__ snode, const i32* __restrict__ sps,
+                            const i32* __restrict__ spd, i32* seqn, i32* seqs, i32* seqd, i32* posn) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
+        const i32 h = H[i];
+        const int hok = (int)(h >= 0) & (int)(h < M);
+        const i32 cs = cstart[hok ? h : 0];
+        const i32 q = hok ? cs + R[i] : -1;
+        if ((int)(q < 0) | (int)(q >= M)) continue;  // unreachable when the chain links are consistent
+        seqn[q] = snode[i];
+        seqs[q] = sps[i];
+        seqd[q] = spd[i];
+        posn[snode[i]] = q;
+    }
+}
+
+// Row lookup: pins(p,e) and pins_in(p,e), zero if p holds no pin of e.
+__device__ __forceinline__ void row_find(const i32* __restrict__ part, const i32* __restrict__ cnt,
+                                         const i32* __restrict__ cin, i64 r0, i32 L, i32 p, i32& c, i32& ci) {
+    i32 lo = 0, hi = L;
+    while (lo < hi) {
+        const i32 mid = (lo + hi) >> 1;
+        if (part[r0 + mid] < p) lo = mid + 1;
+        else hi = mid;
+    }
+    const i32 at = lo < L ? lo : L - 1;  // rows are never empty
+    const int hit = (int)(lo < L) & (int)(part[r0 + at] == p);
+    const i32 cv = cnt[r0 + at], civ = cin[r0 + at];
+    c = hit ? cv : 0;
+    ci = hit ? civ : 0;
+}
+
+// In-sequence gain and events of the mover at sequence position q (one block
+// per mover).  For each e in I(n) the pin counts of p_s and p_d just before
+// n's move are pins(p,e) adjusted by every earlier mover m in e; n's move then
+// changes Conn by omega(e)([c_s = 1] - [c_d = 0]) (the cases of Eq.
+// in_sequence_gain), and D(p_s) / D(p_d) by the pins_in transitions to zero /
+// from zero (Sec. VI-D).  Emits gseq[q] and the two events (p_s, q) and (p_d, q)
+// carrying size and D deltas.
+__global__ __launch_bounds__(256) void k_inseq(
+    i32 M, const i32* __restrict__ seqn, const i32* __restrict__ seqs, const i32* __restrict__ seqd,
+    const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
+    const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ hw, const i32* __restrict__ nw, const i32* __restrict__ part,
+    const i32* __restrict__ cnt, const i32* __restrict__ cin, const i32* __restrict__ len, i64* gseq, u32* evk,
+    i64* evds, i64* evdd) {
+    __shared__ i64 red[16];
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    for (i32 q = blockIdx.x; q < M; q += gridDim.x) {
+        const i32 n = seqn[q], ps = seqs[q], pd = seqd[q];
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        const i32 nin_n = inc_nin[n];
+        i64 g = 0, dDs = 0, dDd = 0;
+        for (i64 k = a + wv; k < b; k += nwv) {
+            const i32 e = inc[k];
+            const bool ein = (k - a) < nin_n;
+            const i64 e0 = he_off[e], e1 = he_off[e + 1], d0 = e0 + he_nsrc[e];
+            i32 cs = 0, cis = 0, cd = 0, cid = 0;
+            if (lane == 0) {
+                row_find(part, cnt, cin, e0, len[e], ps, cs, cis);
+                row_find(part, cnt, cin, e0, len[e], pd, cd, cid);
+            }
+            i32 xs = 0, xd = 0, xis = 0, xid = 0;
+            for (i64 j = e0 + lane; j < e1; j += kWave) {
+                const i32 m = pins[j];
+                if (posn[m] >= q) continue;
+                const i32 ms = rho[m], md = move_dst[m];
+                const i32 ds = (md == ps) - (ms == ps);
+                const i32 dd = (md == pd) - (ms == pd);
+                const i32 isd = (i32)(j >= d0);
+                xs += ds;
+                xd += dd;
+                xis += isd * ds;
+                xid += isd * dd;
+            }
+            xs = wave_sum(xs);
+            xd = wave_sum(xd);
+            xis = wave_sum(xis);
+            xid = wave_sum(xid);
+            if (lane == 0) {
+                cs += xs;
+                cd += xd;
+                cis += xis;
+                cid += xid;
+                const i64 w = hw[e];
+                g += w * ((cs == 1 ? 1 : 0) - (cd == 0 ? 1 : 0));
+                if (ein) {
+                    dDs -= (cis == 1) ? 1 : 0;
+                    dDd += (cid == 0) ? 1 : 0;
+                }
+            }
+        }
+        g = block_sum(g, red);
+        dDs = block_sum(dDs, red);
+        dDd = block_sum(dDd, red);
+        if (threadIdx.x == 0) {
+            gseq[q] = g;
+            evk[2 * (i64)q] = (u32)ps;
+            evds[2 * (i64)q] = -(i64)nw[n];
+            evdd[2 * (i64)q] = dDs;
+            evk[2 * (i64)q + 1] = (u32)pd;
+            evds[2 * (i64)q + 1] = (i64)nw[n];
+            evdd[2 * (i64)q + 1] = dDd;
+        }
+    }
+}
+
+__global__ void k_ev_gather(i64 n2, const i32* __restrict__ idx, const i64* __restrict__ ds,
+                            const i64* __restrict__ dd, i64* es, i64* ed) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (i64)gridDim.x * blockDim.x) {
+        es[i] = ds[idx[i]];
+        ed[i] = dd[idx[i]];
+    }
+}
+
+__global__ void k_ev_segstart(i64 n2, const u32* __restrict__ key, i32* segst) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (i64)gridDim.x * blockDim.x) {
+        const u32 k = key[i], kp = key[i > 0 ? i - 1 : 0];
+        if ((int)(i == 0) | (int)(k != kp)) segst[k] = (i32)i;
+    }
+}
+
+// Events sorted by (p, sequence position): running size and D of p after each
+// event give its validity; a change of validity adds +1 / -1 to the violation
+// count at that position (Sec. VI-D).
+__global__ void k_ev_transitions(i64 n2, const u32* __restrict__ key, const i32* __restrict__ idx,
+                                 const i32* __restrict__ segst, const i64* __restrict__ sex,
+                                 const i64* __restrict__ dex, const i64* __restrict__ psize,
+                                 const i64* __restrict__ pD, i64 omega, i64 delta, i32* dvq) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (i64)gridDim.x * blockDim.x) {
+        const u32 p = key[i];
+        const i64 s = segst[p];
+        const i64 sz0 = psize[p], d0 = pD[p];
+        const i64 s_s = sex[s], s_i = sex[i], s_i1 = sex[i + 1];
+        const i64 d_s = dex[s], d_i = dex[i], d_i1 = dex[i + 1];
+        const int after = (int)(sz0 + s_i1 - s_s > omega) | (int)(d0 + d_i1 - d_s > delta);
+        const int before = (int)(sz0 + s_i - s_s > omega) | (int)(d0 + d_i - d_s > delta);
+        const int d = after - before;
+        if (d) atomicAdd(&dvq[idx[i] >> 1], d);
+    }
+}
+
+// k* = smallest k maximising C_k over k = 0 or V_k = 0 (Sec. VI-D).
+__global__ __launch_bounds__(1024) void k_select(i32 M, const i64* __restrict__ cex, const i64* __restrict__ vex,
+                                                 unsigned long long* rs) {
+    __shared__ i64 sg[16];
+    __shared__ i32 sk[16];
+    const i64 v0 = (i64)rs[5];
+    i64 bg = 0;
+    i32 bk = 0;
+    for (i32 k = threadIdx.x + 1; k <= M; k += blockDim.x) {
+        const i64 vk = vex[k], c = cex[k];
+        const bool t = (int)(v0 + vk == 0) & (int)lex_gt(c, -k, bg, -bk);
+        bg = t ? c : bg;
+        bk = t ? k : bk;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const i64 g2 = __shfl_xor(bg, o, kWave);
+        const i32 k2 = __shfl_xor(bk, o, kWave);
+        const bool t = lex_gt(g2, -k2, bg, -bk);
+        bg = t ? g2 : bg;
+        bk = t ? k2 : bk;
+    }
+    if (lane_id() == 0) {
+        sg[wave_id()] = bg;
+        sk[wave_id()] = bk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        i64 G = 0;
+        i32 K = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+            const i64 g2 = sg[w];
+            const i32 k2 = sk[w];
+            const bool t = lex_gt(g2, -k2, G, -K);
+            G = t ? g2 : G;
+            K = t ? k2 : K;
+        }
+        rs[3] = (unsigned long long)K;
+        rs[4] = (unsigned long long)G;
+    }
+}
+
+__global__ void k_apply(const unsigned long long* __restrict__ rs, const i32* __restrict__ seqn,
+                        const i32* __restrict__ seqd, i32* rho) {
+    const i64 K = (i64)rs[3];
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < K; q += (i64)gridDim.x * blockDim.x)
+        rho[seqn[q]] = seqd[q];
+}
+
+__global__ void k_project(i32 N, const i32* __restrict__ rc, const i32* __restrict__ gamma, i32* rf) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        rf[n] = rc[gamma[n]];
+}
+
+// Eq. connectivity and Eq. cut-net from the row lengths lambda(e).
+__global__ void k_conn(i32 E, const i32* __restrict__ len, const i32* __restrict__ hw, unsigned long long* out) {
+    __shared__ i64 red[16];
+    i64 conn = 0, cut = 0;
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (i64)gridDim.x * blockDim.x) {
+        conn += (i64)hw[e] * (len[e] - 1);
+        cut += len[e] > 1 ? hw[e] : 0;
+    }
+    conn = block_sum(conn, red);
+    cut = block_sum(cut, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], (unsigned long long)conn);
+        atomicAdd(&out[1], (unsigned long long)cut);
+    }
+}
+
+__global__ void k_part_eval(i32 nparts, const i64* __restrict__ psize, const i64* __restrict__ pD, i64 omega,
+                            i64 delta, unsigned long long* out) {
+    unsigned long long ms = 0, md = 0, viol = 0, ne = 0;
+    for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nparts; p += (i64)gridDim.x * blockDim.x) {
+        ms = ms > (u64)psize[p] ? ms : (u64)psize[p];
+        md = md > (u64)pD[p] ? md : (u64)pD[p];
+        const i64 sz = psize[p], dd = pD[p];
+        viol += ((int)(sz > omega) | (int)(dd > delta)) ? 1 : 0;
+        ne += psize[p] > 0 ? 1 : 0;
+    }
+    ms = wave_max(ms);
+    md = wave_max(md);
+    viol = wave_sum(viol);
+    ne = wave_sum(ne);
+    if (lane_id() == 0) {
+        atomicMax(&out[2], ms);
+        atomicMax(&out[3], md);
+        atomicAdd(&out[4], viol);
+        atomicAdd(&out[5], ne);
+    }
+}
+
+int bits_for(u64 v) {
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+struct PhiBufs {
+    i32 *part, *cnt, *cin, *len;
+    i64 *psize, *pD;
+};
+
+PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
+    PhiBufs f;
+    f.part = wsp<i32>(c, WS_PHI_PART, (size_t)L.P + 1);
+    f.cnt = wsp<i32>(c, WS_PHI_CNT, (size_t)L.P + 1);
+    f.cin = wsp<i32>(c, WS_PHI_CIN, (size_t)L.P + 1);
+    f.len = wsp<i32>(c, WS_PHI_LEN, (size_t)L.E + 1);
+    f.psize = wsp<i64>(c, WS_PSIZE, nparts);
+    f.pD = wsp<i64>(c, WS_PD, nparts);
+    build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len);
+    HIPC(hipMemsetAsync(f.psize, 0, sizeof(i64) * nparts, c->stream));
+    HIPC(hipMemsetAsync(f.pD, 0, sizeof(i64) * nparts, c->stream));
+    LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), f.psize);
+    if (L.E > 0)
+        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), f.part,
+               f.cin, f.len, f.pD);
+    return f;
+}
+
+}  // namespace
+
+RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace) {
+    RepInfo info;
+    const i32 N = L.N;
+    const int nbN = grid_for(N, 256, c->num_cu * 8);
+    PhiBufs f = phi_and_parts(c, L, rho, nparts);
+    unsigned long long* rs = wsp<unsigned long long>(c, WS_RSTATS, 8);
+    HIPC(hipMemsetAsync(rs, 0, 8 * sizeof(u64), c->stream));
+    LAUNCH(c, KF_PART_STATS, k_initial_violations, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, f.psize,
+           f.pD, c->omega, c->delta, rs + 5);
+
+    // Moves (Sec. VI-B).
+    i32* mdst = wsp<i32>(c, WS_MDST, N);
+    i64* mgain = wsp<i64>(c, WS_MGAIN, N);
+    const int size_aware = rep >= theta / 2 ? 1 : 0;
+    LAUNCH(c, KF_GAINS, k_gains, std::min<i64>(N, (i64)c->num_cu * 4), 256, 0, N, nparts, L.inc_off(), L.inc(),
+           L.he_off(), f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, size_aware, mdst, mgain);
+    i32* mflag = wsp<i32>(c, WS_MFLAG, N);
+    i32* mpos = wsp<i32>(c, WS_MPOS, (size_t)N + 1);
+    LAUNCH(c, KF_MOVES, k_move_flags, nbN, 256, 0, N, mdst, mflag);
+    scan_excl_i32(c, mflag, mpos, N);
+    if (trace && trace->move_dst)
+        HIPC(hipMemcpyAsync(trace->move_dst, mdst, sizeof(i32) * N, hipMemcpyDeviceToHost, c->stream));
+    if (trace && trace->move_gain)
+        HIPC(hipMemcpyAsync(trace->move_gain, mgain, sizeof(i64) * N, hipMemcpyDeviceToHost, c->stream));
+    i64 M = 0;
+    read_back(c, mpos + N, &M, 1, 4);
+    info.moves = M;
+    if (M == 0) return info;
+    const int nbM = grid_for(M, 256, c->num_cu * 8);
+
+    // Moves sorted by (p_s, -gain, id) (Sec. VI-C).
+    u64* mkey = wsp<u64>(c, WS_MKEY, M);
+    u64* mkey2 = wsp<u64>(c, WS_MKEY2, M);
+    i32* mval = wsp<i32>(c, WS_MVAL, M);
+    i32* snode = wsp<i32>(c, WS_SNODE, M);
+    LAUNCH(c, KF_MOVES, k_move_keys, nbN, 256, 0, N, mflag, mpos, rho, mgain, mkey, mval);
+    sort_pairs_u64(c, mkey, mkey2, mval, snode, M, 32 + bits_for((u64)nparts));
+    i32* sps = wsp<i32>(c, WS_SPS, M);
+    i32* spd = wsp<i32>(c, WS_SPD, M);
+    i64* sg = wsp<i64>(c, WS_SG, M);
+    i32* snw = wsp<i32>(c, WS_SNW, M);
+    i32* snin = wsp<i32>(c, WS_SNIN, M);
+    i32* sidx = wsp<i32>(c, WS_SIDX, N);
+    fill_i32(c, sidx, -1, N);
+    LAUNCH(c, KF_MOVES, k_sorted_attrs, nbM, 256, 0, (i32)M, snode, rho, mdst, mgain, L.nw(), L.inc_nin(), sps, spd,
+           sg, snw, snin, sidx);
+    i32* segb = wsp<i32>(c, WS_SEGB, nparts);
+    i32* sege = wsp<i32>(c, WS_SEGE, nparts);
+    HIPC(hipMemsetAsync(segb, 0, sizeof(i32) * nparts, c->stream));
+    HIPC(hipMemsetAsync(sege, 0, sizeof(i32) * nparts, c->stream));
+    LAUNCH(c, KF_MOVES, k_segments, nbM, 256, 0, (i32)M, sps, segb, sege);
+
+    // Chain rounds.
+    i32* pred = wsp<i32>(c, WS_PRED, M);
+    i32* succ = wsp<i32>(c, WS_SUCC, M);
+    i32* pl = wsp<i32>(c, WS_PL, M);
+    i32* pls = wsp<i32>(c, WS_PLS, M + 1);
+    i32* cl = wsp<i32>(c, WS_CL, M);
+    i32* prop = wsp<i32>(c, WS_PROP, M);
+    i64* propG = wsp<i64>(c, WS_PROPG, M);
+    u64* accG = wsp<u64>(c, WS_ACCG, M);
+    i32* accN = wsp<i32>(c, WS_ACCN, M);
+    fill_i32(c, pred, -1, M);
+    fill_i32(c, succ, -1, M);
+    LAUNCH(c, KF_CHAINS, k_set_flag, 1, 1, 0, rs);
+    const int wblocks = grid_for(M, 4, c->num_cu * 16);
+    for (int round = 0; round < kChainRounds; ++round) {
+        LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
+        scan_excl_i32(c, pl, pls, M);
+        LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
+        LAUNCH(c, KF_CHAINS, k_chain_propose, wblocks, 256, 0, (i32)M, rs, succ, spd, segb, sege, pls, cl, sg, snw,
+               snin, snode, prop, propG);
+        LAUNCH(c, KF_CHAINS, k_chain_accept_a, nbM, 256, 0, (i32)M, rs, prop, propG, accG);
+        LAUNCH(c, KF_CHAINS, k_chain_accept_b, nbM, 256, 0, (i32)M, rs, prop, propG, accG, snode, accN);
+        LAUNCH(c, KF_CHAINS, k_chain_link, nbM, 256, 0, (i32)M, rs, prop, propG, accG, accN, snode, pred, succ);
+        LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);
+    }
+
+    // Chains: cycles, heads, ranks.
+    const int K = bits_for((u64)M) + 1;
+    i32 *J0 = wsp<i32>(c, WS_J0, M), *J1 = wsp<i32>(c, WS_J1, M);
+    i32 *MN0 = wsp<i32>(c, WS_MN0, M), *MN1 = wsp<i32>(c, WS_MN1, M);
+    LAUNCH(c, KF_RANK, k_cyc_init, nbM, 256, 0, (i32)M, succ, snode, J0, MN0);
+    for (int it = 0; it < K; ++it) {
+        LAUNCH(c, KF_RANK, k_cyc_step, nbM, 256, 0, (i32)M, J0, MN0, J1, MN1);
+        std::swap(J0, J1);
+        std::swap(MN0, MN1);
+    }
+    i32 *P0 = wsp<i32>(c, WS_P0, M), *P1 = wsp<i32>(c, WS_P1, M);
+    i32 *R0 = wsp<i32>(c, WS_R0, M), *R1 = wsp<i32>(c, WS_R1, M);
+    i32 *H0 = wsp<i32>(c, WS_H0, M), *H1 = wsp<i32>(c, WS_H1, M);
+    i32* head = wsp<i32>(c, WS_HEAD, M);
+    LAUNCH(c, KF_RANK, k_heads, nbM, 256, 0, (i32)M, J0, MN0, pred, snode, P0, R0, H0, head);
+    for (int it = 0; it < K; ++it) {
+        LAUNCH(c, KF_RANK, k_rank_step, nbM, 256, 0, (i32)M, P0, R0, H0, P1, R1, H1);
+        std::swap(P0, P1);
+        std::swap(R0, R1);
+        std::swap(H0, H1);
+    }
+    i64* cg = wsp<i64>(c, WS_CG, M);
+    i32* clen = wsp<i32>(c, WS_CLEN, M);
+    HIPC(hipMemsetAsync(cg, 0, sizeof(i64) * M, c->stream));
+    HIPC(hipMemsetAsync(clen, 0, sizeof(i32) * M, c->stream));
+    LAUNCH(c, KF_RANK, k_chain_accum, nbM, 256, 0, (i32)M, H0, sg, cg, clen);
+    i32* hf = wsp<i32>(c, WS_HF, N);
+    i32* hpos = wsp<i32>(c, WS_HPOS, (size_t)N + 1);
+    LAUNCH(c, KF_RANK, k_head_flags, nbN, 256, 0, N, sidx, head, hf);
+    scan_excl_i32(c, hf, hpos, N);
+    i64 C = 0;
+    read_back(c, hpos + N, &C, 1, 4);
+    u64* hkey = wsp<u64>(c, WS_HKEY, C);
+    u64* hkey2 = wsp<u64>(c, WS_HKEY2, C);
+    i32* hval = wsp<i32>(c, WS_HVAL, C);
+    i32* rh = wsp<i32>(c, WS_HVAL2, C);
+    LAUNCH(c, KF_RANK, k_head_keys, nbN, 256, 0, N, hf, hpos, sidx, cg, hkey, hval);
+    sort_pairs_u64(c, hkey, hkey2, hval, rh, C, 62);
+    i32* lr = wsp<i32>(c, WS_LR, C);
+    i32* lrs = wsp<i32>(c, WS_LRS, C + 1);
+    i32* cstart = wsp<i32>(c, WS_CSTART, M);
+    const int nbC = grid_for(C, 256, c->num_cu * 8);
+    LAUNCH(c, KF_RANK, k_ranked_len, nbC, 256, 0, (i32)C, rh, clen, lr);
+    scan_excl_i32(c, lr, lrs, C);
+    LAUNCH(c, KF_RANK, k_chain_start, nbC, 256, 0, (i32)C, rh, lrs, cstart);
+    i32* seqn = wsp<i32>(c, WS_SEQN, M);
+    i32* seqs = wsp<i32>(c, WS_SEQS, M);
+    i32* seqd = wsp<i32>(c, WS_SEQD, M);
+    i32* posn = wsp<i32>(c, WS_POSN, N);
+    fill_i32(c, posn, 0x7FFFFFFF, N);
+    LAUNCH(c, KF_RANK, k_positions, nbM, 256, 0, (i32)M, H0, R0, cstart, snode, sps, spd, seqn, seqs, seqd, posn);
+
+    // In-sequence gains and events.
+    i64* gseq = wsp<i64>(c, WS_GSEQ, M);
+    const i64 M2 = 2 * M;
+    u32* evk = wsp<u32>(c, WS_EVK, M2);
+    u32* evk2 = wsp<u32>(c, WS_EVK2, M2);
+    i32* evi = wsp<i32>(c, WS_EVI, M2);
+    i32* evi2 = wsp<i32>(c, WS_EVI2, M2);
+    i64* evds = wsp<i64>(c, WS_EVDS, M2);
+    i64* evdd = wsp<i64>(c, WS_EVDD, M2);
+    LAUNCH(c, KF_INSEQ, k_inseq, std::min<i64>(M, (i64)c->num_cu * 8), 256, 0, (i32)M, seqn, seqs, seqd, posn, rho,
+           mdst, L.inc_off(), L.inc_nin(), L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), f.part,
+           f.cnt, f.cin, f.len, gseq, evk, evds, evdd);
+    iota_i32(c, evi, M2);
+    sort_pairs_u32(c, evk, evk2, evi, evi2, M2, bits_for((u64)nparts));
+    i64* es = wsp<i64>(c, WS_ES, M2);
+    i64* ed = wsp<i64>(c, WS_ED, M2);
+    const int nbE = grid_for(M2, 256, c->num_cu * 8);
+    LAUNCH(c, KF_EVENTS, k_ev_gather, nbE, 256, 0, M2, evi2, evds, evdd, es, ed);
+    i64* sex = wsp<i64>(c, WS_SEX, M2 + 1);
+    i64* dex = wsp<i64>(c, WS_DEX, M2 + 1);
+    scan_excl_i64(c, es, sex, M2);
+    scan_excl_i64(c, ed, dex, M2);
+    i32* segst = wsp<i32>(c, WS_SEGST, nparts);
+    LAUNCH(c, KF_EVENTS, k_ev_segstart, nbE, 256, 0, M2, evk2, segst);
+    i32* dvq = wsp<i32>(c, WS_DVQ, M);
+    HIPC(hipMemsetAsync(dvq, 0, sizeof(i32) * M, c->stream));
+    LAUNCH(c, KF_EVENTS, k_ev_transitions, nbE, 256, 0, M2, evk2, evi2, segst, sex, dex, f.psize, f.pD, c->omega,
+           c->delta, dvq);
+    i64* cex = wsp<i64>(c, WS_CEX, M + 1);
+    i64* vex = wsp<i64>(c, WS_VEX, M + 1);
+    scan_excl_i64(c, gseq, cex, M);
+    scan_excl_i32_to_i64(c, dvq, vex, M);
+    LAUNCH(c, KF_SELECT, k_select, 1, 1024, 0, (i32)M, cex, vex, rs);
+    LAUNCH(c, KF_APPLY, k_apply, nbM, 256, 0, rs, seqn, seqd, rho);
+    i64 out[6];
+    read_back(c, rs, out, 6, 8);
+    info.links = out[2];
+    info.kstar = out[3];
+    info.gain = out[4];
+    if (trace) {
+        auto copy = [&](void* host, const void* dev, size_t bytes) {
+            if (host && bytes) HIPC(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+        };
+        copy(trace->seq, seqn, sizeof(i32) * M);
+        copy(trace->seq_dst, seqd, sizeof(i32) * M);
+        copy(trace->gseq, gseq, sizeof(i64) * M);
+        copy(trace->prefix_gain, cex, sizeof(i64) * (M + 1));
+        copy(trace->prefix_viol, vex, sizeof(i64) * (M + 1));
+        HIPC(hipStreamSynchronize(c->stream));
+        if (trace->prefix_viol)
+            for (i64 k = 0; k <= M; ++k) trace->prefix_viol[k] += out[5];  // V_k = V_0 + changes
+    }
+    return info;
+}
+
+void project_rho(Ctx* c, const i32* rho_coarse, const i32* gamma, i32* rho_fine, i32 N) {
+    LAUNCH(c, KF_PROJECT, k_project, grid_for(N, 256, c->num_cu * 8), 256, 0, N, rho_coarse, gamma, rho_fine);
+}
+
+void evaluate_dev(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out) {
+    PhiBufs f = phi_and_parts(c, L, rho, nparts);
+    unsigned long long* rs = wsp<unsigned long long>(c, WS_RSTATS, 8);
+    HIPC(hipMemsetAsync(rs, 0, 8 * sizeof(u64), c->stream));
+    if (L.E > 0)
+        LAUNCH(c, KF_EVAL, k_conn, grid_for(L.E, 256, c->num_cu * 4), 256, 0, L.E, f.len, c->hw(), rs);
+    LAUNCH(c, KF_EVAL, k_part_eval, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, f.psize, f.pD, c->omega,
+           c->delta, rs);
+    i64 v[6];
+    read_back(c, rs, v, 6, 8);
+    out->conn = v[0];
+    out->cutnet = v[1];
+    out->max_size = v[2];
+    out->max_inbound = v[3];
+    out->violations = v[4];
+    out->n_parts = v[5];
+}
+
+// Phi rows of level-0 for export: copies of the last built rows.
+void phi_export(Ctx* c, const Level& L, const i32* rho, i32 nparts, i32** part, i32** cnt, i32** cin, i32** len) {
+    PhiBufs f = phi_and_parts(c, L, rho, nparts);
+    *part = f.part;
+    *cnt = f.cnt;
+    *cin = f.cin;
+    *len = f.len;
+}
+
+}  // namespace hgp

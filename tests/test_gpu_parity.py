@@ -1,0 +1,198 @@
+"""Parity of the HIP path with the oracle, element by element, on seeded
+inputs: every level's proposal (candidates, scores, matching), cluster map
+and coarse hypergraph, the final partition, connectivity and the pins(p,e)
+rows.  Everything is integer, so the bar is bit-exact equality."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_20497_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(Pi=4, theta=16, seed=0, profile=False):
+    from paper_2605_20497_amd import Partitioner
+    return Partitioner(pi=Pi, theta=theta, seed=seed, profile=profile)
+
+
+def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label=""):
+    print("case", label, "N", hg.n_nodes, "E", hg.n_hedges, "P", hg.n_pins, "omega", omega, "delta", delta,
+          "k", k, flush=True)
+    og = oracle.Graph(hg)
+    res = og.partition(omega, delta, k=k, Pi=Pi, theta=theta, seed=seed)
+    g = _gpu(Pi, theta, seed)
+    g.load(hg)
+    g.hgp_set_limits(omega, delta, k)
+    nl = g.hgp_coarsen()
+    g.hgp_refine()
+    assert nl == res.nlevels, (nl, res.nlevels)
+    levels = g.hgp_get_levels()
+    for lv in range(nl):
+        o = res.levels[lv]
+        assert (levels[lv, 0], levels[lv, 1], levels[lv, 2]) == (o["N"], o["E"], o["P"]), lv
+        he_off, nsrc, pins, nw = g.hgp_get_level_graph(lv)
+        ooff, onsrc, opins, ohw, onw = res.graph(lv).csr()
+        assert np.array_equal(he_off, ooff) and np.array_equal(nsrc, onsrc), lv
+        assert np.array_equal(pins, opins) and np.array_equal(nw, onw), lv
+    for lv in range(res.ncoarsened):
+        cand, score, match = g.hgp_get_proposal(lv)
+        ocand, oscore, omatch = res.proposal(lv)
+        assert np.array_equal(cand, ocand), ("cand", lv)
+        assert np.array_equal(score, oscore), ("score", lv)
+        assert np.array_equal(match, omatch), ("match", lv)
+    for lv in range(nl - 1):
+        assert np.array_equal(g.hgp_get_cluster_map(lv), res.gamma(lv)), ("gamma", lv)
+    rho, nparts = g.hgp_get_partition()
+    assert nparts == res.nparts
+    assert np.array_equal(rho, res.rho(0))
+    ev = g.hgp_evaluate()
+    oev = og.evaluate(rho, nparts, omega, delta)
+    for key in ("conn", "cutnet", "max_size", "max_inbound", "violations"):
+        assert ev[key] == oev[key], key
+    assert ev["n_parts"] == oev["nonempty"]
+    assert ev["violations"] == 0
+    off, part, cnt, cin = g.hgp_get_phi()
+    ooff, opart, ocnt, ocin = og.phi(rho)
+    assert np.array_equal(off, ooff) and np.array_equal(part, opart)
+    assert np.array_equal(cnt, ocnt) and np.array_equal(cin, ocin)
+    g.close()
+    return res
+
+
+SMALL_CASES = [
+    # (n, e, max_card, seed, max_src, max_hw, max_nw, omega, delta)
+    (60, 50, 6, 1, 1, 1, 1, 8, 40),
+    (120, 100, 9, 2, 3, 4, 3, 12, 60),
+    (200, 260, 12, 3, 1, 2, 1, 16, 90),
+    (300, 200, 30, 4, 2, 1, 2, 40, 300),
+    (150, 400, 5, 5, 0, 3, 1, 10, 1000),
+    (500, 450, 20, 6, 1, 1, 4, 64, 200),
+]
+
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=lambda c: "n%d-e%d-s%d" % (c[0], c[1], c[3]))
+def test_small_random_full_pipeline(case):
+    n, e, card, seed, msrc, mhw, mnw, omega, delta = case
+    hg = W.random_small(n, e, card, seed, max_src=msrc, max_hw=mhw, max_nw=mnw)
+    _compare_runs(hg, omega, delta, label="small-%d" % seed)
+
+
+def test_snn_shaped_small():
+    hg = W.random_snn(1024, 15, 3)
+    _compare_runs(hg, 64, 256, label="snn-1k")
+
+
+def test_layered_small():
+    hg = W.layered_snn(4, 512, 31, 128, 0.8, seed=1)
+    _compare_runs(hg, 64, 512, label="layered-2k")
+
+
+def test_pi_and_theta_variants():
+    hg = W.random_snn(700, 11, 9)
+    _compare_runs(hg, 48, 200, Pi=1, theta=4, label="pi1")
+    _compare_runs(hg, 48, 200, Pi=8, theta=6, seed=5, label="pi8")
+
+
+def test_config1_full():
+    hg = W.config1()
+    _compare_runs(hg, hg.omega, hg.delta, label="rand-4k-e32")
+
+
+def test_edge_cases():
+    # no h-edges at all: every node isolated, pairing by size only
+    nw = np.array([3, 1, 6, 2, 5, 4, 1, 7, 2, 2], np.int32)
+    hg = W.Hypergraph(10, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                      np.zeros(0, np.int32), nw)
+    _compare_runs(hg, 8, 5, label="no-edges")
+    # single node
+    hg = W.Hypergraph(1, np.array([0, 1], np.int64), np.array([1], np.int32), np.array([0], np.int32),
+                      np.ones(1, np.int32), np.ones(1, np.int32))
+    _compare_runs(hg, 1, 0, label="one-node")
+    # single-pin h-edges, zero-source h-edges, caps so loose that one part remains
+    hg = W.random_small(80, 90, 4, 17, max_src=0, max_hw=5)
+    _compare_runs(hg, 80, 90, label="one-part")
+    hg = W.random_small(64, 64, 1, 18, max_src=1)
+    _compare_runs(hg, 4, 64, label="singletons")
+
+
+def test_kway_small_netlist():
+    hg = W.netlist(6000, 6600, 2, 80, 2.827, 256, 0.9, 8, seed=2, k=8, delta=1 << 15)
+    _compare_runs(hg, hg.omega, hg.delta, k=8, label="netlist-6k-k8")
+
+
+@pytest.mark.parametrize("rep", [0, 11])
+def test_refine_rep_step(rep):
+    hg = W.random_small(400, 380, 10, 33, max_src=2, max_hw=3, max_nw=2)
+    og = oracle.Graph(hg)
+    rng = np.random.default_rng(rep)
+    P = 9
+    rho0 = rng.integers(0, P, size=400).astype(np.int32)
+    ev = og.evaluate(rho0, P)
+    omega, delta = int(ev["max_size"]) + 2, int(ev["max_inbound"]) + 1
+    g = _gpu()
+    g.load(hg)
+    g.hgp_set_limits(omega, delta, 0)
+    rho = rho0
+    for it in range(3):
+        orho, od = og.refine_rep(rho, P, rep, 16, omega, delta)
+        odst, ogain = og.moves(rho, P, rep, 16, omega)
+        grho, gd = g.hgp_refine_rep(rho, P, rep)
+        assert np.array_equal(gd["move_dst"], odst) and np.array_equal(gd["move_gain"], ogain)
+        assert gd["moves"] == od["M"] and gd["kstar"] == od["kstar"] and gd["gain"] == od["applied_gain"]
+        assert gd["links"] == od["links"]
+        for key in ("seq", "seq_pd", "gseq", "C", "V"):
+            assert np.array_equal(gd[key], od[key]), key
+        assert np.array_equal(grho, orho)
+        rho = orho
+
+
+def test_evaluate_arbitrary_rho():
+    hg = W.random_small(250, 300, 12, 44, max_src=2, max_hw=6, max_nw=3)
+    og = oracle.Graph(hg)
+    g = _gpu()
+    g.load(hg)
+    g.hgp_set_limits(30, 40, 0)
+    rng = np.random.default_rng(0)
+    for P in (1, 5, 250):
+        rho = rng.integers(0, P, size=250).astype(np.int32)
+        ev = g.hgp_evaluate(rho, P)
+        oev = og.evaluate(rho, P, 30, 40)
+        for key in ("conn", "cutnet", "max_size", "max_inbound", "violations"):
+            assert ev[key] == oev[key]
+
+
+def test_deterministic_across_runs():
+    hg = W.random_snn(2048, 23, 4)
+    outs = []
+    for _ in range(2):
+        g = _gpu()
+        outs.append(g.partition(hg, 96, 400)[0])
+        g.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_error_paths():
+    from paper_2605_20497_amd import HgpError, HGP_E_INVALID, HGP_E_INFEASIBLE, HGP_E_STATE
+    g = _gpu()
+    with pytest.raises(HgpError) as ei:  # a pin both source and destination
+        g.hgp_load_csr(4, np.array([0, 3]), np.array([1], np.int32), np.array([1, 1, 2], np.int32))
+    assert ei.value.status == HGP_E_INVALID
+    with pytest.raises(HgpError) as ei:  # unsorted destinations
+        g.hgp_load_csr(4, np.array([0, 3]), np.array([1], np.int32), np.array([0, 3, 2], np.int32))
+    assert ei.value.status == HGP_E_INVALID
+    with pytest.raises(HgpError) as ei:  # pin out of range
+        g.hgp_load_csr(4, np.array([0, 2]), np.array([1], np.int32), np.array([0, 4], np.int32))
+    assert ei.value.status == HGP_E_INVALID
+    with pytest.raises(HgpError) as ei:
+        g.hgp_coarsen()
+    assert ei.value.status == HGP_E_STATE
+    hg = W.random_small(30, 20, 5, 1, max_nw=5)
+    g.load(hg)
+    with pytest.raises(HgpError) as ei:  # a node heavier than omega
+        g.hgp_set_limits(2, 100, 0)
+    assert ei.value.status == HGP_E_INFEASIBLE
+    g.hgp_set_limits(10, 100, 0)  # the context stays usable
+    g.hgp_coarsen()
+    g.hgp_refine()
+    g.close()
