@@ -1,0 +1,57 @@
+"""Full-size parity: the HIP path on the configurations' full sizes against
+digests the oracle wrote (tests/golden/<workload>.json, produced by
+tests/golden/make_oracle_golden.py, which calls only the oracle).  Compares
+the hierarchy sizes, every level's candidates, scores, matching and cluster
+map, the final partition and its connectivity, bit for bit."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2605_20497_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle digests for %s" % name)
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name", ["rand-4k-e32", "rand-64k-e192"])
+def test_full_size_against_oracle_digests(name):
+    from paper_2605_20497_amd import Partitioner
+    gold = _golden(name)
+    hg = W.CONFIGS[name]()
+    print("case", name, "N", hg.n_nodes, "P", hg.n_pins, flush=True)
+    g = Partitioner(pi=gold["pi"], theta=gold["theta"], seed=gold["seed"])
+    g.load(hg)
+    g.hgp_set_limits(gold["omega"], gold["delta"], gold["k"])
+    nl = g.hgp_coarsen()
+    g.hgp_refine()
+    assert nl == gold["nlevels"]
+    levels = g.hgp_get_levels()
+    for lv, L in enumerate(gold["levels"]):
+        assert (levels[lv, 0], levels[lv, 1], levels[lv, 2]) == (L["N"], L["E"], L["P"]), lv
+    for lv, d in enumerate(gold["proposal"]):
+        cand, score, match = g.hgp_get_proposal(lv)
+        assert _digest(cand) == d["cand"], ("cand", lv)
+        assert _digest(score) == d["score"], ("score", lv)
+        assert _digest(match) == d["match"], ("match", lv)
+    for lv, d in enumerate(gold["gamma"]):
+        assert _digest(g.hgp_get_cluster_map(lv)) == d, ("gamma", lv)
+    rho, nparts = g.hgp_get_partition()
+    assert nparts == gold["nparts"]
+    assert _digest(rho) == gold["rho_sha256"]
+    ev = g.hgp_evaluate()
+    assert ev["conn"] == gold["conn"] and ev["violations"] == 0
+    g.close()
