@@ -33,6 +33,8 @@ def _args():
     ap.add_argument("--workload", default="rand-64k-e192")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--cpu-nodes", type=int, default=4096)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -88,6 +90,14 @@ def main():
     t_hw = torch.from_numpy(hg.hedge_w).to(dev)
     t_nw = torch.from_numpy(hg.node_w).to(dev)
     torch.cuda.synchronize()
+
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     part = pkg.Partitioner(device=0, profile=True)
 

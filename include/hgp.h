@@ -62,7 +62,9 @@ typedef struct hgp_options {
     int32_t theta;         /* refinement repetitions per level (Sec. VI-A); default 16 */
     uint64_t seed;         /* seed of the symmetric histogram noise (Sec. V-C); default 0 */
     int32_t profile;       /* 1 = time every kernel launch with HIP events (see hgp_kernel_stats) */
-    int32_t reserved[7];
+    int32_t flags;         /* bit 0: use the sparse (hash-table) candidate proposal at every level;
+                              by default it serves only levels with more than 65,536 nodes */
+    int32_t reserved[6];
 } hgp_options;
 
 /* Fills `opt` with the defaults above. */

@@ -29,7 +29,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 class hgp_options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", C.c_void_p), ("pi", C.c_int32), ("theta", C.c_int32), ("seed", C.c_uint64),
-                ("profile", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("profile", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class hgp_eval(C.Structure):
@@ -124,11 +124,12 @@ class Partitioner:
     """One library context on one device and torch stream."""
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
-                 use_torch: bool = True, stream=None):
+                 use_torch: bool = True, stream=None, sparse_proposal: bool = False):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
         opt.device, opt.pi, opt.theta, opt.seed, opt.profile = device, pi, theta, seed, int(profile)
+        opt.flags = 1 if sparse_proposal else 0
         self._keep = []
         self._stream = None
         if use_torch:

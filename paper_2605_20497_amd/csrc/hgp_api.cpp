@@ -127,7 +127,10 @@ void drop_hierarchy(Ctx* c) {
     }
     c->release(c->b_rho);
     for (auto& e : c->level_ev_coarsen) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
-    for (auto& e : c->level_ev_refine) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : c->level_ev_refine) {
+        if (e.first) (void)hipEventDestroy(e.first);
+        if (e.second) (void)hipEventDestroy(e.second);
+    }
     c->level_ev_coarsen.clear();
     c->level_ev_refine.clear();
     c->coarsened = c->refined = false;
@@ -287,6 +290,7 @@ hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt) {
         }
         HIPC(hipHostMalloc((void**)&c->host_scalars, 64 * sizeof(i64), hipHostMallocDefault));
         c->ws.resize(160);
+        c->force_hash_propose = (c->opt.flags & 1) != 0;
     } catch (const Error& e) {
         std::fprintf(stderr, "hgp_create: %s\n", e.msg.c_str());
         delete h;
@@ -340,6 +344,7 @@ hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int
         P = c->host_scalars[0];
     }
     require(P >= 0 && P < ((i64)1 << 40), HGP_E_INVALID, "he_off[E] out of range");
+    require(n_hedges > 0 || P == 0, HGP_E_INVALID, "he_off[0] must be 0");
     Level L;
     L.N = n_nodes;
     L.E = n_hedges;
@@ -450,6 +455,10 @@ static void refine_all(Ctx* c) {
         HIPC(hipMemcpyAsync(cur, r.data(), sizeof(i32) * r.size(), hipMemcpyHostToDevice, c->stream));
         c->sync();
     }
+    for (auto& e : c->level_ev_refine) {
+        if (e.first) (void)hipEventDestroy(e.first);
+        if (e.second) (void)hipEventDestroy(e.second);
+    }
     c->level_ev_refine.assign(l + 1, {nullptr, nullptr});
     const int theta = c->opt.theta;
     for (int lv = l; lv >= 0; --lv) {
@@ -460,8 +469,10 @@ static void refine_all(Ctx* c) {
             project_rho(c, cur, L.gamma(), nxt, L.N);
             std::swap(cur, nxt);
         }
+        bool unchanged = false;  // rho as the previous repetition found it
         for (int rep = 0; rep < theta; ++rep) {
-            RepInfo ri = refine_rep(c, L, cur, c->nparts, rep, theta);
+            RepInfo ri = refine_rep(c, L, cur, c->nparts, rep, theta, nullptr, unchanged);
+            unchanged = ri.kstar == 0;
             // A repetition that applies nothing leaves rho and the sizes as
             // they were, so the rest of its half would repeat it exactly.
             if (ri.kstar == 0) {

@@ -97,6 +97,7 @@ struct Ctx {
     i32 k = 0;
     i64 total_nw = 0, total_hw = 0;
     i32 max_card = 1;  // largest input h-edge; bounds every level
+    bool force_hash_propose = false;  // testing: use the sparse proposal at every level
 
     Buf b_hw;  // h-edge weights, shared by every level (h-edges keep their id)
     std::vector<Level> levels;
@@ -186,7 +187,10 @@ struct RepTrace {
     i64* prefix_gain = nullptr;
     i64* prefix_viol = nullptr;
 };
-RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace = nullptr);
+// reuse = rho is unchanged since the previous call on this level (it applied
+// no move), so its pins rows, sizes and moves are taken as they are.
+RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace = nullptr,
+                   bool reuse = false);
 void project_rho(Ctx* c, const i32* rho_coarse, const i32* gamma, i32* rho_fine, i32 N);
 void evaluate_dev(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out);
 

@@ -84,9 +84,9 @@ __global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ 
                                                  const i32* __restrict__ pins, const i32* __restrict__ hw,
                                                  const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
                                                  const unsigned long long* __restrict__ stats, int ib, i32* cand,
-                                                 u64* score) {
-    constexpr int R = 65536 / (int)sizeof(BIN);
-    __shared__ BIN bins[R];
+                                                 u64* score, int R) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    BIN* bins = (BIN*)smem_raw;  // R bins: one pass covers R consecutive neighbour ids
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
     const u64 cap = stats[4];
@@ -109,16 +109,28 @@ __global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ 
         for (int pass = 0; pass < npass && a < b; ++pass) {
             const i32 lo = pass * R;
             const i32 hi = min(N, lo + R);
-            for (i64 k = a + wv; k < b; k += nwv) {
-                const i32 e = inc[k];
-                const bool ein = (k - a) < nin_n;
-                const i64 e0 = he_off[e], e1 = he_off[e + 1];
+            // Each lane fetches the metadata of one incident h-edge (64 at a time
+            // per wave, so the dependent loads overlap); the wave then sweeps
+            // those h-edges' pins one h-edge at a time with coalesced reads.
+            for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
+                const i64 k = kb + lane;
+                const int valid = (int)(k < b);
+                const i32 e = inc[valid ? k : kb];
+                const i64 e0 = he_off[e], e1v = he_off[e + 1];
+                const i64 e1 = valid ? e1v : e0;
                 const i64 d0 = e0 + he_nsrc[e];
-                const BIN add = ((BIN)norm_weight(hw[e], e1 - e0)) << ib;
-                for (i64 j = e0 + lane; j < e1; j += kWave) {
-                    const i32 m = pins[j];
-                    if ((int)(m == n) | (int)(m < lo) | (int)(m >= hi)) continue;
-                    atomicAdd(&bins[m - lo], add + (((int)ein & (int)(j >= d0)) ? (BIN)1 : (BIN)0));
+                const BIN add = ((BIN)norm_weight(hw[e], e1v - e0)) << ib;
+                const int ein = (int)((k - a) < nin_n);
+                const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
+                for (int i = 0; i < nb; ++i) {
+                    const i64 s0 = __shfl(e0, i, kWave), s1 = __shfl(e1, i, kWave), sd = __shfl(d0, i, kWave);
+                    const BIN sadd = __shfl(add, i, kWave);
+                    const int sin = __shfl(ein, i, kWave);
+                    for (i64 j = s0 + lane; j < s1; j += kWave) {
+                        const i32 m = pins[j];
+                        if ((int)(m == n) | (int)(m < lo) | (int)(m >= hi)) continue;
+                        atomicAdd(&bins[m - lo], sadd + ((sin & (int)(j >= sd)) ? (BIN)1 : (BIN)0));
+                    }
                 }
             }
             __syncthreads();
@@ -152,6 +164,198 @@ __global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ 
             __syncthreads();
         }
         // Merge the per-thread lists: PI block-wide lexicographic maxima.
+        for (int r = 0; r < PI; ++r) {
+            u64 hs = bs[0];
+            i32 hm = bm[0];
+            wave_lexmax(hs, hm);
+            if (lane == 0) {
+                red_s[wv] = hs;
+                red_m[wv] = hm;
+            }
+            __syncthreads();
+            u64 ws = red_s[0];
+            i32 wm = red_m[0];
+            for (int w = 1; w < nwv; ++w) {
+                const u64 s2 = red_s[w];
+                const i32 m2 = red_m[w];
+                const bool t = lex_gt(s2, m2, ws, wm);
+                ws = t ? s2 : ws;
+                wm = t ? m2 : wm;
+            }
+            __syncthreads();
+            if ((int)(wm >= 0) & (int)(bm[0] == wm)) {
+#pragma unroll
+                for (int q = 0; q + 1 < PI; ++q) {
+                    bs[q] = bs[q + 1];
+                    bm[q] = bm[q + 1];
+                }
+                bs[PI - 1] = 0;
+                bm[PI - 1] = -1;
+            }
+            if (threadIdx.x == 0) {
+                cand[(i64)n * PI + r] = wm;
+                score[(i64)n * PI + r] = wm >= 0 ? ws : 0;
+            }
+        }
+    }
+}
+
+// Sparse variant of the proposal for levels with many nodes and modest
+// neighbourhoods: the histogram is an open-addressing table of C slots in
+// shared memory (key, packed (eta << ib) | inter, and a list of used slots).
+// When a node's neighbour bound sum_{e in I(n)} (|e| - 1) exceeds half the
+// table, neighbours are split into B passes by a hash of their id; a pass whose
+// keys do not fit restarts the node with twice as many passes.  The result is
+// the same exact top-PI as the dense variant.
+constexpr u32 kEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ u32 slot_hash(u32 m) { return m * 0x9E3779B1u; }
+__device__ __forceinline__ u32 pass_hash(u32 m) { return (m * 0x85EBCA77u) ^ (m >> 15); }
+
+template <typename BIN, int PI>
+__global__ __launch_bounds__(256) void k_propose_hash(
+    i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
+    const unsigned long long* __restrict__ stats, int ib, i32* cand, u64* score, int C) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    BIN* vals = (BIN*)smem_raw;
+    u32* keys = (u32*)(vals + C);
+    u32* touched = keys + C;
+    __shared__ u32 ntouched;
+    __shared__ int overflow;
+    __shared__ u64 red_s[16];
+    __shared__ i32 red_m[16];
+    __shared__ u64 red_b[16];
+    const u64 cap = stats[4];
+    const BIN imask = (((BIN)1) << ib) - 1;
+    const u32 cmask = (u32)C - 1;
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    for (int i = threadIdx.x; i < C; i += blockDim.x) {
+        vals[i] = 0;
+        keys[i] = kEmpty;
+    }
+    if (threadIdx.x == 0) {
+        ntouched = 0;
+        overflow = 0;
+    }
+    __syncthreads();
+    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        const i32 nin_n = inc_nin[n];
+        const i64 nw_n = nw[n];
+        // Upper bound on the number of distinct neighbours.
+        u64 bound = 0;
+        for (i64 k = a + threadIdx.x; k < b; k += blockDim.x) {
+            const i32 e = inc[k];
+            bound += (u64)(he_off[e + 1] - he_off[e] - 1);
+        }
+        bound = block_sum(bound, red_b);
+        u64 B = (bound + (u64)(C / 2) - 1) / (u64)(C / 2);
+        if (B == 0) B = 1;
+        u64 bs[PI];
+        i32 bm[PI];
+        for (;;) {  // restarts with more passes if a pass overflows the table
+#pragma unroll
+            for (int r = 0; r < PI; ++r) {
+                bs[r] = 0;
+                bm[r] = -1;
+            }
+            bool again = false;
+            for (u64 pass = 0; pass < B && bound > 0; ++pass) {
+                for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
+                    const i64 k = kb + lane;
+                    const int valid = (int)(k < b);
+                    const i32 e = inc[valid ? k : kb];
+                    const i64 e0 = he_off[e], e1v = he_off[e + 1];
+                    const i64 e1 = valid ? e1v : e0;
+                    const i64 d0 = e0 + he_nsrc[e];
+                    const BIN add = ((BIN)norm_weight(hw[e], e1v - e0)) << ib;
+                    const int ein = (int)((k - a) < nin_n);
+                    const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
+                    for (int i = 0; i < nb; ++i) {
+                        const i64 s0 = __shfl(e0, i, kWave), s1 = __shfl(e1, i, kWave), sd = __shfl(d0, i, kWave);
+                        const BIN sadd = __shfl(add, i, kWave);
+                        const int sin = __shfl(ein, i, kWave);
+                        for (i64 j = s0 + lane; j < s1; j += kWave) {
+                            const i32 m = pins[j];
+                            const int mine = (int)(m != n) & (int)((u64)pass_hash((u32)m) % B == pass);
+                            if (!mine) continue;
+                            const BIN v = sadd + ((sin & (int)(j >= sd)) ? (BIN)1 : (BIN)0);
+                            u32 sl = slot_hash((u32)m) & cmask;
+                            int done = 0;
+                            for (int probe = 0; probe < C; ++probe) {
+                                const u32 kk = keys[sl];
+                                if (kk == (u32)m) {
+                                    atomicAdd(&vals[sl], v);
+                                    done = 1;
+                                    break;
+                                }
+                                if (kk == kEmpty) {
+                                    const u32 prev = atomicCAS(&keys[sl], kEmpty, (u32)m);
+                                    if (prev == kEmpty) {
+                                        touched[atomicAdd(&ntouched, 1u)] = sl;
+                                        atomicAdd(&vals[sl], v);
+                                        done = 1;
+                                        break;
+                                    }
+                                    if (prev == (u32)m) {
+                                        atomicAdd(&vals[sl], v);
+                                        done = 1;
+                                        break;
+                                    }
+                                }
+                                sl = (sl + 1) & cmask;
+                            }
+                            if (!done) overflow = 1;
+                        }
+                    }
+                }
+                __syncthreads();
+                const u32 nt = ntouched;
+                const int ov = overflow;
+                for (u32 t = threadIdx.x; t < nt; t += blockDim.x) {
+                    const u32 sl = touched[t];
+                    const i32 m = (i32)keys[sl];
+                    const BIN v = vals[sl];
+                    keys[sl] = kEmpty;
+                    vals[sl] = 0;
+                    if (ov) continue;
+                    const u64 eta = (u64)(v >> ib);
+                    const i64 inter = (i64)(v & imask);
+                    const bool full = bm[PI - 1] >= 0;
+                    if ((int)full & (int)(eta + cap < bs[PI - 1])) continue;
+                    const u64 sc = eta + pair_noise(seed, n, m, cap);
+                    if ((int)full & (int)!lex_gt(sc, m, bs[PI - 1], bm[PI - 1])) continue;
+                    const i64 nw_m = nw[m], nin_m = inc_nin[m];
+                    if ((int)(nw_n + nw_m > omega) | (int)((i64)nin_n + nin_m - inter > delta)) continue;
+                    u64 cs = sc;
+                    i32 cm = m;
+#pragma unroll
+                    for (int r = 0; r < PI; ++r) {
+                        const bool better = lex_better(cs, cm, bs[r], bm[r]);
+                        const u64 ts = bs[r];
+                        const i32 tm = bm[r];
+                        bs[r] = better ? cs : ts;
+                        bm[r] = better ? cm : tm;
+                        cs = better ? ts : cs;
+                        cm = better ? tm : cm;
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    ntouched = 0;
+                    overflow = 0;
+                }
+                __syncthreads();
+                if (ov) {
+                    again = true;
+                    break;
+                }
+            }
+            if (!again) break;
+            B *= 2;
+        }
         for (int r = 0; r < PI; ++r) {
             u64 hs = bs[0];
             i32 hm = bm[0];
@@ -229,17 +433,22 @@ __global__ void k_round_parent(i32 N, const i32* __restrict__ t, i32* parent, i3
 }
 
 // Pointer jumping towards the roots: depth = number of hops to the root.
-__global__ void k_jump(i32 N, const i32* __restrict__ jin, const i32* __restrict__ din, i32* jout, i32* dout) {
+// *pending counts nodes whose pointer has not reached a root yet.
+__global__ void k_jump(i32 N, const i32* __restrict__ jin, const i32* __restrict__ din, i32* jout, i32* dout,
+                       unsigned long long* pending) {
+    unsigned long long c = 0;
     for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
         const i32 j = jin[n];
-        if (j >= 0) {
-            dout[n] = din[n] + din[j];
-            jout[n] = jin[j];
-        } else {
-            dout[n] = din[n];
-            jout[n] = j;
-        }
+        const i32 jj = j >= 0 ? j : (i32)n;
+        const i32 dj = din[jj], nj = jin[jj];
+        const i32 dn = din[n];
+        dout[n] = j >= 0 ? dn + dj : dn;
+        const i32 nxt = j >= 0 ? nj : j;
+        jout[n] = nxt;
+        c += nxt >= 0 ? 1 : 0;
     }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(pending, c);
 }
 
 __global__ void k_max_i32(i32 N, const i32* __restrict__ v, unsigned long long* out) {
@@ -383,14 +592,46 @@ int bits_for(u64 v) {
 }
 
 template <typename BIN>
+void launch_propose_hash(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, i32* cand,
+                         u64* score) {
+    const int C = 4096;  // slots; shared memory = C * (8 + sizeof(BIN)) bytes
+    const size_t lds = (size_t)C * (8 + sizeof(BIN));
+    const int grid = std::min<i64>(L.N, (i64)c->num_cu * 4);
+#define HGP_PROPH(PIV)                                                                                             \
+    case PIV:                                                                                                      \
+        LAUNCH(c, KF_PROPOSE, (k_propose_hash<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(),          \
+               L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed,       \
+               stats, ib, cand, score, C);                                                                         \
+        break;
+    switch (Pi) {
+        HGP_PROPH(1) HGP_PROPH(2) HGP_PROPH(3) HGP_PROPH(4) HGP_PROPH(5) HGP_PROPH(6) HGP_PROPH(7) HGP_PROPH(8)
+        default: fail(HGP_E_INVALID, "pi must be in 1..8");
+    }
+#undef HGP_PROPH
+}
+
+template <typename BIN>
 void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, i32* cand,
                     u64* score) {
-    const int grid = std::min<i64>(L.N, (i64)c->num_cu * 4);
+    // Dense id-range histogram while the node ids fit in a few passes over
+    // 64 KiB of bins; the hash table beyond.
+    if ((i64)L.N > 4 * (i64)(65536 / (int)sizeof(BIN)) || c->force_hash_propose) {
+        launch_propose_hash<BIN>(c, L, Pi, stats, ib, cand, score);
+        return;
+    }
+    // Bins per pass: all neighbour ids at once when they fit 64 KiB of LDS,
+    // otherwise 64 KiB worth per pass; smaller histograms let more blocks share
+    // a CU.
+    const int rmax = 65536 / (int)sizeof(BIN);
+    const int R = (int)std::min<i64>(rmax, std::max<i64>(64, L.N));
+    const size_t lds = sizeof(BIN) * (size_t)R;
+    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 1024))));
+    const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu * 2);
 #define HGP_PROP(PIV)                                                                                              \
     case PIV:                                                                                                      \
-        LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, 256, 0, L.N, L.inc_off(), L.inc_nin(), L.inc(),       \
+        LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(), L.inc(),     \
                L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib,     \
-               cand, score);                                                                                       \
+               cand, score, R);                                                                                    \
         break;
     switch (Pi) {
         HGP_PROP(1) HGP_PROP(2) HGP_PROP(3) HGP_PROP(4) HGP_PROP(5) HGP_PROP(6) HGP_PROP(7) HGP_PROP(8)
@@ -455,9 +696,15 @@ void coarsen_level(Ctx* c, int lv) {
         LAUNCH(c, KF_MATCH, k_round_parent, nb, 256, 0, N, t, parent, j0, d0, accA, accBV, accBC);
         i32 *ja = j0, *jb = j1, *da = d0, *db = d1;
         for (int it = 0; it < jump_iters; ++it) {
-            LAUNCH(c, KF_MATCH, k_jump, nb, 256, 0, N, ja, da, jb, db);
+            HIPC(hipMemsetAsync(stats + 7, 0, sizeof(u64), c->stream));
+            LAUNCH(c, KF_MATCH, k_jump, nb, 256, 0, N, ja, da, jb, db, stats + 7);
             std::swap(ja, jb);
             std::swap(da, db);
+            if (it % 3 == 2) {  // every pointer at a root: depths are final
+                i64 pend = 0;
+                read_back(c, stats + 7, &pend, 1, 8);
+                if (pend == 0) break;
+            }
         }
         HIPC(hipMemsetAsync(stats + 5, 0, sizeof(u64), c->stream));
         LAUNCH(c, KF_MATCH, k_max_i32, nb, 256, 0, N, da, stats + 5);

@@ -20,7 +20,7 @@ enum {
     WS_LRS = 112, WS_CSTART = 113, WS_SEQN = 114, WS_SEQS = 115, WS_SEQD = 116, WS_POSN = 117, WS_GSEQ = 118,
     WS_EVK = 119, WS_EVK2 = 120, WS_EVI = 121, WS_EVI2 = 122, WS_EVDS = 123, WS_EVDD = 124, WS_ES = 125,
     WS_ED = 126, WS_SEX = 127, WS_DEX = 128, WS_SEGST = 129, WS_DVQ = 130, WS_CEX = 131, WS_VEX = 132,
-    WS_RSTATS = 133
+    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137
 };
 
 // rstats: [0] active chain rounds flag, [1] links this round, [2] total links,
@@ -28,6 +28,22 @@ enum {
 constexpr i64 kGradeScale = 10000000;  // 10^7 x the paper's grade with alpha=1e-6, beta=1e-7
 constexpr int kWindow = 256;
 constexpr int kChainRounds = 16;
+
+// Row lookup: pins(p,e) and pins_in(p,e), zero if p holds no pin of e.
+__device__ __forceinline__ void row_find(const i32* __restrict__ part, const i32* __restrict__ cnt,
+                                         const i32* __restrict__ cin, i64 r0, i32 L, i32 p, i32& c, i32& ci) {
+    i32 lo = 0, hi = L;
+    while (lo < hi) {
+        const i32 mid = (lo + hi) >> 1;
+        if (part[r0 + mid] < p) lo = mid + 1;
+        else hi = mid;
+    }
+    const i32 at = lo < L ? lo : L - 1;  // rows are never empty
+    const int hit = (int)(lo < L) & (int)(part[r0 + at] == p);
+    const i32 cv = cnt[r0 + at], civ = cin[r0 + at];
+    c = hit ? cv : 0;
+    ci = hit ? civ : 0;
+}
 
 __global__ void k_part_sizes(i32 N, const i32* __restrict__ rho, const i32* __restrict__ nw, i64* psize) {
     for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
@@ -71,13 +87,12 @@ __global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __r
                                                const i32* __restrict__ part, const i32* __restrict__ cnt,
                                                const i32* __restrict__ len, const i32* __restrict__ hw,
                                                const i32* __restrict__ nw, const i32* __restrict__ rho,
-                                               const i64* __restrict__ psize, i64 omega, int size_aware,
-                                               i32* move_dst, i64* move_gain) {
-    constexpr int R = 16384;
-    __shared__ u32 bins[R];
+                                               const i64* __restrict__ psize, i64 omega, i32* move_dst,
+                                               i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R) {
+    extern __shared__ u32 bins[];  // R bins: one pass covers R consecutive partition ids
     __shared__ i64 red[16];
-    __shared__ i64 red_g[16];
-    __shared__ i32 red_p[16];
+    __shared__ i64 red_g[16], red_g2[16];
+    __shared__ i32 red_p[16], red_p2[16];
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     const int npass = (int)((nparts + R - 1) / R);
     for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
@@ -86,23 +101,37 @@ __global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __r
         const i32 ps = rho[n];
         const i64 a = inc_off[n], b = inc_off[n + 1];
         i64 saving = 0, wi = 0;
-        i64 bg = 0;
-        i32 bp = -1;
+        i64 bg = 0, bg2 = 0;  // best move, and best move that keeps size(p) + size(n) <= Omega
+        i32 bp = -1, bp2 = -1;
         for (int pass = 0; pass < npass; ++pass) {
             const i32 lo = pass * R;
             const i32 hi = min(nparts, lo + R);
-            for (i64 k = a + wv; k < b; k += nwv) {
-                const i32 e = inc[k];
-                const i32 w = hw[e];
+            // Each lane fetches the metadata of one incident h-edge (64 at a time
+            // per wave, so the dependent loads overlap); the wave then sweeps
+            // those rows one by one with coalesced reads of the partition ids.
+            for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
+                const i64 k = kb + lane;
+                const int valid = (int)(k < b);
+                const i32 e = inc[valid ? k : kb];
                 const i64 r0 = he_off[e];
-                const i32 L = len[e];
-                wi += ((int)(pass == 0) & (int)(lane == 0)) ? w : 0;
-                for (int q = lane; q < L; q += kWave) {
-                    const i32 p = part[r0 + q];
-                    const i32 cq = cnt[r0 + q];
-                    const int own = (int)(p == ps);
-                    saving += (own & (int)(pass == 0) & (int)(cq == 1)) ? w : 0;
-                    if ((own ^ 1) & (int)(p >= lo) & (int)(p < hi)) atomicAdd(&bins[p - lo], (u32)w);
+                const i32 Le = len[e], we = hw[e];
+                const i32 L = valid ? Le : 0;
+                const i32 w = valid ? we : 0;
+                if (pass == 0) {
+                    i32 c_own, ci_own;
+                    row_find(part, cnt, cnt, r0, Le, ps, c_own, ci_own);  // pins(p_s, e), never 0
+                    wi += w;
+                    saving += (int)(c_own == 1) ? w : 0;
+                }
+                const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
+                for (int i = 0; i < nb; ++i) {
+                    const i64 ri = __shfl(r0, i, kWave);
+                    const i32 Li = __shfl(L, i, kWave);
+                    const u32 wi_ = (u32)__shfl(w, i, kWave);
+                    for (int q = lane; q < Li; q += kWave) {
+                        const i32 p = part[ri + q];
+                        if ((int)(p != ps) & (int)(p >= lo) & (int)(p < hi)) atomicAdd(&bins[p - lo], wi_);
+                    }
                 }
             }
             if (pass == 0) {
@@ -119,31 +148,42 @@ __global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __r
                 const i32 p = lo + sidx;
                 const i64 g = saving - (wi - (i64)v);
                 const i64 szp = psize[p];
-                const int ok = (int)(g > 0) & ((size_aware ^ 1) | (int)((i64)nw[n] + szp <= omega));
-                const bool t = (ok & (int)lex_better(g, p, bg, bp)) != 0;
+                const int pos = (int)(g > 0);
+                const int fits = (int)((i64)nw[n] + szp <= omega);
+                const bool t = (pos & (int)lex_better(g, p, bg, bp)) != 0;
                 bg = t ? g : bg;
                 bp = t ? p : bp;
+                const bool t2 = (pos & fits & (int)lex_better(g, p, bg2, bp2)) != 0;
+                bg2 = t2 ? g : bg2;
+                bp2 = t2 ? p : bp2;
             }
             __syncthreads();
         }
         wave_lexmax_i64(bg, bp);
+        wave_lexmax_i64(bg2, bp2);
         if (lane == 0) {
             red_g[wv] = bg;
             red_p[wv] = bp;
+            red_g2[wv] = bg2;
+            red_p2[wv] = bp2;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            i64 G = red_g[0];
-            i32 Pp = red_p[0];
+        if (threadIdx.x < 2) {
+            const i64* rg = threadIdx.x == 0 ? red_g : red_g2;
+            const i32* rp = threadIdx.x == 0 ? red_p : red_p2;
+            i64 G = rg[0];
+            i32 Pp = rp[0];
             for (int w = 1; w < nwv; ++w) {
-                const i64 g2 = red_g[w];
-                const i32 p2 = red_p[w];
+                const i64 g2 = rg[w];
+                const i32 p2 = rp[w];
                 const bool t = lex_better(g2, p2, G, Pp);
                 G = t ? g2 : G;
                 Pp = t ? p2 : Pp;
             }
-            move_dst[n] = Pp;
-            move_gain[n] = Pp >= 0 ? G : 0;
+            i32* md = threadIdx.x == 0 ? move_dst : move_dst_sa;
+            i64* mg = threadIdx.x == 0 ? move_gain : move_gain_sa;
+            md[n] = Pp;
+            mg[n] = Pp >= 0 ? G : 0;
         }
         __syncthreads();
     }
@@ -421,95 +461,96 @@ __global__ void k_positions(i32 M, const i32* __restrict__ H, const i32* __restr
     }
 }
 
-// Row lookup: pins(p,e) and pins_in(p,e), zero if p holds no pin of e.
-__device__ __forceinline__ void row_find(const i32* __restrict__ part, const i32* __restrict__ cnt,
-                                         const i32* __restrict__ cin, i64 r0, i32 L, i32 p, i32& c, i32& ci) {
-    i32 lo = 0, hi = L;
-    while (lo < hi) {
-        const i32 mid = (lo + hi) >> 1;
-        if (part[r0 + mid] < p) lo = mid + 1;
-        else hi = mid;
-    }
-    const i32 at = lo < L ? lo : L - 1;  // rows are never empty
-    const int hit = (int)(lo < L) & (int)(part[r0 + at] == p);
-    const i32 cv = cnt[r0 + at], civ = cin[r0 + at];
-    c = hit ? cv : 0;
-    ci = hit ? civ : 0;
-}
 
-// In-sequence gain and events of the mover at sequence position q (one block
-// per mover).  For each e in I(n) the pin counts of p_s and p_d just before
-// n's move are pins(p,e) adjusted by every earlier mover m in e; n's move then
-// changes Conn by omega(e)([c_s = 1] - [c_d = 0]) (the cases of Eq.
-// in_sequence_gain), and D(p_s) / D(p_d) by the pins_in transitions to zero /
-// from zero (Sec. VI-D).  Emits gseq[q] and the two events (p_s, q) and (p_d, q)
-// carrying size and D deltas.
-__global__ __launch_bounds__(256) void k_inseq(
-    i32 M, const i32* __restrict__ seqn, const i32* __restrict__ seqs, const i32* __restrict__ seqd,
-    const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
-    const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
-    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
-    const i32* __restrict__ hw, const i32* __restrict__ nw, const i32* __restrict__ part,
-    const i32* __restrict__ cnt, const i32* __restrict__ cin, const i32* __restrict__ len, i64* gseq, u32* evk,
-    i64* evds, i64* evdd) {
-    __shared__ i64 red[16];
-    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
-    for (i32 q = blockIdx.x; q < M; q += gridDim.x) {
-        const i32 n = seqn[q], ps = seqs[q], pd = seqd[q];
-        const i64 a = inc_off[n], b = inc_off[n + 1];
-        const i32 nin_n = inc_nin[n];
-        i64 g = 0, dDs = 0, dDd = 0;
-        for (i64 k = a + wv; k < b; k += nwv) {
-            const i32 e = inc[k];
-            const bool ein = (k - a) < nin_n;
-            const i64 e0 = he_off[e], e1 = he_off[e + 1], d0 = e0 + he_nsrc[e];
-            i32 cs = 0, cis = 0, cd = 0, cid = 0;
-            if (lane == 0) {
-                row_find(part, cnt, cin, e0, len[e], ps, cs, cis);
-                row_find(part, cnt, cin, e0, len[e], pd, cd, cid);
+// In-sequence gains and D changes, one wave per h-edge (Sec. VI-C, VI-D).
+// For a mover n at sequence position q, h-edge e contributes to n's exact
+// connectivity change omega(e)([c_s = 1] - [c_d = 0]), where c_s and c_d are
+// the pin counts of e in p_s(n) and p_d(n) just before n moves (the cases of
+// Eq. in_sequence_gain), and, when n is a destination of e, the transitions of
+// pins_in(p,e) through zero that change D(p_s) and D(p_d).  Only movers among
+// e's own pins alter those counts, so the wave streams e's pins once, gathers
+// its movers in shared memory, and each mover adds up the effect of the earlier
+// ones.  Contributions reach per-mover accumulators through integer atomics
+// (order-independent).
+__global__ __launch_bounds__(64) void k_inseq_edges(
+    i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ hw, const i32* __restrict__ posn, const i32* __restrict__ rho,
+    const i32* __restrict__ move_dst, const i32* __restrict__ part, const i32* __restrict__ cnt,
+    const i32* __restrict__ cin, const i32* __restrict__ len, unsigned long long* gseq, i32* dds, i32* ddd,
+    int cap) {
+    extern __shared__ i32 sm[];  // 4 x cap entries; cap = the largest h-edge, so every mover of e fits
+    i32* lq = sm;
+    i32* lps = sm + cap;
+    i32* lpd = sm + 2 * cap;
+    i32* ldst = sm + 3 * cap;
+    const int lane = threadIdx.x;
+    const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+        const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
+        int k = 0;
+        for (i64 base = a; base < b; base += kWave) {
+            const i64 j = base + lane;
+            const int inb = (int)(j < b);
+            const i32 m = pins[inb ? j : a];
+            const i32 q = posn[m];
+            const int mv = inb & (int)(q < M);
+            const u64 mask = __ballot(mv);
+            if (mv) {
+                const int at = k + __popcll(mask & lt_mask);
+                lq[at] = q;
+                lps[at] = rho[m];
+                lpd[at] = move_dst[m];
+                ldst[at] = (int)(j >= d0);
             }
-            i32 xs = 0, xd = 0, xis = 0, xid = 0;
-            for (i64 j = e0 + lane; j < e1; j += kWave) {
-                const i32 m = pins[j];
-                if (posn[m] >= q) continue;
-                const i32 ms = rho[m], md = move_dst[m];
-                const i32 ds = (md == ps) - (ms == ps);
-                const i32 dd = (md == pd) - (ms == pd);
-                const i32 isd = (i32)(j >= d0);
-                xs += ds;
-                xd += dd;
-                xis += isd * ds;
-                xid += isd * dd;
-            }
-            xs = wave_sum(xs);
-            xd = wave_sum(xd);
-            xis = wave_sum(xis);
-            xid = wave_sum(xid);
-            if (lane == 0) {
+            k += __popcll(mask);
+        }
+        __syncthreads();
+        if (k > 0) {
+            const i64 w = hw[e];
+            const i32 L = len[e];
+            for (int i = lane; i < k; i += kWave) {
+                const i32 qi = lq[i], psi = lps[i], pdi = lpd[i], di = ldst[i];
+                i32 xs = 0, xd = 0, xis = 0, xid = 0;
+                for (int jj = 0; jj < k; ++jj) {
+                    const i32 qj = lq[jj], psj = lps[jj], pdj = lpd[jj], dj = ldst[jj];
+                    const i32 before = (i32)(qj < qi);
+                    const i32 es = before * ((i32)(pdj == psi) - (i32)(psj == psi));
+                    const i32 ed = before * ((i32)(pdj == pdi) - (i32)(psj == pdi));
+                    xs += es;
+                    xd += ed;
+                    xis += dj * es;
+                    xid += dj * ed;
+                }
+                i32 cs, cis, cd, cid;
+                row_find(part, cnt, cin, a, L, psi, cs, cis);
+                row_find(part, cnt, cin, a, L, pdi, cd, cid);
                 cs += xs;
                 cd += xd;
                 cis += xis;
                 cid += xid;
-                const i64 w = hw[e];
-                g += w * ((cs == 1 ? 1 : 0) - (cd == 0 ? 1 : 0));
-                if (ein) {
-                    dDs -= (cis == 1) ? 1 : 0;
-                    dDd += (cid == 0) ? 1 : 0;
-                }
+                const i64 g = w * ((i64)(cs == 1) - (i64)(cd == 0));
+                if (g != 0) atomicAdd(&gseq[qi], (unsigned long long)g);
+                const i32 ls = di * (i32)(cis == 1), gd = di * (i32)(cid == 0);
+                if (ls) atomicSub(&dds[qi], ls);
+                if (gd) atomicAdd(&ddd[qi], gd);
             }
         }
-        g = block_sum(g, red);
-        dDs = block_sum(dDs, red);
-        dDd = block_sum(dDd, red);
-        if (threadIdx.x == 0) {
-            gseq[q] = g;
-            evk[2 * (i64)q] = (u32)ps;
-            evds[2 * (i64)q] = -(i64)nw[n];
-            evdd[2 * (i64)q] = dDs;
-            evk[2 * (i64)q + 1] = (u32)pd;
-            evds[2 * (i64)q + 1] = (i64)nw[n];
-            evdd[2 * (i64)q + 1] = dDd;
-        }
+        __syncthreads();
+    }
+}
+
+// Two events per mover: (p_s, q) and (p_d, q) with their size and D deltas.
+__global__ void k_events_build(i32 M, const i32* __restrict__ seqn, const i32* __restrict__ seqs,
+                               const i32* __restrict__ seqd, const i32* __restrict__ nw, const i32* __restrict__ dds,
+                               const i32* __restrict__ ddd, u32* evk, i64* evds, i64* evdd) {
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < M; q += (i64)gridDim.x * blockDim.x) {
+        const i64 s = nw[seqn[q]];
+        evk[2 * q] = (u32)seqs[q];
+        evds[2 * q] = -s;
+        evdd[2 * q] = dds[q];
+        evk[2 * q + 1] = (u32)seqd[q];
+        evds[2 * q + 1] = s;
+        evdd[2 * q + 1] = ddd[q];
     }
 }
 
@@ -651,6 +692,17 @@ struct PhiBufs {
     i64 *psize, *pD;
 };
 
+PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
+    PhiBufs f;
+    f.part = wsp<i32>(c, WS_PHI_PART, (size_t)L.P + 1);
+    f.cnt = wsp<i32>(c, WS_PHI_CNT, (size_t)L.P + 1);
+    f.cin = wsp<i32>(c, WS_PHI_CIN, (size_t)L.P + 1);
+    f.len = wsp<i32>(c, WS_PHI_LEN, (size_t)L.E + 1);
+    f.psize = wsp<i64>(c, WS_PSIZE, nparts);
+    f.pD = wsp<i64>(c, WS_PD, nparts);
+    return f;
+}
+
 PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
     PhiBufs f;
     f.part = wsp<i32>(c, WS_PHI_PART, (size_t)L.P + 1);
@@ -671,22 +723,35 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
 
 }  // namespace
 
-RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace) {
+RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace,
+                   bool reuse) {
     RepInfo info;
     const i32 N = L.N;
     const int nbN = grid_for(N, 256, c->num_cu * 8);
-    PhiBufs f = phi_and_parts(c, L, rho, nparts);
+    // With `reuse`, rho is unchanged since the previous repetition (it applied
+    // nothing): its pins rows, sizes, D and both move variants still hold.
+    PhiBufs f = reuse ? phi_bufs(c, L, nparts) : phi_and_parts(c, L, rho, nparts);
     unsigned long long* rs = wsp<unsigned long long>(c, WS_RSTATS, 8);
     HIPC(hipMemsetAsync(rs, 0, 8 * sizeof(u64), c->stream));
     LAUNCH(c, KF_PART_STATS, k_initial_violations, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, f.psize,
            f.pD, c->omega, c->delta, rs + 5);
 
-    // Moves (Sec. VI-B).
-    i32* mdst = wsp<i32>(c, WS_MDST, N);
-    i64* mgain = wsp<i64>(c, WS_MGAIN, N);
-    const int size_aware = rep >= theta / 2 ? 1 : 0;
-    LAUNCH(c, KF_GAINS, k_gains, std::min<i64>(N, (i64)c->num_cu * 4), 256, 0, N, nparts, L.inc_off(), L.inc(),
-           L.he_off(), f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, size_aware, mdst, mgain);
+    // Moves (Sec. VI-B): both the unconstrained and the size-aware variant.
+    i32* mdst_any = wsp<i32>(c, WS_MDST, N);
+    i64* mgain_any = wsp<i64>(c, WS_MGAIN, N);
+    i32* mdst_sa = wsp<i32>(c, WS_MDST_SA, N);
+    i64* mgain_sa = wsp<i64>(c, WS_MGAIN_SA, N);
+    const bool size_aware = rep >= theta / 2;
+    if (!reuse) {
+        const int R = (int)std::min<i64>(16384, std::max<i64>(64, nparts));
+        const size_t lds = sizeof(u32) * (size_t)R;
+        const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 1024))));
+        LAUNCH(c, KF_GAINS, k_gains, std::min<i64>(N, (i64)c->num_cu * per_cu * 2), 256, lds, N, nparts, L.inc_off(),
+               L.inc(), L.he_off(), f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, mdst_any,
+               mgain_any, mdst_sa, mgain_sa, R);
+    }
+    i32* mdst = size_aware ? mdst_sa : mdst_any;
+    i64* mgain = size_aware ? mgain_sa : mgain_any;
     i32* mflag = wsp<i32>(c, WS_MFLAG, N);
     i32* mpos = wsp<i32>(c, WS_MPOS, (size_t)N + 1);
     LAUNCH(c, KF_MOVES, k_move_flags, nbN, 256, 0, N, mdst, mflag);
@@ -747,6 +812,12 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         LAUNCH(c, KF_CHAINS, k_chain_accept_b, nbM, 256, 0, (i32)M, rs, prop, propG, accG, snode, accN);
         LAUNCH(c, KF_CHAINS, k_chain_link, nbM, 256, 0, (i32)M, rs, prop, propG, accG, accN, snode, pred, succ);
         LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);
+        // Later rounds of a finished chain build are no-ops; stop issuing them.
+        if (round == 1 || round == 3 || round == 7) {
+            i64 active = 0;
+            read_back(c, rs, &active, 1, 8);
+            if (!active) break;
+        }
     }
 
     // Chains: cycles, heads, ranks.
@@ -810,9 +881,18 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i32* evi2 = wsp<i32>(c, WS_EVI2, M2);
     i64* evds = wsp<i64>(c, WS_EVDS, M2);
     i64* evdd = wsp<i64>(c, WS_EVDD, M2);
-    LAUNCH(c, KF_INSEQ, k_inseq, std::min<i64>(M, (i64)c->num_cu * 8), 256, 0, (i32)M, seqn, seqs, seqd, posn, rho,
-           mdst, L.inc_off(), L.inc_nin(), L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), f.part,
-           f.cnt, f.cin, f.len, gseq, evk, evds, evdd);
+    i32* dds = wsp<i32>(c, WS_DDS, M);
+    i32* ddd = wsp<i32>(c, WS_DDD, M);
+    HIPC(hipMemsetAsync(gseq, 0, sizeof(i64) * M, c->stream));
+    HIPC(hipMemsetAsync(dds, 0, sizeof(i32) * M, c->stream));
+    HIPC(hipMemsetAsync(ddd, 0, sizeof(i32) * M, c->stream));
+    if (L.E > 0) {
+        const int cap = c->max_card;
+        LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, sizeof(i32) * 4 * cap,
+               L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), c->hw(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len,
+               (unsigned long long*)gseq, dds, ddd, cap);
+    }
+    LAUNCH(c, KF_EVENTS, k_events_build, nbM, 256, 0, (i32)M, seqn, seqs, seqd, L.nw(), dds, ddd, evk, evds, evdd);
     iota_i32(c, evi, M2);
     sort_pairs_u32(c, evk, evk2, evi, evi2, M2, bits_for((u64)nparts));
     i64* es = wsp<i64>(c, WS_ES, M2);

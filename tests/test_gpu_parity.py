@@ -11,17 +11,17 @@ from paper_2605_20497_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _gpu(Pi=4, theta=16, seed=0, profile=False):
+def _gpu(Pi=4, theta=16, seed=0, profile=False, sparse=False):
     from paper_2605_20497_amd import Partitioner
-    return Partitioner(pi=Pi, theta=theta, seed=seed, profile=profile)
+    return Partitioner(pi=Pi, theta=theta, seed=seed, profile=profile, sparse_proposal=sparse)
 
 
-def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label=""):
+def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label="", sparse=False):
     print("case", label, "N", hg.n_nodes, "E", hg.n_hedges, "P", hg.n_pins, "omega", omega, "delta", delta,
-          "k", k, flush=True)
+          "k", k, "sparse", sparse, flush=True)
     og = oracle.Graph(hg)
     res = og.partition(omega, delta, k=k, Pi=Pi, theta=theta, seed=seed)
-    g = _gpu(Pi, theta, seed)
+    g = _gpu(Pi, theta, seed, sparse=sparse)
     g.load(hg)
     g.hgp_set_limits(omega, delta, k)
     nl = g.hgp_coarsen()
@@ -76,6 +76,20 @@ def test_small_random_full_pipeline(case):
     n, e, card, seed, msrc, mhw, mnw, omega, delta = case
     hg = W.random_small(n, e, card, seed, max_src=msrc, max_hw=mhw, max_nw=mnw)
     _compare_runs(hg, omega, delta, label="small-%d" % seed)
+
+
+@pytest.mark.parametrize("case", SMALL_CASES[:4], ids=lambda c: "n%d-e%d-s%d" % (c[0], c[1], c[3]))
+def test_small_random_sparse_proposal(case):
+    n, e, card, seed, msrc, mhw, mnw, omega, delta = case
+    hg = W.random_small(n, e, card, seed, max_src=msrc, max_hw=mhw, max_nw=mnw)
+    _compare_runs(hg, omega, delta, label="sparse-%d" % seed, sparse=True)
+
+
+def test_sparse_proposal_with_passes():
+    # Neighbourhoods (~7,000) above half the 4,096-slot table force several
+    # hashed passes per node.
+    hg = W.random_snn(8192, 95, 6)
+    _compare_runs(hg, 512, 2048, label="snn-8k-sparse", sparse=True)
 
 
 def test_snn_shaped_small():
