@@ -13,7 +13,8 @@ namespace {
 enum {
     WS_STATS = 30, WS_T = 31, WS_S = 32, WS_PARENT = 33, WS_J0 = 34, WS_J1 = 35, WS_D0 = 36, WS_D1 = 37,
     WS_ACC_A = 38, WS_ACC_BV = 39, WS_ACC_BC = 40, WS_SS0 = 41, WS_SS10 = 42, WS_ISO_FLAG = 43, WS_ISO_POS = 44,
-    WS_ISO_KEYS = 45, WS_ISO_KEYS2 = 46, WS_ISO_VALS = 47, WS_ISO_VALS2 = 48, WS_REP = 49, WS_CID = 50
+    WS_ISO_KEYS = 45, WS_ISO_KEYS2 = 46, WS_ISO_VALS = 47, WS_ISO_VALS2 = 48, WS_REP = 49, WS_CID = 50,
+    WS_BND = 51
 };
 
 // stats: [0] max_n sum_{e in I(n)} t(e); [1] max |in(n)|; [2] sum of t(e) over
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ 
                                                  const i32* __restrict__ pins, const i32* __restrict__ hw,
                                                  const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
                                                  const unsigned long long* __restrict__ stats, int ib, i32* cand,
-                                                 u64* score, int R) {
+                                                 u64* score, int R, const i32* __restrict__ bnd) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     BIN* bins = (BIN*)smem_raw;  // R bins: one pass covers R consecutive neighbour ids
     __shared__ u64 red_s[16];
@@ -112,24 +113,44 @@ __global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ 
             // Each lane fetches the metadata of one incident h-edge (64 at a time
             // per wave, so the dependent loads overlap); the wave then sweeps
             // those h-edges' pins one h-edge at a time with coalesced reads.
+            // With several passes, bnd[] gives where this pass's id range starts
+            // and ends inside every h-edge's sorted destination block, so a
+            // pass reads only its own destinations; sources are few and tested.
             for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
                 const i64 k = kb + lane;
                 const int valid = (int)(k < b);
                 const i32 e = inc[valid ? k : kb];
                 const i64 e0 = he_off[e], e1v = he_off[e + 1];
-                const i64 e1 = valid ? e1v : e0;
-                const i64 d0 = e0 + he_nsrc[e];
+                const i64 d0v = e0 + he_nsrc[e];
+                const i64 d0 = valid ? d0v : e0;  // source block end
+                i64 dlo = d0v, dhi = e1v;
+                if (npass > 1) {
+                    dlo = e0 + bnd[(i64)e * (npass + 1) + pass];
+                    dhi = e0 + bnd[(i64)e * (npass + 1) + pass + 1];
+                }
+                dhi = valid ? dhi : dlo;
                 const BIN add = ((BIN)norm_weight(hw[e], e1v - e0)) << ib;
-                const int ein = (int)((k - a) < nin_n);
+                const BIN add_in = add + (((k - a) < nin_n) ? (BIN)1 : (BIN)0);  // destination pins of e in in(n)
                 const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
                 for (int i = 0; i < nb; ++i) {
-                    const i64 s0 = __shfl(e0, i, kWave), s1 = __shfl(e1, i, kWave), sd = __shfl(d0, i, kWave);
-                    const BIN sadd = __shfl(add, i, kWave);
-                    const int sin = __shfl(ein, i, kWave);
-                    for (i64 j = s0 + lane; j < s1; j += kWave) {
+                    const i64 s0 = __shfl(e0, i, kWave), sd = __shfl(d0, i, kWave);
+                    const i64 t0 = __shfl(dlo, i, kWave), t1 = __shfl(dhi, i, kWave);
+                    const BIN sadd = __shfl(add, i, kWave), sadd_in = __shfl(add_in, i, kWave);
+                    for (i64 j = s0 + lane; j < sd; j += kWave) {  // sources of e
                         const i32 m = pins[j];
                         if ((int)(m == n) | (int)(m < lo) | (int)(m >= hi)) continue;
-                        atomicAdd(&bins[m - lo], sadd + ((sin & (int)(j >= sd)) ? (BIN)1 : (BIN)0));
+                        atomicAdd(&bins[m - lo], sadd);
+                    }
+                    for (i64 j0 = t0; j0 < t1; j0 += 4 * kWave) {  // this pass's destinations
+                        i32 mm[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const i64 j = j0 + u * kWave + lane;
+                            mm[u] = j < t1 ? pins[j] : n;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (mm[u] != n) atomicAdd(&bins[mm[u] - lo], sadd_in);
                     }
                 }
             }
@@ -392,6 +413,30 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     }
 }
 
+// For each h-edge: offsets (from the h-edge start) where the destination
+// block crosses the pass boundaries 0, R, 2R, ..., npass*R; the destination
+// block is sorted, so each is a lower bound.
+__global__ void k_pass_bounds(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
+                              const i32* __restrict__ pins, int R, int npass, i32* bnd) {
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (i64)gridDim.x * blockDim.x) {
+        const i64 e0 = he_off[e], e1 = he_off[e + 1], d0 = e0 + he_nsrc[e];
+        i64 lo = d0;
+        for (int p = 0; p <= npass; ++p) {
+            const i64 key = (i64)p * R;
+            i64 l = lo, h = e1;
+            while (l < h) {
+                const i64 mid = (l + h) >> 1;
+                const i32 v = pins[mid];
+                const int lt = (int)((i64)v < key);
+                l = lt ? mid + 1 : l;
+                h = lt ? h : mid;
+            }
+            bnd[e * (npass + 1) + p] = (i32)(l - e0);
+            lo = l;
+        }
+    }
+}
+
 // ---- matching rounds (Sec. V-D) -------------------------------------------
 // Round r's target: the r-th candidate if both ends are still unmatched
 // (t = -2 marks nodes matched in an earlier round, -1 an undefined target).
@@ -542,14 +587,29 @@ __global__ void k_iso_keys(i32 N, const i32* __restrict__ flag, const i32* __res
 // Nodes sorted by (size, id): the smallest left pairs with the largest that
 // fits both caps, with |in| + |in| standing in for the union.  Serial by
 // nature; one thread.
-__global__ void k_iso_pair(i32 cnt, const i32* __restrict__ order, const i32* __restrict__ nw,
-                           const i32* __restrict__ nin, i64 omega, i64 delta, i32* match) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(1024) void k_iso_pair(i32 cnt, const i32* __restrict__ order,
+                                                   const i32* __restrict__ nw, const i32* __restrict__ nin,
+                                                   i64 omega, i64 delta, i32* match, int staged) {
+    // With `staged`, the block first gathers sizes and |in| of the sorted nodes
+    // into shared memory so that the serial two-pointer walk reads only LDS.
+    extern __shared__ i32 st[];
+    i32* sw = st;
+    i32* si = st + (staged ? cnt : 0);
+    if (staged) {
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const i32 v = order[t];
+            sw[t] = nw[v];
+            si[t] = nin[v];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     i32 i = 0, j = cnt - 1;
     while (i < j) {
-        const i32 a = order[i], b = order[j];
-        const i64 wa = nw[a], wb = nw[b], ia = nin[a], ib = nin[b];
+        const i64 wa = staged ? sw[i] : nw[order[i]], wb = staged ? sw[j] : nw[order[j]];
+        const i64 ia = staged ? si[i] : nin[order[i]], ib = staged ? si[j] : nin[order[j]];
         if ((int)(wa + wb <= omega) & (int)(ia + ib <= delta)) {
+            const i32 a = order[i], b = order[j];
             match[a] = b;
             match[b] = a;
             ++i;
@@ -627,11 +687,18 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
     const size_t lds = sizeof(BIN) * (size_t)R;
     const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 1024))));
     const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu * 2);
+    const int npass = (int)ceil_div(L.N, R);
+    i32* bnd = nullptr;
+    if (npass > 1 && L.E > 0) {
+        bnd = wsp<i32>(c, WS_BND, (size_t)L.E * (npass + 1));
+        LAUNCH(c, KF_PROPOSE, k_pass_bounds, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, L.he_off(),
+               L.he_nsrc(), L.pins(), R, npass, bnd);
+    }
 #define HGP_PROP(PIV)                                                                                              \
     case PIV:                                                                                                      \
         LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(), L.inc(),     \
                L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib,     \
-               cand, score, R);                                                                                    \
+               cand, score, R, bnd);                                                                               \
         break;
     switch (Pi) {
         HGP_PROP(1) HGP_PROP(2) HGP_PROP(3) HGP_PROP(4) HGP_PROP(5) HGP_PROP(6) HGP_PROP(7) HGP_PROP(8)
@@ -734,8 +801,9 @@ void coarsen_level(Ctx* c, int lv) {
         i32* vals2 = wsp<i32>(c, WS_ISO_VALS2, niso);
         LAUNCH(c, KF_ISOLATED, k_iso_keys, nb, 256, 0, N, flag, pos, L.nw(), keys, vals);
         sort_pairs_u64(c, keys, keys2, vals, vals2, niso, 64);
-        LAUNCH(c, KF_ISOLATED, k_iso_pair, 1, 64, 0, (i32)niso, vals2, L.nw(), L.inc_nin(), c->omega, c->delta,
-               match);
+        const int staged = niso <= 8192 ? 1 : 0;  // 64 KiB of shared memory at most
+        LAUNCH(c, KF_ISOLATED, k_iso_pair, 1, 1024, staged ? sizeof(i32) * 2 * niso : 0, (i32)niso, vals2, L.nw(),
+               L.inc_nin(), c->omega, c->delta, match, staged);
     }
 
     // Cluster map.

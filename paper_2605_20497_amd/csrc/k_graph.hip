@@ -95,19 +95,38 @@ __global__ __launch_bounds__(256) void k_validate_nodes(i32 N, const i32* __rest
 // h-edges first and each block ascending (Sec. IV-B).
 __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__ he_off,
                                                   const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
-                                                  u32* keys, i32* vals, i32* cnt, i32* nin) {
+                                                  u32* keys, i32* vals) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
         const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
         for (i64 j = a + lane; j < b; j += kWave) {
             const i32 n = pins[j];
-            const bool is_src = j < d0;
-            keys[j] = ((u32)n << 1) | (is_src ? 1u : 0u);
+            keys[j] = ((u32)n << 1) | (j < d0 ? 1u : 0u);
             vals[j] = (i32)e;
-            atomicAdd(&cnt[n], 1);
-            if (!is_src) atomicAdd(&nin[n], 1);
         }
+    }
+}
+
+// Incidence offsets and inbound counts from the sorted keys: node n's entries
+// start at the first key >= 2n; its outbound ones at the first key >= 2n+1.
+__global__ void k_inc_offsets(i32 N, i64 P, const u32* __restrict__ skeys, i64* inc_off, i32* nin) {
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n <= N; n += (i64)gridDim.x * blockDim.x) {
+        i64 pos[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const u64 key = 2ull * (u64)n + (u64)t;
+            i64 l = 0, h = P;
+            while (l < h) {
+                const i64 mid = (l + h) >> 1;
+                const int lt = (int)((u64)skeys[mid] < key);
+                l = lt ? mid + 1 : l;
+                h = lt ? h : mid;
+            }
+            pos[t] = l;
+        }
+        inc_off[n] = pos[0];
+        if (n < N) nin[n] = (i32)(pos[1] - pos[0]);
     }
 }
 
@@ -244,17 +263,15 @@ void build_incidence(Ctx* c, Level& L) {
     u32* keys = wsp<u32>(c, WS_KEYS, P);
     u32* keys_out = wsp<u32>(c, WS_KEYS_OUT, P);
     i32* vals = wsp<i32>(c, WS_VALS, P);
-    i32* cnt = wsp<i32>(c, WS_CNT, (size_t)L.N + 1);
     L.b_inc_nin = c->alloc(sizeof(i32) * (size_t)L.N);
     L.b_inc_off = c->alloc(sizeof(i64) * ((size_t)L.N + 1));
     L.b_inc = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
-    HIPC(hipMemsetAsync(cnt, 0, sizeof(i32) * (size_t)L.N, c->stream));
-    HIPC(hipMemsetAsync(L.inc_nin(), 0, sizeof(i32) * (size_t)L.N, c->stream));
     if (L.E > 0)
         LAUNCH(c, KF_TRANSPOSE, k_pin_keys, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(),
-               L.pins(), keys, vals, cnt, L.inc_nin());
+               L.pins(), keys, vals);
     sort_pairs_u32(c, keys, keys_out, vals, L.inc(), P, bits_for(2ull * (u64)L.N));
-    scan_excl_i32_to_i64(c, cnt, L.inc_off(), L.N);
+    LAUNCH(c, KF_TRANSPOSE, k_inc_offsets, grid_for((i64)L.N + 1, 256, c->num_cu * 8), 256, 0, L.N, P,
+           (const u32*)keys_out, L.inc_off(), L.inc_nin());
 }
 
 void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {

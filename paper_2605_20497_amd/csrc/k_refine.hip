@@ -50,18 +50,31 @@ __global__ void k_part_sizes(i32 N, const i32* __restrict__ rho, const i32* __re
         atomicAdd((unsigned long long*)&psize[rho[n]], (unsigned long long)nw[n]);
 }
 
-// D(p) = |{e : pins_in(p,e) > 0}| from the rows.
+// D(p) = |{e : pins_in(p,e) > 0}| from the rows.  With nbins > 0 (all
+// partition ids fit) each block counts in shared memory and adds its nonzero
+// counts once at the end.
 __global__ __launch_bounds__(256) void k_part_inbound(i32 E, const i64* __restrict__ he_off,
                                                       const i32* __restrict__ part, const i32* __restrict__ cin,
-                                                      const i32* __restrict__ len, i64* pD) {
+                                                      const i32* __restrict__ len, i64* pD, int nbins) {
+    extern __shared__ u32 hist[];
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
         const i64 a = he_off[e];
         const i32 L = len[e];
-        for (int r = lane; r < L; r += kWave)
-            if (cin[a + r] > 0) atomicAdd((unsigned long long*)&pD[part[a + r]], 1ull);
+        for (int r = lane; r < L; r += kWave) {
+            const i32 ci = cin[a + r], p = part[a + r];
+            if (ci > 0) {
+                if (nbins > 0) atomicAdd(&hist[p], 1u);
+                else atomicAdd((unsigned long long*)&pD[p], 1ull);
+            }
+        }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        if (hist[i]) atomicAdd((unsigned long long*)&pD[i], (unsigned long long)hist[i]);
 }
 
 // Violated partitions before any move.
@@ -128,9 +141,17 @@ __global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __r
                     const i64 ri = __shfl(r0, i, kWave);
                     const i32 Li = __shfl(L, i, kWave);
                     const u32 wi_ = (u32)__shfl(w, i, kWave);
-                    for (int q = lane; q < Li; q += kWave) {
-                        const i32 p = part[ri + q];
-                        if ((int)(p != ps) & (int)(p >= lo) & (int)(p < hi)) atomicAdd(&bins[p - lo], wi_);
+                    for (int q0 = 0; q0 < Li; q0 += 4 * kWave) {
+                        i32 pp[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int q = q0 + u * kWave + lane;
+                            pp[u] = q < Li ? part[ri + q] : ps;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if ((int)(pp[u] != ps) & (int)(pp[u] >= lo) & (int)(pp[u] < hi))
+                                atomicAdd(&bins[pp[u] - lo], wi_);
                     }
                 }
             }
@@ -715,9 +736,11 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
     HIPC(hipMemsetAsync(f.psize, 0, sizeof(i64) * nparts, c->stream));
     HIPC(hipMemsetAsync(f.pD, 0, sizeof(i64) * nparts, c->stream));
     LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), f.psize);
-    if (L.E > 0)
-        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), f.part,
-               f.cin, f.len, f.pD);
+    if (L.E > 0) {
+        const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
+        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 4, c->num_cu * 2), 256, sizeof(u32) * nbins, L.E,
+               L.he_off(), f.part, f.cin, f.len, f.pD, nbins);
+    }
     return f;
 }
 
