@@ -48,6 +48,14 @@ __device__ __forceinline__ T wave_min(T v) {
 }
 
 // Inclusive prefix sum across the wave.
+// Orders shared-memory writes of one wave before later reads of other lanes of
+// the same wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
     const int l = lane_id();

@@ -78,18 +78,38 @@ __global__ void k_noise_cap(unsigned long long* stats) {
 // validity (Eq. proposal_graph: sizes, and |in(n) ∪ in(m)| through inter), and
 // keeps per thread the best PI valid neighbours by (score desc, id desc); the
 // block merges the thread lists at the end.
+//
+// Pin sweep: each wave owns a batch of up to 64 incident h-edges (one per
+// lane).  Their pin segments for the current pass (all sources, plus the
+// destinations whose ids fall in the pass's range) are concatenated into one
+// index space through a per-wave offset table in shared memory, and every lane
+// walks that space with stride 64, kProposeU loads in flight at a time, so a
+// wave keeps many loads outstanding whatever the h-edge sizes.
+constexpr int kProposeU = 8;
+constexpr int kProposeWaves = 4;
+
+template <typename BIN>
+struct SegTable {
+    i32 start[kProposeWaves][kWave];    // first flat index of the lane's segment
+    i32 src_end[kProposeWaves][kWave];  // flat index where its destinations begin
+    i64 sbase[kProposeWaves][kWave];    // pin position = base + flat index
+    i64 dbase[kProposeWaves][kWave];
+    BIN add[kProposeWaves][kWave];      // per source pin
+    BIN add_in[kProposeWaves][kWave];   // per destination pin
+};
+
 template <typename BIN, int PI>
-__global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ inc_off,
-                                                 const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
-                                                 const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
-                                                 const i32* __restrict__ pins, const i32* __restrict__ hw,
-                                                 const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
-                                                 const unsigned long long* __restrict__ stats, int ib, i32* cand,
-                                                 u64* score, int R, const i32* __restrict__ bnd) {
+__global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
+    i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
+    const unsigned long long* __restrict__ stats, int ib, i32* cand, u64* score, int R,
+    const i32* __restrict__ bnd) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     BIN* bins = (BIN*)smem_raw;  // R bins: one pass covers R consecutive neighbour ids
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
+    __shared__ SegTable<BIN> tab;
     const u64 cap = stats[4];
     const int npass = (int)((N + R - 1) / R);
     const BIN imask = (((BIN)1) << ib) - 1;
@@ -107,52 +127,69 @@ __global__ __launch_bounds__(256) void k_propose(i32 N, const i64* __restrict__ 
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i32 nin_n = inc_nin[n];
         const i64 nw_n = nw[n];
+        // h-edges per wave batch: spread the node's h-edges evenly over the waves.
+        const i64 deg = b - a;
+        const i64 chunk = deg <= (i64)nwv * kWave ? (deg + nwv - 1) / nwv : (i64)kWave;
+        const bool one_batch = deg <= (i64)nwv * kWave;
+        i32 e = 0;
+        i64 e0 = 0, e1v = 0, d0v = 0;
+        BIN add = 0, add_in = 0;
+        int valid = 0;
         for (int pass = 0; pass < npass && a < b; ++pass) {
             const i32 lo = pass * R;
             const i32 hi = min(N, lo + R);
-            // Each lane fetches the metadata of one incident h-edge (64 at a time
-            // per wave, so the dependent loads overlap); the wave then sweeps
-            // those h-edges' pins one h-edge at a time with coalesced reads.
-            // With several passes, bnd[] gives where this pass's id range starts
-            // and ends inside every h-edge's sorted destination block, so a
-            // pass reads only its own destinations; sources are few and tested.
-            for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
-                const i64 k = kb + lane;
-                const int valid = (int)(k < b);
-                const i32 e = inc[valid ? k : kb];
-                const i64 e0 = he_off[e], e1v = he_off[e + 1];
-                const i64 d0v = e0 + he_nsrc[e];
-                const i64 d0 = valid ? d0v : e0;  // source block end
+            for (i64 kb = a + (i64)wv * chunk; kb < b; kb += (i64)nwv * chunk) {
+                if ((pass == 0) | !one_batch) {
+                    const i64 k = kb + lane;
+                    valid = (int)(lane < chunk) & (int)(k < b);
+                    e = inc[valid ? k : kb];
+                    e0 = he_off[e];
+                    e1v = he_off[e + 1];
+                    d0v = e0 + he_nsrc[e];
+                    add = ((BIN)norm_weight(hw[e], e1v - e0)) << ib;
+                    add_in = add + (((k - a) < nin_n) ? (BIN)1 : (BIN)0);  // destinations of e lie in in(n)
+                }
                 i64 dlo = d0v, dhi = e1v;
                 if (npass > 1) {
                     dlo = e0 + bnd[(i64)e * (npass + 1) + pass];
                     dhi = e0 + bnd[(i64)e * (npass + 1) + pass + 1];
                 }
-                dhi = valid ? dhi : dlo;
-                const BIN add = ((BIN)norm_weight(hw[e], e1v - e0)) << ib;
-                const BIN add_in = add + (((k - a) < nin_n) ? (BIN)1 : (BIN)0);  // destination pins of e in in(n)
-                const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
-                for (int i = 0; i < nb; ++i) {
-                    const i64 s0 = __shfl(e0, i, kWave), sd = __shfl(d0, i, kWave);
-                    const i64 t0 = __shfl(dlo, i, kWave), t1 = __shfl(dhi, i, kWave);
-                    const BIN sadd = __shfl(add, i, kWave), sadd_in = __shfl(add_in, i, kWave);
-                    for (i64 j = s0 + lane; j < sd; j += kWave) {  // sources of e
-                        const i32 m = pins[j];
-                        if ((int)(m == n) | (int)(m < lo) | (int)(m >= hi)) continue;
-                        atomicAdd(&bins[m - lo], sadd);
-                    }
-                    for (i64 j0 = t0; j0 < t1; j0 += 4 * kWave) {  // this pass's destinations
-                        i32 mm[4];
+                const i32 cs = valid ? (i32)(d0v - e0) : 0;
+                const i32 cd = valid ? (i32)(dhi - dlo) : 0;
+                const i32 incl = wave_incl_scan(cs + cd);
+                const i32 excl = incl - cs - cd;
+                const i32 T = __shfl(incl, kWave - 1, kWave);
+                tab.start[wv][lane] = excl;
+                tab.src_end[wv][lane] = excl + cs;
+                tab.sbase[wv][lane] = e0 - excl;
+                tab.dbase[wv][lane] = dlo - cs - excl;
+                tab.add[wv][lane] = add;
+                tab.add_in[wv][lane] = add_in;
+                wave_sync();
+                int cur = 0;
+                for (i32 j0 = 0; j0 < T; j0 += kProposeU * kWave) {
+                    i32 mm[kProposeU];
+                    BIN ad[kProposeU];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const i64 j = j0 + u * kWave + lane;
-                            mm[u] = j < t1 ? pins[j] : n;
+                    for (int u = 0; u < kProposeU; ++u) {
+                        const i32 j = j0 + u * kWave + lane;
+                        const int in = (int)(j < T);
+                        while ((int)(cur + 1 < kWave) & in) {
+                            if (tab.start[wv][cur + 1] > j) break;
+                            ++cur;
                         }
+                        const int is_src = (int)(j < tab.src_end[wv][cur]);
+                        const i64 pos = in ? (is_src ? tab.sbase[wv][cur] : tab.dbase[wv][cur]) + j : 0;
+                        ad[u] = is_src ? tab.add[wv][cur] : tab.add_in[wv][cur];
+                        mm[u] = in ? pins[pos] : n;
+                    }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (mm[u] != n) atomicAdd(&bins[mm[u] - lo], sadd_in);
+                    for (int u = 0; u < kProposeU; ++u) {
+                        const i32 m = mm[u];
+                        if ((int)(m != n) & (int)(m >= lo) & (int)(m < hi)) atomicAdd(&bins[m - lo], ad[u]);
                     }
                 }
+                wave_sync();  // the table is rewritten by the next batch
             }
             __syncthreads();
             const int used = hi - lo;
@@ -685,7 +722,8 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
     const int rmax = 65536 / (int)sizeof(BIN);
     const int R = (int)std::min<i64>(rmax, std::max<i64>(64, L.N));
     const size_t lds = sizeof(BIN) * (size_t)R;
-    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 1024))));
+    const size_t lds_all = lds + sizeof(SegTable<BIN>) + 256;
+    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / lds_all)));
     const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu * 2);
     const int npass = (int)ceil_div(L.N, R);
     i32* bnd = nullptr;
@@ -696,7 +734,7 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
     }
 #define HGP_PROP(PIV)                                                                                              \
     case PIV:                                                                                                      \
-        LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(), L.inc(),     \
+        LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, kProposeWaves * kWave, lds, L.N, L.inc_off(), L.inc_nin(), L.inc(),     \
                L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib,     \
                cand, score, R, bnd);                                                                               \
         break;
