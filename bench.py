@@ -23,6 +23,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# The proposal kernel's histogram updates are 32-bit integer adds executed by
+# the LDS: at most one per bank per clock, 32 banks per CU, 256 CUs at 2.4 GHz.
+LDS_UPDATE_PEAK_GOPS = 256 * 32 * 2.4
+
+# Measured HBM traffic of k_propose per launch on the bench workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by what the counters read
+# for a plain 256 MiB copy), valid only for the kernel sources they were taken
+# on (sha256 over the files below); otherwise traffic is reported as null.
+TRAFFIC_SOURCES = ["paper_2605_20497_amd/csrc/k_coarsen.hip", "paper_2605_20497_amd/csrc/dev_util.h",
+                   "paper_2605_20497_amd/csrc/hgp_internal.h"]
+TRAFFIC = {  # {sources_sha256: bytes per k_propose launch}
+    "f21b196745d97b186fcf36500a9628956c76aa6e7e016851e86e556dc5656930": 8871307888,
+}
 
 
 def _args():
@@ -36,6 +49,15 @@ def _args():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def algorithmic_bytes(kernel, levels, pi):
@@ -139,12 +161,29 @@ def main():
     roof = None
     prop = fam.get("propose")
     if prop:
+        # Per launch (one launch per coarsened level): histogram updates
+        # sum_e |e| (|e| - 1) of the level, and the compulsory HBM bytes.
+        launches = prop[0] / args.steps
         t_launch = prop[1] / prop[0] * 1e-9
-        nbytes = algorithmic_bytes("propose", levels.tolist(), part.pi) / (prop[0] / args.steps)
-        ach = nbytes / t_launch / 1e9
-        roof = {"kernel": "propose", "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-                "avg_launch_ms": round(t_launch * 1e3, 4), "algorithmic_bytes_per_launch": int(nbytes)}
+        per_lv = []
+        for lv in range(int(levels.shape[0])):
+            he_off = part.hgp_get_level_graph(lv, what=("he_off",))[0]
+            card = np.diff(he_off).astype(np.int64)
+            per_lv.append(int((card * (card - 1)).sum()))
+        # the last level is proposed on only when the loop stopped there
+        # because it merged nothing
+        updates = sum(per_lv[:int(round(launches))])
+        upd = updates / launches
+        ach = upd / t_launch / 1e9
+        nbytes = algorithmic_bytes("propose", levels.tolist()[:int(round(launches))], part.pi) / launches
+        tr = TRAFFIC.get(sources_sha256())
+        roof = {"kernel": "k_propose", "bound": "alu", "achieved": round(ach, 2), "peak": LDS_UPDATE_PEAK_GOPS,
+                "unit": "Gop/s", "frac": round(ach / LDS_UPDATE_PEAK_GOPS, 5), "traffic": tr,
+                "op": "histogram update (32-bit LDS atomic add)", "ops_per_launch": int(upd),
+                "avg_launch_ms": round(t_launch * 1e3, 4),
+                "hbm_compulsory_bytes_per_launch": int(nbytes),
+                "hbm_compulsory_gbs": round(nbytes / t_launch / 1e9, 2),
+                "hbm_frac": round(nbytes / t_launch / 1e9 / HBM_PEAK_GBS, 5)}
 
     out = {
         "metric": "pins/s per coarsen+refine level & % HBM peak; batched vs plain jobs/s, p50/p99",

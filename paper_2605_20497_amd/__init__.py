@@ -214,13 +214,15 @@ class Partitioner:
         self._chk(lib().hgp_get_proposal(self.h, level, _p(cand), _p(score), _p(match), n))
         return cand, score, match
 
-    def hgp_get_level_graph(self, level):
+    def hgp_get_level_graph(self, level, what=("he_off", "he_nsrc", "pins", "node_w")):
+        """Level `level`'s CSR; arrays not named in `what` are not copied (None)."""
         N, E, P, _ = (int(x) for x in self.hgp_get_levels()[level])
-        he_off = np.zeros(E + 1, np.int64)
-        nsrc = np.zeros(E, np.int32)
-        pins = np.zeros(P, np.int32)
-        nw = np.zeros(N, np.int32)
-        self._chk(lib().hgp_get_level_graph(self.h, level, _p(he_off), _p(nsrc), _p(pins), _p(nw)))
+        he_off = np.zeros(E + 1, np.int64) if "he_off" in what else None
+        nsrc = np.zeros(E, np.int32) if "he_nsrc" in what else None
+        pins = np.zeros(P, np.int32) if "pins" in what else None
+        nw = np.zeros(N, np.int32) if "node_w" in what else None
+        opt = lambda a: _p(a) if a is not None else None
+        self._chk(lib().hgp_get_level_graph(self.h, level, opt(he_off), opt(nsrc), opt(pins), opt(nw)))
         return he_off, nsrc, pins, nw
 
     def hgp_get_partition(self):

@@ -48,6 +48,14 @@ __device__ __forceinline__ T wave_min(T v) {
 }
 
 // Inclusive prefix sum across the wave.
+// Loads of values that other threads update with device atomics (performed in
+// L2): device-scope relaxed loads, so a workgroup that runs several dependent
+// steps never reads an older copy held in its vector L1 cache.
+template <typename T>
+__device__ __forceinline__ T load_l2(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Orders shared-memory writes of one wave before later reads of other lanes of
 // the same wave.
 __device__ __forceinline__ void wave_sync() {

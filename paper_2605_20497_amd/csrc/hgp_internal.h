@@ -64,7 +64,7 @@ struct Level {
     i32 N = 0, E = 0;
     i64 P = 0;
     i64 pairs = 0;
-    Buf b_he_off, b_he_nsrc, b_pins, b_nw, b_inc_off, b_inc_nin, b_inc, b_gamma, b_cand, b_score, b_match;
+    Buf b_he_off, b_he_nsrc, b_pins, b_nw, b_inc_off, b_inc_nin, b_inc, b_inc_pos, b_gamma, b_cand, b_score, b_match;
     i64* he_off() const { return (i64*)b_he_off.p; }
     i32* he_nsrc() const { return (i32*)b_he_nsrc.p; }
     i32* pins() const { return (i32*)b_pins.p; }
@@ -72,6 +72,7 @@ struct Level {
     i64* inc_off() const { return (i64*)b_inc_off.p; }
     i32* inc_nin() const { return (i32*)b_inc_nin.p; }
     i32* inc() const { return (i32*)b_inc.p; }
+    i32* inc_pos() const { return (i32*)b_inc_pos.p; }  // pin position of each incidence entry
     i32* gamma() const { return (i32*)b_gamma.p; }
 };
 

@@ -87,6 +87,11 @@ __global__ void k_noise_cap(unsigned long long* stats) {
 // wave keeps many loads outstanding whatever the h-edge sizes.
 constexpr int kProposeU = 8;
 constexpr int kProposeWaves = 4;
+// Batches whose segments average at least kLongSegment pins are instead swept
+// kProposeG h-edges at a time with kProposeGU loads per h-edge and lane.
+constexpr int kLongSegment = 64;
+constexpr int kProposeG = 4;
+constexpr int kProposeGU = 4;
 
 template <typename BIN>
 struct SegTable {
@@ -159,6 +164,63 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                 const i32 incl = wave_incl_scan(cs + cd);
                 const i32 excl = incl - cs - cd;
                 const i32 T = __shfl(incl, kWave - 1, kWave);
+                const int nb = __popcll(__ballot(valid));
+                if (T >= kLongSegment * nb) {
+                    // Long segments: kProposeG h-edges at a time, kProposeGU
+                    // coalesced loads per h-edge and lane.
+                    for (int i0 = 0; i0 < nb; i0 += kProposeG) {
+                        i64 sb[kProposeG], db[kProposeG];
+                        i32 ss[kProposeG], dl[kProposeG];
+                        BIN sa[kProposeG], sai[kProposeG];
+                        i32 maxs = 0, maxd = 0;
+#pragma unroll
+                        for (int g = 0; g < kProposeG; ++g) {
+                            const int src = min(i0 + g, kWave - 1);
+                            const int on = (int)(i0 + g < nb);
+                            sb[g] = __shfl(e0, src, kWave);
+                            db[g] = __shfl(dlo, src, kWave);
+                            const i32 s1 = __shfl(cs, src, kWave), d1 = __shfl(cd, src, kWave);
+                            ss[g] = on ? s1 : 0;
+                            dl[g] = on ? d1 : 0;
+                            sa[g] = __shfl(add, src, kWave);
+                            sai[g] = __shfl(add_in, src, kWave);
+                            maxs = max(maxs, ss[g]);
+                            maxd = max(maxd, dl[g]);
+                        }
+                        for (i32 q0 = 0; q0 < maxs; q0 += kWave) {  // sources
+                            i32 mm[kProposeG];
+#pragma unroll
+                            for (int g = 0; g < kProposeG; ++g) {
+                                const i32 q = q0 + lane;
+                                mm[g] = q < ss[g] ? pins[sb[g] + q] : n;
+                            }
+#pragma unroll
+                            for (int g = 0; g < kProposeG; ++g) {
+                                const i32 m = mm[g];
+                                if ((int)(m != n) & (int)(m >= lo) & (int)(m < hi)) atomicAdd(&bins[m - lo], sa[g]);
+                            }
+                        }
+                        for (i32 q0 = 0; q0 < maxd; q0 += kProposeGU * kWave) {  // this pass's destinations
+                            i32 mm[kProposeG][kProposeGU];
+#pragma unroll
+                            for (int g = 0; g < kProposeG; ++g)
+#pragma unroll
+                                for (int u = 0; u < kProposeGU; ++u) {
+                                    const i32 q = q0 + u * kWave + lane;
+                                    mm[g][u] = q < dl[g] ? pins[db[g] + q] : n;
+                                }
+#pragma unroll
+                            for (int g = 0; g < kProposeG; ++g)
+#pragma unroll
+                                for (int u = 0; u < kProposeGU; ++u) {
+                                    const i32 m = mm[g][u];
+                                    if ((int)(m != n) & (int)(m >= lo) & (int)(m < hi))
+                                        atomicAdd(&bins[m - lo], sai[g]);
+                                }
+                        }
+                    }
+                    continue;
+                }
                 tab.start[wv][lane] = excl;
                 tab.src_end[wv][lane] = excl + cs;
                 tab.sbase[wv][lane] = e0 - excl;
@@ -477,131 +539,213 @@ __global__ void k_pass_bounds(i32 E, const i64* __restrict__ he_off, const i32* 
 // ---- matching rounds (Sec. V-D) -------------------------------------------
 // Round r's target: the r-th candidate if both ends are still unmatched
 // (t = -2 marks nodes matched in an earlier round, -1 an undefined target).
-__global__ void k_round_targets(i32 N, int Pi, int r, const i32* __restrict__ cand, const u64* __restrict__ score,
-                                const i32* __restrict__ match, i32* t, u64* s) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        if (match[n] >= 0) {
-            t[n] = -2;
-            continue;
-        }
-        const i32 c = cand[n * Pi + r];
-        const i32 mc = match[c >= 0 ? c : 0];  // in bounds either way; used only when c >= 0
-        t[n] = ((int)(c >= 0) & (int)(mc < 0)) ? c : -1;
-        s[n] = score[n * Pi + r];
+__device__ __forceinline__ void round_targets_elem(i64 n, int Pi, int r, const i32* __restrict__ cand,
+                                                   const u64* __restrict__ score, const i32* __restrict__ match,
+                                                   i32* t, u64* s) {
+    if (match[n] >= 0) {
+        t[n] = -2;
+        return;
     }
+    const i32 c = cand[n * Pi + r];
+    const i32 mc = match[c >= 0 ? c : 0];  // in bounds either way; used only when c >= 0
+    t[n] = ((int)(c >= 0) & (int)(mc < 0)) ? c : -1;
+    s[n] = score[n * Pi + r];
 }
 
 // Parent in the pseudo-forest: the target, except inside a two-cycle (the set
 // R of the paper) and for undefined targets, whose nodes are tree roots.
-__global__ void k_round_parent(i32 N, const i32* __restrict__ t, i32* parent, i32* jump, i32* depth, i64* accA,
-                               u64* accBV, i32* accBC) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        accA[n] = 0;
-        accBV[n] = 0;
-        accBC[n] = -1;
-        const i32 tn = t[n];
-        if (tn == -2) {
-            parent[n] = -2;
-            jump[n] = -1;
-            depth[n] = -1;
-            continue;
-        }
-        const i32 tp = t[tn >= 0 ? tn : 0];
-        const i32 p = ((int)(tn >= 0) & (int)(tp == (i32)n)) ? -1 : tn;
-        parent[n] = p;
-        jump[n] = p;
-        depth[n] = p >= 0 ? 1 : 0;
+__device__ __forceinline__ void round_parent_elem(i64 n, const i32* __restrict__ t, i32* parent, i32* jump,
+                                                  i32* depth, i64* accA, u64* accBV, i32* accBC) {
+    accA[n] = 0;
+    accBV[n] = 0;
+    accBC[n] = -1;
+    const i32 tn = t[n];
+    if (tn == -2) {
+        parent[n] = -2;
+        jump[n] = -1;
+        depth[n] = -1;
+        return;
     }
+    const i32 tp = t[tn >= 0 ? tn : 0];
+    const i32 p = ((int)(tn >= 0) & (int)(tp == (i32)n)) ? -1 : tn;
+    parent[n] = p;
+    jump[n] = p;
+    depth[n] = p >= 0 ? 1 : 0;
 }
 
 // Pointer jumping towards the roots: depth = number of hops to the root.
+// Returns 1 while n's pointer has not reached a root.
+__device__ __forceinline__ int jump_elem(i64 n, const i32* __restrict__ jin, const i32* __restrict__ din,
+                                         i32* jout, i32* dout) {
+    const i32 j = jin[n];
+    const i32 jj = j >= 0 ? j : (i32)n;
+    const i32 dj = din[jj], nj = jin[jj];
+    const i32 dn = din[n];
+    dout[n] = j >= 0 ? dn + dj : dn;
+    const i32 nxt = j >= 0 ? nj : j;
+    jout[n] = nxt;
+    return nxt >= 0 ? 1 : 0;
+}
+
+// Bottom-up at depth d: ss0 from the children's sums (Eq. ss0), the return of
+// matching with the parent ss1 - ss0, and the push of both to the parent.
+__device__ __forceinline__ void up_a_elem(i64 n, int d, const i32* __restrict__ depth,
+                                          const i32* __restrict__ parent, const u64* __restrict__ s, i64* accA,
+                                          u64* accBV, const i32* __restrict__ accBC, i64* ss0, i64* ss10) {
+    if (depth[n] != d) return;
+    const i32 bc = load_l2(&accBC[n]);
+    const i64 bvr = dec_i64(load_l2(&accBV[n]));
+    const i64 take = ((int)(bc >= 0) & (int)(bvr > 0)) ? bvr : 0;
+    const i64 v0 = load_l2(&accA[n]) + take;
+    ss0[n] = v0;
+    const i32 p = parent[n];
+    if (p >= 0) {
+        const i64 x = (i64)s[n] - take;
+        ss10[n] = x;
+        atomicAdd((unsigned long long*)&accA[p], (unsigned long long)v0);
+        atomicMax((unsigned long long*)&accBV[p], (unsigned long long)enc_i64(x));
+    }
+}
+
+// Second half of the lexicographic (ss1 - ss0, id) maximum over children.
+__device__ __forceinline__ void up_b_elem(i64 n, int d, const i32* __restrict__ depth,
+                                          const i32* __restrict__ parent, const i64* __restrict__ ss10,
+                                          const u64* __restrict__ accBV, i32* accBC) {
+    if (depth[n] != d) return;
+    const i32 p = parent[n];
+    const u64 bvp = load_l2(&accBV[p >= 0 ? p : 0]);
+    if ((int)(p >= 0) & (int)(enc_i64(ss10[n]) == bvp)) atomicMax(&accBC[p], (i32)n);
+}
+
+// Two-cycle roots (Eq. ss1_roots, Eq. match_root): the pair matches iff
+// ss1 > ss0(n) + ss0(target(n)).
+__device__ __forceinline__ void pairs_elem(i64 n, const i32* __restrict__ t, const u64* __restrict__ s,
+                                           const i64* __restrict__ accA, const i64* __restrict__ ss0, i32* match) {
+    const i32 m = t[n];
+    const i32 tm = t[m >= 0 ? m : 0];
+    if (!((int)(m >= 0) & (int)(tm == (i32)n) & (int)((i32)n < m))) return;
+    const i64 ss1 = (i64)s[n] + load_l2(&accA[n]) + load_l2(&accA[m]);
+    if (ss1 > ss0[n] + ss0[m]) {
+        match[n] = m;
+        match[m] = (i32)n;
+    }
+}
+
+// Top-down at depth d (Eq. match): a node its parent did not take picks its
+// best child when that child's return is positive.
+__device__ __forceinline__ void down_elem(i64 n, int d, const i32* __restrict__ depth,
+                                          const u64* __restrict__ accBV, const i32* __restrict__ accBC,
+                                          i32* match) {
+    const i32 dn = depth[n], mn = match[n];
+    if ((int)(dn != d) | (int)(mn >= 0)) return;
+    const i32 bc = load_l2(&accBC[n]);
+    const i64 bv = dec_i64(load_l2(&accBV[n]));
+    if ((int)(bc >= 0) & (int)(bv > 0)) {
+        match[n] = bc;
+        match[bc] = (i32)n;
+    }
+}
+
+#define HGP_GRID_LOOP(i, n) for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
+
+__global__ void k_round_targets(i32 N, int Pi, int r, const i32* __restrict__ cand, const u64* __restrict__ score,
+                                const i32* __restrict__ match, i32* t, u64* s) {
+    HGP_GRID_LOOP(n, N) round_targets_elem(n, Pi, r, cand, score, match, t, s);
+}
+
+__global__ void k_round_parent(i32 N, const i32* __restrict__ t, i32* parent, i32* jump, i32* depth, i64* accA,
+                               u64* accBV, i32* accBC) {
+    HGP_GRID_LOOP(n, N) round_parent_elem(n, t, parent, jump, depth, accA, accBV, accBC);
+}
+
 // *pending counts nodes whose pointer has not reached a root yet.
 __global__ void k_jump(i32 N, const i32* __restrict__ jin, const i32* __restrict__ din, i32* jout, i32* dout,
                        unsigned long long* pending) {
     unsigned long long c = 0;
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        const i32 j = jin[n];
-        const i32 jj = j >= 0 ? j : (i32)n;
-        const i32 dj = din[jj], nj = jin[jj];
-        const i32 dn = din[n];
-        dout[n] = j >= 0 ? dn + dj : dn;
-        const i32 nxt = j >= 0 ? nj : j;
-        jout[n] = nxt;
-        c += nxt >= 0 ? 1 : 0;
-    }
+    HGP_GRID_LOOP(n, N) c += (unsigned long long)jump_elem(n, jin, din, jout, dout);
     c = wave_sum(c);
     if (lane_id() == 0 && c) atomicAdd(pending, c);
 }
 
 __global__ void k_max_i32(i32 N, const i32* __restrict__ v, unsigned long long* out) {
     i32 m = -1;
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
-        m = max(m, v[n]);
+    HGP_GRID_LOOP(n, N) m = max(m, v[n]);
     m = wave_max(m);
     if (lane_id() == 0 && m >= 0) atomicMax(out, (unsigned long long)m);
 }
 
-// Bottom-up at depth d: ss0 from the children's sums (Eq. ss0), the return of
-// matching with the parent ss1 - ss0, and the push of both to the parent.
 __global__ void k_up_a(i32 N, int d, const i32* __restrict__ depth, const i32* __restrict__ parent,
                        const u64* __restrict__ s, i64* accA, u64* accBV, const i32* __restrict__ accBC, i64* ss0,
                        i64* ss10) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        if (depth[n] != d) continue;
-        const i32 bc = accBC[n];
-        const i64 bvr = dec_i64(accBV[n]);
-        const i64 take = ((int)(bc >= 0) & (int)(bvr > 0)) ? bvr : 0;
-        const i64 v0 = accA[n] + take;
-        ss0[n] = v0;
-        const i32 p = parent[n];
-        if (p >= 0) {
-            const i64 x = (i64)s[n] - take;
-            ss10[n] = x;
-            atomicAdd((unsigned long long*)&accA[p], (unsigned long long)v0);
-            atomicMax((unsigned long long*)&accBV[p], (unsigned long long)enc_i64(x));
-        }
-    }
+    HGP_GRID_LOOP(n, N) up_a_elem(n, d, depth, parent, s, accA, accBV, accBC, ss0, ss10);
 }
 
-// Second half of the lexicographic (ss1 - ss0, id) maximum over children.
 __global__ void k_up_b(i32 N, int d, const i32* __restrict__ depth, const i32* __restrict__ parent,
                        const i64* __restrict__ ss10, const u64* __restrict__ accBV, i32* accBC) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        if (depth[n] != d) continue;
-        const i32 p = parent[n];
-        const u64 bvp = accBV[p >= 0 ? p : 0];
-        if ((int)(p >= 0) & (int)(enc_i64(ss10[n]) == bvp)) atomicMax(&accBC[p], (i32)n);
-    }
+    HGP_GRID_LOOP(n, N) up_b_elem(n, d, depth, parent, ss10, accBV, accBC);
 }
 
-// Two-cycle roots (Eq. ss1_roots, Eq. match_root): the pair matches iff
-// ss1 > ss0(n) + ss0(target(n)).
 __global__ void k_pairs(i32 N, const i32* __restrict__ t, const u64* __restrict__ s, const i64* __restrict__ accA,
                         const i64* __restrict__ ss0, i32* match) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        const i32 m = t[n];
-        const i32 tm = t[m >= 0 ? m : 0];
-        if (!((int)(m >= 0) & (int)(tm == (i32)n) & (int)((i32)n < m))) continue;
-        const i64 ss1 = (i64)s[n] + accA[n] + accA[m];
-        if (ss1 > ss0[n] + ss0[m]) {
-            match[n] = m;
-            match[m] = (i32)n;
-        }
-    }
+    HGP_GRID_LOOP(n, N) pairs_elem(n, t, s, accA, ss0, match);
 }
 
-// Top-down at depth d (Eq. match): a node its parent did not take picks its
-// best child when that child's return is positive.
 __global__ void k_down(i32 N, int d, const i32* __restrict__ depth, const u64* __restrict__ accBV,
                        const i32* __restrict__ accBC, i32* match) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
-        const i32 dn = depth[n], mn = match[n];
-        if ((int)(dn != d) | (int)(mn >= 0)) continue;
-        const i32 bc = accBC[n];
-        const i64 bv = dec_i64(accBV[n]);
-        if ((int)(bc >= 0) & (int)(bv > 0)) {
-            match[n] = bc;
-            match[bc] = (i32)n;
+    HGP_GRID_LOOP(n, N) down_elem(n, d, depth, accBV, accBC, match);
+}
+
+// All Pi matching rounds in one workgroup, for levels where the per-depth
+// launches and host checks would dominate.  Same steps as the kernels above,
+// separated by block barriers; pointer buffers alternate as on the host.
+constexpr int kMatchSingleMax = 16384;
+
+__global__ __launch_bounds__(1024) void k_match_rounds(i32 N, int Pi, int jump_iters, const i32* __restrict__ cand,
+                                                       const u64* __restrict__ score, i32* match, i32* t, u64* s,
+                                                       i32* parent, i32* j0, i32* j1, i32* d0, i32* d1, i64* accA,
+                                                       u64* accBV, i32* accBC, i64* ss0, i64* ss10) {
+    __shared__ unsigned long long red[16];
+    __shared__ i32 redi[16];
+    for (int r = 0; r < Pi; ++r) {
+        for (i64 n = threadIdx.x; n < N; n += blockDim.x) round_targets_elem(n, Pi, r, cand, score, match, t, s);
+        __syncthreads();
+        for (i64 n = threadIdx.x; n < N; n += blockDim.x)
+            round_parent_elem(n, t, parent, j0, d0, accA, accBV, accBC);
+        __syncthreads();
+        i32 *ja = j0, *jb = j1, *da = d0, *db = d1;
+        for (int it = 0; it < jump_iters; ++it) {
+            unsigned long long c = 0;
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x) c += (unsigned long long)jump_elem(n, ja, da, jb, db);
+            c = block_sum(c, red);  // ends with a barrier
+            i32* tp = ja;
+            ja = jb;
+            jb = tp;
+            tp = da;
+            da = db;
+            db = tp;
+            if (c == 0) break;
+        }
+        i32 m = -1;
+        for (i64 n = threadIdx.x; n < N; n += blockDim.x) m = max(m, da[n]);
+        m = wave_max(m);
+        if (lane_id() == 0) redi[wave_id()] = m;
+        __syncthreads();
+        i32 maxd = -1;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) maxd = max(maxd, redi[w]);
+        __syncthreads();
+        const i32* depth = da;
+        for (int d = maxd; d >= 0; --d) {
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x)
+                up_a_elem(n, d, depth, parent, s, accA, accBV, accBC, ss0, ss10);
+            __syncthreads();
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x) up_b_elem(n, d, depth, parent, ss10, accBV, accBC);
+            __syncthreads();
+        }
+        for (i64 n = threadIdx.x; n < N; n += blockDim.x) pairs_elem(n, t, s, accA, ss0, match);
+        __syncthreads();
+        for (int d = 0; d <= maxd; ++d) {
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x) down_elem(n, d, depth, accBV, accBC, match);
+            __syncthreads();
         }
     }
 }
@@ -622,13 +766,16 @@ __global__ void k_iso_keys(i32 N, const i32* __restrict__ flag, const i32* __res
 }
 
 // Nodes sorted by (size, id): the smallest left pairs with the largest that
-// fits both caps, with |in| + |in| standing in for the union.  Serial by
-// nature; one thread.
+// fits both caps, with |in| + |in| standing in for the union.  The walk is
+// serial (each pairing moves both ends), but the search for the largest
+// fitting partner of the current smallest node is done by one wave over 64
+// candidates at a time: the serial walk would step down one candidate per
+// iteration to the same partner.
 __global__ __launch_bounds__(1024) void k_iso_pair(i32 cnt, const i32* __restrict__ order,
                                                    const i32* __restrict__ nw, const i32* __restrict__ nin,
                                                    i64 omega, i64 delta, i32* match, int staged) {
     // With `staged`, the block first gathers sizes and |in| of the sorted nodes
-    // into shared memory so that the serial two-pointer walk reads only LDS.
+    // into shared memory so that the walk reads only LDS.
     extern __shared__ i32 st[];
     i32* sw = st;
     i32* si = st + (staged ? cnt : 0);
@@ -640,20 +787,30 @@ __global__ __launch_bounds__(1024) void k_iso_pair(i32 cnt, const i32* __restric
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
+    if (wave_id() != 0) return;
+    const int lane = lane_id();
     i32 i = 0, j = cnt - 1;
     while (i < j) {
-        const i64 wa = staged ? sw[i] : nw[order[i]], wb = staged ? sw[j] : nw[order[j]];
-        const i64 ia = staged ? si[i] : nin[order[i]], ib = staged ? si[j] : nin[order[j]];
-        if ((int)(wa + wb <= omega) & (int)(ia + ib <= delta)) {
-            const i32 a = order[i], b = order[j];
+        const i64 wa = staged ? sw[i] : nw[order[i]];
+        const i64 ia = staged ? si[i] : nin[order[i]];
+        const i32 jl = j - lane;
+        const i32 q = jl > i ? jl : i;  // in range; lanes at or below i never fit
+        const i64 wb = staged ? sw[q] : nw[order[q]];
+        const i64 ib = staged ? si[q] : nin[order[q]];
+        const int ok = (int)(jl > i) & (int)(wa + wb <= omega) & (int)(ia + ib <= delta);
+        const u64 mask = __ballot(ok);
+        if (mask == 0) {
+            j -= kWave;
+            continue;
+        }
+        const i32 jp = j - (__ffsll((long long)mask) - 1);  // lowest lane: the largest fitting partner
+        if (lane == 0) {
+            const i32 a = order[i], b = order[jp];
             match[a] = b;
             match[b] = a;
-            ++i;
-            --j;
-        } else {
-            --j;
         }
+        ++i;
+        j = jp - 1;
     }
 }
 
@@ -729,7 +886,7 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
     i32* bnd = nullptr;
     if (npass > 1 && L.E > 0) {
         bnd = wsp<i32>(c, WS_BND, (size_t)L.E * (npass + 1));
-        LAUNCH(c, KF_PROPOSE, k_pass_bounds, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, L.he_off(),
+        LAUNCH(c, KF_LEVEL_STATS, k_pass_bounds, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, L.he_off(),
                L.he_nsrc(), L.pins(), R, npass, bnd);
     }
 #define HGP_PROP(PIV)                                                                                              \
@@ -796,7 +953,10 @@ void coarsen_level(Ctx* c, int lv) {
     i64* ss10 = wsp<i64>(c, WS_SS10, N);
     fill_i32(c, match, -1, N);
     const int jump_iters = bits_for((u64)N) + 1;
-    for (int r = 0; r < Pi; ++r) {
+    if (N <= kMatchSingleMax)
+        LAUNCH(c, KF_MATCH, k_match_rounds, 1, 1024, 0, N, Pi, jump_iters, cand, (const u64*)score, match, t, s,
+               parent, j0, j1, d0, d1, accA, accBV, accBC, ss0, ss10);
+    for (int r = 0; r < Pi && N > kMatchSingleMax; ++r) {
         LAUNCH(c, KF_MATCH, k_round_targets, nb, 256, 0, N, Pi, r, cand, score, match, t, s);
         LAUNCH(c, KF_MATCH, k_round_parent, nb, 256, 0, N, t, parent, j0, d0, accA, accBV, accBC);
         i32 *ja = j0, *jb = j1, *da = d0, *db = d1;

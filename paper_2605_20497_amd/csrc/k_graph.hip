@@ -8,7 +8,7 @@ namespace hgp {
 
 namespace {
 
-enum { WS_KEYS = 10, WS_KEYS_OUT = 11, WS_VALS = 12, WS_CNT = 13, WS_EDGE_TMP = 14, WS_CARD = 15, WS_NSRC = 16 };
+enum { WS_KEYS = 10, WS_KEYS_OUT = 11, WS_VALS = 12, WS_PIN_EDGE = 13, WS_EDGE_TMP = 14, WS_CARD = 15, WS_NSRC = 16 };
 
 // Error bits reported by validation.
 enum {
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_validate_nodes(i32 N, const i32* __rest
 // h-edges first and each block ascending (Sec. IV-B).
 __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__ he_off,
                                                   const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
-                                                  u32* keys, i32* vals) {
+                                                  u32* keys, i32* vals, i32* pin_edge) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
@@ -103,9 +103,16 @@ __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__
         for (i64 j = a + lane; j < b; j += kWave) {
             const i32 n = pins[j];
             keys[j] = ((u32)n << 1) | (j < d0 ? 1u : 0u);
-            vals[j] = (i32)e;
+            vals[j] = (i32)j;
+            pin_edge[j] = (i32)e;
         }
     }
+}
+
+// h-edge of every incidence entry from its pin position.
+__global__ void k_inc_edges(i64 P, const i32* __restrict__ inc_pos, const i32* __restrict__ pin_edge, i32* inc) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
+        inc[i] = pin_edge[inc_pos[i]];
 }
 
 // Incidence offsets and inbound counts from the sorted keys: node n's entries
@@ -263,13 +270,21 @@ void build_incidence(Ctx* c, Level& L) {
     u32* keys = wsp<u32>(c, WS_KEYS, P);
     u32* keys_out = wsp<u32>(c, WS_KEYS_OUT, P);
     i32* vals = wsp<i32>(c, WS_VALS, P);
+    i32* pin_edge = wsp<i32>(c, WS_PIN_EDGE, P);
+    if (P > 0x7FFFFFFF) fail(HGP_E_UNSUPPORTED, "more than 2^31 - 1 pins in one level");
     L.b_inc_nin = c->alloc(sizeof(i32) * (size_t)L.N);
     L.b_inc_off = c->alloc(sizeof(i64) * ((size_t)L.N + 1));
     L.b_inc = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
+    L.b_inc_pos = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
     if (L.E > 0)
         LAUNCH(c, KF_TRANSPOSE, k_pin_keys, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(),
-               L.pins(), keys, vals);
-    sort_pairs_u32(c, keys, keys_out, vals, L.inc(), P, bits_for(2ull * (u64)L.N));
+               L.pins(), keys, vals, pin_edge);
+    // Stable sort by (node, source flag): per node its inbound h-edges first,
+    // each group in ascending h-edge order, since pins are stored by h-edge.
+    sort_pairs_u32(c, keys, keys_out, vals, L.inc_pos(), P, bits_for(2ull * (u64)L.N));
+    if (P > 0)
+        LAUNCH(c, KF_TRANSPOSE, k_inc_edges, grid_for(P, 256, c->num_cu * 8), 256, 0, P, (const i32*)L.inc_pos(),
+               (const i32*)pin_edge, L.inc());
     LAUNCH(c, KF_TRANSPOSE, k_inc_offsets, grid_for((i64)L.N + 1, 256, c->num_cu * 8), 256, 0, L.N, P,
            (const u32*)keys_out, L.inc_off(), L.inc_nin());
 }

@@ -66,6 +66,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const Tin* __restrict_
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (Tout)part[gridDim.x];
 }
 
+// Whole scan in one workgroup, for arrays small enough that three launches
+// would cost more than the work.
+constexpr int kScanSingleMax = 1 << 16;
+
+template <typename Tin, typename Tacc, typename Tout>
+__global__ __launch_bounds__(1024) void k_scan_single(const Tin* __restrict__ in, i64 n, Tout* out) {
+    __shared__ Tacc red[16];
+    Tacc carry = 0;
+    for (i64 base0 = 0; base0 < n; base0 += 1024 * kScanItems) {
+        const i64 base = base0 + (i64)threadIdx.x * kScanItems;
+        Tacc v[kScanItems];
+        Tacc s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (base + k < n) ? (Tacc)in[base + k] : 0;
+            s += v[k];
+        }
+        Tacc tot;
+        Tacc run = carry + block_excl_scan(s, red, &tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < n) out[base + k] = (Tout)run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = (Tout)carry;
+}
+
 template <typename T>
 __global__ void k_fill(T* p, T v, i64 n) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
@@ -84,6 +113,10 @@ template <typename Tin, typename Tacc, typename Tout>
 void scan_impl(Ctx* c, const Tin* in, Tout* out, i64 n) {
     if (n <= 0) {
         HIPC(hipMemsetAsync(out, 0, sizeof(Tout), c->stream));
+        return;
+    }
+    if (n <= kScanSingleMax) {
+        LAUNCH(c, KF_SCAN, (k_scan_single<Tin, Tacc, Tout>), 1, 1024, 0, in, n, out);
         return;
     }
     const int nb = (int)ceil_div(n, kScanTile);

@@ -20,7 +20,7 @@ enum {
     WS_LRS = 112, WS_CSTART = 113, WS_SEQN = 114, WS_SEQS = 115, WS_SEQD = 116, WS_POSN = 117, WS_GSEQ = 118,
     WS_EVK = 119, WS_EVK2 = 120, WS_EVI = 121, WS_EVI2 = 122, WS_EVDS = 123, WS_EVDD = 124, WS_ES = 125,
     WS_ED = 126, WS_SEX = 127, WS_DEX = 128, WS_SEGST = 129, WS_DVQ = 130, WS_CEX = 131, WS_VEX = 132,
-    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137
+    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137, WS_CODE = 138
 };
 
 // rstats: [0] active chain rounds flag, [1] links this round, [2] total links,
@@ -95,17 +95,28 @@ __global__ void k_initial_violations(i32 nparts, const i64* __restrict__ psize, 
 // (W_I(n) - conn(n,p)).  Only partitions adjacent through some h-edge can have
 // a positive gain, so only those are visited.  Partition ids are split into
 // ranges of R bins, one pass each.
-__global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __restrict__ inc_off,
-                                               const i32* __restrict__ inc, const i64* __restrict__ he_off,
-                                               const i32* __restrict__ part, const i32* __restrict__ cnt,
-                                               const i32* __restrict__ len, const i32* __restrict__ hw,
-                                               const i32* __restrict__ nw, const i32* __restrict__ rho,
-                                               const i64* __restrict__ psize, i64 omega, i32* move_dst,
-                                               i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R) {
+//
+// Row sweep: each wave owns a batch of up to 64 incident h-edges (metadata one
+// per lane) and walks their pins(p,e) rows kGainsG h-edges at a time, kGainsU
+// coalesced loads per h-edge and lane, so kGainsG * kGainsU loads are in flight.
+// The row of n's own partition is noted during the first pass's sweep (shared
+// memory, one entry per h-edge), and its count, which decides the saving, is
+// read once per h-edge after the batch.
+constexpr int kGainsG = 4;
+constexpr int kGainsU = 4;
+constexpr int kGainsWaves = 4;
+
+__global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
+    i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
+    const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ len,
+    const i32* __restrict__ hw, const i32* __restrict__ nw, const i32* __restrict__ rho,
+    const i64* __restrict__ psize, i64 omega, i32* move_dst, i64* move_gain, i32* move_dst_sa,
+    i64* move_gain_sa, int R) {
     extern __shared__ u32 bins[];  // R bins: one pass covers R consecutive partition ids
     __shared__ i64 red[16];
     __shared__ i64 red_g[16], red_g2[16];
     __shared__ i32 red_p[16], red_p2[16];
+    __shared__ i64 own[kGainsWaves][kWave];  // row of p_s in each h-edge of the batch
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     const int npass = (int)((nparts + R - 1) / R);
     for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
@@ -113,47 +124,72 @@ __global__ __launch_bounds__(256) void k_gains(i32 N, i32 nparts, const i64* __r
     for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
         const i32 ps = rho[n];
         const i64 a = inc_off[n], b = inc_off[n + 1];
+        const i64 deg = b - a;
+        const bool one_batch = deg <= (i64)nwv * kWave;
+        const i64 chunk = one_batch ? (deg + nwv - 1) / nwv : (i64)kWave;
         i64 saving = 0, wi = 0;
         i64 bg = 0, bg2 = 0;  // best move, and best move that keeps size(p) + size(n) <= Omega
         i32 bp = -1, bp2 = -1;
+        i64 r0 = 0;
+        i32 L = 0, w = 0;
         for (int pass = 0; pass < npass; ++pass) {
             const i32 lo = pass * R;
             const i32 hi = min(nparts, lo + R);
-            // Each lane fetches the metadata of one incident h-edge (64 at a time
-            // per wave, so the dependent loads overlap); the wave then sweeps
-            // those rows one by one with coalesced reads of the partition ids.
-            for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
-                const i64 k = kb + lane;
-                const int valid = (int)(k < b);
-                const i32 e = inc[valid ? k : kb];
-                const i64 r0 = he_off[e];
-                const i32 Le = len[e], we = hw[e];
-                const i32 L = valid ? Le : 0;
-                const i32 w = valid ? we : 0;
+            for (i64 kb = a + (i64)wv * chunk; kb < b; kb += (i64)nwv * chunk) {
+                const int nb = (int)min((i64)chunk, b - kb);
+                if ((pass == 0) | !one_batch) {
+                    const i64 k = kb + lane;
+                    const int valid = (int)(lane < nb);
+                    const i32 e = inc[valid ? k : kb];
+                    r0 = he_off[e];
+                    const i32 Le = len[e], we = hw[e];
+                    L = valid ? Le : 0;
+                    w = valid ? we : 0;
+                }
+                if (pass == 0) own[wv][lane] = r0;
+                wave_sync();
+                for (int i0 = 0; i0 < nb; i0 += kGainsG) {
+                    i64 sb[kGainsG];
+                    i32 sl[kGainsG];
+                    u32 sw[kGainsG];
+                    i32 maxl = 0;
+#pragma unroll
+                    for (int g = 0; g < kGainsG; ++g) {
+                        const int src = min(i0 + g, kWave - 1);
+                        sb[g] = __shfl(r0, src, kWave);
+                        const i32 l = __shfl(L, src, kWave);
+                        sl[g] = i0 + g < nb ? l : 0;
+                        sw[g] = (u32)__shfl(w, src, kWave);
+                        maxl = max(maxl, sl[g]);
+                    }
+                    for (i32 q0 = 0; q0 < maxl; q0 += kGainsU * kWave) {
+                        i32 pp[kGainsG][kGainsU];
+#pragma unroll
+                        for (int g = 0; g < kGainsG; ++g)
+#pragma unroll
+                            for (int u = 0; u < kGainsU; ++u) {
+                                const i32 q = q0 + u * kWave + lane;
+                                pp[g][u] = q < sl[g] ? part[sb[g] + q] : -1;
+                            }
+#pragma unroll
+                        for (int g = 0; g < kGainsG; ++g)
+#pragma unroll
+                            for (int u = 0; u < kGainsU; ++u) {
+                                const i32 p = pp[g][u];
+                                if ((int)(p != ps) & (int)(p >= lo) & (int)(p < hi)) atomicAdd(&bins[p - lo], sw[g]);
+                                // every h-edge of n has exactly one row of p_s: one writer per entry
+                                if ((int)(pass == 0) & (int)(p == ps))
+                                    own[wv][i0 + g] = sb[g] + q0 + u * kWave + lane;
+                            }
+                    }
+                }
+                wave_sync();
                 if (pass == 0) {
-                    i32 c_own, ci_own;
-                    row_find(part, cnt, cnt, r0, Le, ps, c_own, ci_own);  // pins(p_s, e), never 0
+                    const i32 c_own = L > 0 ? cnt[own[wv][lane]] : 0;  // pins(p_s, e) >= 1
                     wi += w;
                     saving += (int)(c_own == 1) ? w : 0;
                 }
-                const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
-                for (int i = 0; i < nb; ++i) {
-                    const i64 ri = __shfl(r0, i, kWave);
-                    const i32 Li = __shfl(L, i, kWave);
-                    const u32 wi_ = (u32)__shfl(w, i, kWave);
-                    for (int q0 = 0; q0 < Li; q0 += 4 * kWave) {
-                        i32 pp[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int q = q0 + u * kWave + lane;
-                            pp[u] = q < Li ? part[ri + q] : ps;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if ((int)(pp[u] != ps) & (int)(pp[u] >= lo) & (int)(pp[u] < hi))
-                                atomicAdd(&bins[pp[u] - lo], wi_);
-                    }
-                }
+                wave_sync();  // the table is rewritten by the next batch
             }
             if (pass == 0) {
                 saving = block_sum(saving, red);
@@ -252,25 +288,110 @@ __global__ void k_segments(i32 M, const i32* __restrict__ sps, i32* seg_b, i32* 
 }
 
 // ---- chain rounds (Sec. VI-C) ----------------------------------------------
-__global__ void k_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pred, i32* pl) {
-    if (!rs[0]) return;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x)
-        pl[i] = pred[i] < 0 ? 1 : 0;
+// Per-element steps of one synchronous chain round; the multi-block kernels
+// below and the single-workgroup k_chain_rounds run the same functions.
+__device__ __forceinline__ void predless_elem(i64 i, const i32* __restrict__ pred, i32* pl) {
+    pl[i] = pred[i] < 0 ? 1 : 0;
 }
 
-__global__ void k_compact_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pl,
-                                   const i32* __restrict__ pls, i32* cl, u64* accG, i32* accN) {
-    if (!rs[0]) return;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
-        if (pl[i]) cl[pls[i]] = (i32)i;
-        accG[i] = 0;
-        accN[i] = -1;
-    }
+__device__ __forceinline__ void compact_elem(i64 i, const i32* __restrict__ pl, const i32* __restrict__ pls, i32* cl,
+                                             u64* accG, i32* accN) {
+    if (pl[i]) cl[pls[i]] = (i32)i;
+    accG[i] = 0;
+    accN[i] = -1;
 }
 
 // Every move without a successor grades the first kWindow moves without a
 // predecessor that leave its destination, and proposes the lexicographic max
 // of (grade, node id).  One wave per move.
+__device__ __forceinline__ void propose_wave(i64 i, int lane, const i32* __restrict__ succ,
+                                             const i32* __restrict__ spd, const i32* __restrict__ seg_b,
+                                             const i32* __restrict__ seg_e, const i32* __restrict__ pls,
+                                             const i32* __restrict__ cl, const i64* __restrict__ sg,
+                                             const i32* __restrict__ snw, const i32* __restrict__ snin,
+                                             const i32* __restrict__ snode, i32* prop, i64* propG) {
+    if (succ[i] >= 0) {
+        if (lane == 0) prop[i] = -1;
+        return;
+    }
+    const i32 p = spd[i];
+    const i32 b = seg_b[p], e = seg_e[p];
+    i64 bG = 0;
+    i32 bn = -1, bj = -1;
+    if (b < e) {
+        const i32 w0 = pls[b];
+        const i32 w1 = min(pls[e], w0 + kWindow);
+        const i64 nw_i = snw[i], nin_i = snin[i];
+        for (i32 k = w0 + lane; k < w1; k += kWave) {
+            const i32 j = cl[k];
+            const i64 ds = nw_i - snw[j], dn = nin_i - snin[j];
+            const i64 G = sg[j] * kGradeScale - (10 * (ds < 0 ? -ds : ds) + (dn < 0 ? -dn : dn));
+            const i32 nj = snode[j];
+            const bool t = lex_better(G, nj, bG, bn);
+            bG = t ? G : bG;
+            bn = t ? nj : bn;
+            bj = t ? j : bj;
+        }
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const i64 G2 = __shfl_xor(bG, o, kWave);
+        const i32 n2 = __shfl_xor(bn, o, kWave);
+        const i32 j2 = __shfl_xor(bj, o, kWave);
+        const bool t = lex_better(G2, n2, bG, bn);
+        bG = t ? G2 : bG;
+        bn = t ? n2 : bn;
+        bj = t ? j2 : bj;
+    }
+    if (lane == 0) {
+        prop[i] = bj;
+        propG[i] = bG;
+    }
+}
+
+// A successor accepts the lexicographic max of (grade, proposer node id).
+__device__ __forceinline__ void accept_a_elem(i64 i, const i32* __restrict__ prop, const i64* __restrict__ propG,
+                                              u64* accG) {
+    const i32 j = prop[i];
+    if (j >= 0) atomicMax((unsigned long long*)&accG[j], (unsigned long long)enc_i64(propG[i]));
+}
+
+__device__ __forceinline__ void accept_b_elem(i64 i, const i32* __restrict__ prop, const i64* __restrict__ propG,
+                                              const u64* __restrict__ accG, const i32* __restrict__ snode,
+                                              i32* accN) {
+    const i32 j = prop[i];
+    const u64 aj = load_l2(&accG[j >= 0 ? j : 0]);
+    if ((int)(j >= 0) & (int)(enc_i64(propG[i]) == aj)) atomicMax(&accN[j], snode[i]);
+}
+
+__device__ __forceinline__ int link_elem(i64 i, const i32* __restrict__ prop, const i64* __restrict__ propG,
+                                         const u64* __restrict__ accG, const i32* __restrict__ accN,
+                                         const i32* __restrict__ snode, i32* pred, i32* succ) {
+    const i32 j = prop[i];
+    const i32 jj = j >= 0 ? j : 0;
+    const u64 aj = load_l2(&accG[jj]);
+    const i32 nj = load_l2(&accN[jj]);
+    const int ok = (int)(j >= 0) & (int)(enc_i64(propG[i]) == aj) & (int)(nj == snode[i]);
+    if (ok) {
+        succ[i] = j;
+        pred[j] = (i32)i;
+    }
+    return ok;
+}
+
+#define HGP_GRID_LOOP(i, n) for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
+
+__global__ void k_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pred, i32* pl) {
+    if (!rs[0]) return;
+    HGP_GRID_LOOP(i, M) predless_elem(i, pred, pl);
+}
+
+__global__ void k_compact_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pl,
+                                   const i32* __restrict__ pls, i32* cl, u64* accG, i32* accN) {
+    if (!rs[0]) return;
+    HGP_GRID_LOOP(i, M) compact_elem(i, pl, pls, cl, accG, accN);
+}
+
 __global__ __launch_bounds__(256) void k_chain_propose(i32 M, const unsigned long long* __restrict__ rs,
                                                        const i32* __restrict__ succ, const i32* __restrict__ spd,
                                                        const i32* __restrict__ seg_b, const i32* __restrict__ seg_e,
@@ -279,68 +400,22 @@ __global__ __launch_bounds__(256) void k_chain_propose(i32 M, const unsigned lon
                                                        const i32* __restrict__ snin, const i32* __restrict__ snode,
                                                        i32* prop, i64* propG) {
     if (!rs[0]) return;
-    const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
-    for (i64 i = (i64)blockIdx.x * wpb + wave_id(); i < M; i += (i64)gridDim.x * wpb) {
-        if (succ[i] >= 0) {
-            if (lane == 0) prop[i] = -1;
-            continue;
-        }
-        const i32 p = spd[i];
-        const i32 b = seg_b[p], e = seg_e[p];
-        i64 bG = 0;
-        i32 bn = -1, bj = -1;
-        if (b < e) {
-            const i32 w0 = pls[b];
-            const i32 w1 = min(pls[e], w0 + kWindow);
-            const i64 nw_i = snw[i], nin_i = snin[i];
-            for (i32 k = w0 + lane; k < w1; k += kWave) {
-                const i32 j = cl[k];
-                const i64 ds = nw_i - snw[j], dn = nin_i - snin[j];
-                const i64 G = sg[j] * kGradeScale - (10 * (ds < 0 ? -ds : ds) + (dn < 0 ? -dn : dn));
-                const i32 nj = snode[j];
-                const bool t = lex_better(G, nj, bG, bn);
-                bG = t ? G : bG;
-                bn = t ? nj : bn;
-                bj = t ? j : bj;
-            }
-        }
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) {
-            const i64 G2 = __shfl_xor(bG, o, kWave);
-            const i32 n2 = __shfl_xor(bn, o, kWave);
-            const i32 j2 = __shfl_xor(bj, o, kWave);
-            const bool t = lex_better(G2, n2, bG, bn);
-            bG = t ? G2 : bG;
-            bn = t ? n2 : bn;
-            bj = t ? j2 : bj;
-        }
-        if (lane == 0) {
-            prop[i] = bj;
-            propG[i] = bG;
-        }
-    }
+    for (i64 i = (i64)blockIdx.x * wpb + wave_id(); i < M; i += (i64)gridDim.x * wpb)
+        propose_wave(i, lane_id(), succ, spd, seg_b, seg_e, pls, cl, sg, snw, snin, snode, prop, propG);
 }
 
-// A successor accepts the lexicographic max of (grade, proposer node id).
 __global__ void k_chain_accept_a(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ prop,
                                  const i64* __restrict__ propG, u64* accG) {
     if (!rs[0]) return;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
-        const i32 j = prop[i];
-        if (j >= 0) atomicMax((unsigned long long*)&accG[j], (unsigned long long)enc_i64(propG[i]));
-    }
+    HGP_GRID_LOOP(i, M) accept_a_elem(i, prop, propG, accG);
 }
 
 __global__ void k_chain_accept_b(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ prop,
                                  const i64* __restrict__ propG, const u64* __restrict__ accG,
                                  const i32* __restrict__ snode, i32* accN) {
     if (!rs[0]) return;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
-        const i32 j = prop[i];
-        const u64 aj = accG[j >= 0 ? j : 0];
-        if ((int)(j >= 0) & (int)(enc_i64(propG[i]) == aj)) atomicMax(&accN[j], snode[i]);
-    }
+    HGP_GRID_LOOP(i, M) accept_b_elem(i, prop, propG, accG, snode, accN);
 }
 
 __global__ void k_chain_link(i32 M, unsigned long long* rs, const i32* __restrict__ prop,
@@ -348,17 +423,7 @@ __global__ void k_chain_link(i32 M, unsigned long long* rs, const i32* __restric
                              const i32* __restrict__ accN, const i32* __restrict__ snode, i32* pred, i32* succ) {
     if (!rs[0]) return;
     unsigned long long c = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
-        const i32 j = prop[i];
-        const i32 jj = j >= 0 ? j : 0;
-        const u64 aj = accG[jj];
-        const i32 nj = accN[jj];
-        if ((int)(j >= 0) & (int)(enc_i64(propG[i]) == aj) & (int)(nj == snode[i])) {
-            succ[i] = j;
-            pred[j] = (i32)i;
-            c += 1;
-        }
-    }
+    HGP_GRID_LOOP(i, M) c += (unsigned long long)link_elem(i, prop, propG, accG, accN, snode, pred, succ);
     c = wave_sum(c);
     if (lane_id() == 0 && c) atomicAdd(&rs[1], c);
 }
@@ -372,6 +437,59 @@ __global__ void k_round_end(unsigned long long* rs) {
     rs[1] = 0;
 }
 
+// All chain rounds in one workgroup, for move counts so small that per-round
+// launches and host checks would dominate (beyond a few hundred moves the
+// windowed proposals, one wave per move, need the whole GPU).  Same steps,
+// separated by block barriers; stops after the first round that links
+// nothing, and adds the links to rs[2].
+constexpr int kChainSingleMax = 256;
+
+__global__ __launch_bounds__(1024) void k_chain_rounds(
+    i32 M, unsigned long long* rs, i32* pred, i32* succ, i32* pl, i32* pls, i32* cl, u64* accG, i32* accN,
+    const i32* __restrict__ spd, const i32* __restrict__ seg_b, const i32* __restrict__ seg_e,
+    const i64* __restrict__ sg, const i32* __restrict__ snw, const i32* __restrict__ snin,
+    const i32* __restrict__ snode, i32* prop, i64* propG) {
+    __shared__ i32 red[16];
+    __shared__ unsigned long long red_l[16];
+    const int nwv = blockDim.x / kWave;
+    unsigned long long total = 0;
+    for (int round = 0; round < kChainRounds; ++round) {
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x) predless_elem(i, pred, pl);
+        __syncthreads();
+        // exclusive scan of pl into pls (kScanItems-free: one pass per 1024 entries)
+        i32 carry = 0;
+        for (i64 base = 0; base < M; base += blockDim.x) {
+            const i64 i = base + threadIdx.x;
+            const i32 v = i < M ? pl[i] : 0;
+            i32 tot;
+            const i32 ex = block_excl_scan(v, red, &tot);
+            if (i < M) pls[i] = carry + ex;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) pls[M] = carry;
+        __syncthreads();
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x) compact_elem(i, pl, pls, cl, accG, accN);
+        __syncthreads();
+        for (i64 i = wave_id(); i < M; i += nwv)
+            propose_wave(i, lane_id(), succ, spd, seg_b, seg_e, pls, cl, sg, snw, snin, snode, prop, propG);
+        __syncthreads();
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x) accept_a_elem(i, prop, propG, accG);
+        __syncthreads();
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x) accept_b_elem(i, prop, propG, accG, snode, accN);
+        __syncthreads();
+        unsigned long long c = 0;
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x)
+            c += (unsigned long long)link_elem(i, prop, propG, accG, accN, snode, pred, succ);
+        c = block_sum(c, red_l);  // ends with a barrier
+        total += c;
+        if (c == 0) break;
+    }
+    if (threadIdx.x == 0) {
+        rs[2] += total;
+        rs[0] = 0;
+    }
+}
+
 // ---- chain extraction and ranking (Sec. VI-C) -------------------------------
 __global__ void k_cyc_init(i32 M, const i32* __restrict__ succ, const i32* __restrict__ snode, i32* J, i32* MN) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
@@ -382,16 +500,36 @@ __global__ void k_cyc_init(i32 M, const i32* __restrict__ succ, const i32* __res
 
 // Pointer doubling along successors: after enough steps a node on a cycle
 // still points somewhere and holds the smallest node id of its cycle.
+__device__ __forceinline__ void cyc_elem(i64 i, const i32* __restrict__ J, const i32* __restrict__ MN, i32* J2,
+                                         i32* MN2) {
+    const i32 j = J[i];
+    if (j >= 0) {
+        MN2[i] = min(MN[i], MN[j]);
+        J2[i] = J[j];
+    } else {
+        MN2[i] = MN[i];
+        J2[i] = j;
+    }
+}
+
 __global__ void k_cyc_step(i32 M, const i32* __restrict__ J, const i32* __restrict__ MN, i32* J2, i32* MN2) {
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
-        const i32 j = J[i];
-        if (j >= 0) {
-            MN2[i] = min(MN[i], MN[j]);
-            J2[i] = J[j];
-        } else {
-            MN2[i] = MN[i];
-            J2[i] = j;
-        }
+    HGP_GRID_LOOP(i, M) cyc_elem(i, J, MN, J2, MN2);
+}
+
+// K doubling steps in one workgroup (small M); buffers alternate as in K
+// launches of k_cyc_step, so the result lands where the host expects it.
+constexpr int kJumpSingleMax = 16384;
+
+__global__ __launch_bounds__(1024) void k_cyc_steps(i32 M, int K, i32* J, i32* MN, i32* J2, i32* MN2) {
+    for (int it = 0; it < K; ++it) {
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x) cyc_elem(i, J, MN, J2, MN2);
+        __syncthreads();
+        i32* t = J;
+        J = J2;
+        J2 = t;
+        t = MN;
+        MN = MN2;
+        MN2 = t;
     }
 }
 
@@ -413,19 +551,39 @@ __global__ void k_heads(i32 M, const i32* __restrict__ J, const i32* __restrict_
 }
 
 // List ranking: distance to the chain head and the head itself.
+__device__ __forceinline__ void rank_elem(i64 i, const i32* __restrict__ P, const i32* __restrict__ R,
+                                          const i32* __restrict__ H, i32* P2, i32* R2, i32* H2) {
+    const i32 p = P[i];
+    if (p >= 0) {
+        R2[i] = R[i] + R[p];
+        H2[i] = H[p];
+        P2[i] = P[p];
+    } else {
+        R2[i] = R[i];
+        H2[i] = H[i];
+        P2[i] = p;
+    }
+}
+
 __global__ void k_rank_step(i32 M, const i32* __restrict__ P, const i32* __restrict__ R, const i32* __restrict__ H,
                             i32* P2, i32* R2, i32* H2) {
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (i64)gridDim.x * blockDim.x) {
-        const i32 p = P[i];
-        if (p >= 0) {
-            R2[i] = R[i] + R[p];
-            H2[i] = H[p];
-            P2[i] = P[p];
-        } else {
-            R2[i] = R[i];
-            H2[i] = H[i];
-            P2[i] = p;
-        }
+    HGP_GRID_LOOP(i, M) rank_elem(i, P, R, H, P2, R2, H2);
+}
+
+__global__ __launch_bounds__(1024) void k_rank_steps(i32 M, int K, i32* P, i32* R, i32* H, i32* P2, i32* R2,
+                                                     i32* H2) {
+    for (int it = 0; it < K; ++it) {
+        for (i64 i = threadIdx.x; i < M; i += blockDim.x) rank_elem(i, P, R, H, P2, R2, H2);
+        __syncthreads();
+        i32* t = P;
+        P = P2;
+        P2 = t;
+        t = R;
+        R = R2;
+        R2 = t;
+        t = H;
+        H = H2;
+        H2 = t;
     }
 }
 
@@ -483,80 +641,139 @@ __global__ void k_positions(i32 M, const i32* __restrict__ H, const i32* __restr
 }
 
 
-// In-sequence gains and D changes, one wave per h-edge (Sec. VI-C, VI-D).
-// For a mover n at sequence position q, h-edge e contributes to n's exact
-// connectivity change omega(e)([c_s = 1] - [c_d = 0]), where c_s and c_d are
-// the pin counts of e in p_s(n) and p_d(n) just before n moves (the cases of
-// Eq. in_sequence_gain), and, when n is a destination of e, the transitions of
-// pins_in(p,e) through zero that change D(p_s) and D(p_d).  Only movers among
-// e's own pins alter those counts, so the wave streams e's pins once, gathers
-// its movers in shared memory, and each mover adds up the effect of the earlier
-// ones.  Contributions reach per-mover accumulators through integer atomics
-// (order-independent).
+// In-sequence gains (Sec. VI-C), h-edge side.  One wave per h-edge: the
+// h-edge's pins(p,e) rows are staged in shared memory and its movers gathered
+// with their sequence positions.  For each mover, the counts of its source and
+// destination parts in e just before it moves are the row counts plus the
+// moves of e's earlier movers into and out of those parts.  From them follow
+// the mover's gain on e, w(e) * ([pins(p_s) = 1] - [pins(p_d) = 0]), and (for a
+// destination pin) whether p_s loses e from its inbound set and p_d gains it.
+// The outcome is one byte at the mover's pin slot:
+//   bit 0: pins(p_s, e) = 1,  bit 1: pins(p_d, e) = 0,
+//   bit 2: p_s loses e from D, bit 3: p_d gains e in D.
+// The per-mover sums run in k_inseq_movers, so no atomics are needed.
+struct MoverRec {
+    i32 q, ps, pd, slot;  // slot = (pin offset in e) << 1 | destination flag
+};
+
+__device__ __forceinline__ i32 lds_row(const i32* __restrict__ rp, const u32* __restrict__ rc, i32 L, i32 p,
+                                       i32& ci) {
+    i32 lo = 0, hi = L;
+    while (lo < hi) {
+        const i32 mid = (lo + hi) >> 1;
+        const int lt = (int)(rp[mid] < p);
+        lo = lt ? mid + 1 : lo;
+        hi = lt ? hi : mid;
+    }
+    const i32 at = lo < L ? lo : L - 1;
+    const int hit = (int)(lo < L) & (int)(rp[at] == p);
+    const u32 v = rc[at];
+    ci = hit ? (i32)(v >> 16) : 0;
+    return hit ? (i32)(v & 0xFFFFu) : 0;
+}
+
 __global__ __launch_bounds__(64) void k_inseq_edges(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
-    const i32* __restrict__ hw, const i32* __restrict__ posn, const i32* __restrict__ rho,
-    const i32* __restrict__ move_dst, const i32* __restrict__ part, const i32* __restrict__ cnt,
-    const i32* __restrict__ cin, const i32* __restrict__ len, unsigned long long* gseq, i32* dds, i32* ddd,
-    int cap) {
-    extern __shared__ i32 sm[];  // 4 x cap entries; cap = the largest h-edge, so every mover of e fits
-    i32* lq = sm;
-    i32* lps = sm + cap;
-    i32* lpd = sm + 2 * cap;
-    i32* ldst = sm + 3 * cap;
+    const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
+    const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
+    const i32* __restrict__ len, unsigned char* code, int cap) {
+    // shared memory: cap movers, then cap row parts and cap packed row counts
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    MoverRec* mv = (MoverRec*)smem_raw;
+    i32* rp = (i32*)(mv + cap);
+    u32* rc = (u32*)(rp + cap);
     const int lane = threadIdx.x;
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
         const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
+        const i32 L = len[e];
+        for (i32 r = lane; r < L; r += kWave) {
+            rp[r] = part[a + r];
+            rc[r] = (u32)cnt[a + r] | ((u32)cin[a + r] << 16);  // both <= |e| <= 4096
+        }
         int k = 0;
         for (i64 base = a; base < b; base += kWave) {
             const i64 j = base + lane;
             const int inb = (int)(j < b);
             const i32 m = pins[inb ? j : a];
             const i32 q = posn[m];
-            const int mv = inb & (int)(q < M);
-            const u64 mask = __ballot(mv);
-            if (mv) {
-                const int at = k + __popcll(mask & lt_mask);
-                lq[at] = q;
-                lps[at] = rho[m];
-                lpd[at] = move_dst[m];
-                ldst[at] = (int)(j >= d0);
+            const int is_mv = inb & (int)(q < M);
+            const u64 mask = __ballot(is_mv);
+            if (is_mv) {
+                MoverRec r;
+                r.q = q;
+                r.ps = rho[m];
+                r.pd = move_dst[m];
+                r.slot = (i32)((j - a) << 1) | (i32)(j >= d0);
+                mv[k + __popcll(mask & lt_mask)] = r;
             }
             k += __popcll(mask);
         }
         __syncthreads();
-        if (k > 0) {
-            const i64 w = hw[e];
-            const i32 L = len[e];
-            for (int i = lane; i < k; i += kWave) {
-                const i32 qi = lq[i], psi = lps[i], pdi = lpd[i], di = ldst[i];
-                i32 xs = 0, xd = 0, xis = 0, xid = 0;
-                for (int jj = 0; jj < k; ++jj) {
-                    const i32 qj = lq[jj], psj = lps[jj], pdj = lpd[jj], dj = ldst[jj];
-                    const i32 before = (i32)(qj < qi);
-                    const i32 es = before * ((i32)(pdj == psi) - (i32)(psj == psi));
-                    const i32 ed = before * ((i32)(pdj == pdi) - (i32)(psj == pdi));
-                    xs += es;
-                    xd += ed;
-                    xis += dj * es;
-                    xid += dj * ed;
-                }
-                i32 cs, cis, cd, cid;
-                row_find(part, cnt, cin, a, L, psi, cs, cis);
-                row_find(part, cnt, cin, a, L, pdi, cd, cid);
-                cs += xs;
-                cd += xd;
-                cis += xis;
-                cid += xid;
-                const i64 g = w * ((i64)(cs == 1) - (i64)(cd == 0));
-                if (g != 0) atomicAdd(&gseq[qi], (unsigned long long)g);
-                const i32 ls = di * (i32)(cis == 1), gd = di * (i32)(cid == 0);
-                if (ls) atomicSub(&dds[qi], ls);
-                if (gd) atomicAdd(&ddd[qi], gd);
+        for (int i = lane; i < k; i += kWave) {
+            const MoverRec me = mv[i];
+            i32 xs = 0, xd = 0, xis = 0, xid = 0;
+            for (int jj = 0; jj < k; ++jj) {
+                const MoverRec o = mv[jj];
+                const i32 before = (i32)(o.q < me.q);
+                const i32 dj = o.slot & 1;
+                const i32 es = before * ((i32)(o.pd == me.ps) - (i32)(o.ps == me.ps));
+                const i32 ed = before * ((i32)(o.pd == me.pd) - (i32)(o.ps == me.pd));
+                xs += es;
+                xd += ed;
+                xis += dj * es;
+                xid += dj * ed;
             }
+            i32 cis, cid;
+            const i32 cs = lds_row(rp, rc, L, me.ps, cis) + xs;
+            const i32 cd = lds_row(rp, rc, L, me.pd, cid) + xd;
+            const i32 di = me.slot & 1;
+            const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis + xis == 1)) << 2) |
+                             ((u32)(di & (int)(cid + xid == 0)) << 3);
+            code[a + (me.slot >> 1)] = (unsigned char)bits;
         }
         __syncthreads();
+    }
+}
+
+// In-sequence gains, mover side: one wave per sequence position q sums the
+// outcome bytes over the mover's incidence list.
+__global__ __launch_bounds__(256) void k_inseq_movers(i32 M, const i32* __restrict__ seqn,
+                                                      const i64* __restrict__ inc_off, const i32* __restrict__ inc,
+                                                      const i32* __restrict__ inc_pos, const i32* __restrict__ hw,
+                                                      const unsigned char* __restrict__ code, i64* gseq, i32* dds,
+                                                      i32* ddd) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 q = (i64)blockIdx.x * wpb + wave_id(); q < M; q += (i64)gridDim.x * wpb) {
+        const i32 n = seqn[q];
+        const i64 s = inc_off[n], t = inc_off[n + 1];
+        i64 g = 0;
+        i32 ls = 0, gd = 0;
+        for (i64 i0 = s; i0 < t; i0 += 4 * kWave) {
+            i32 cc[4], ww[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const i64 i = i0 + u * kWave + lane;
+                const int in = (int)(i < t);
+                cc[u] = in ? (i32)code[inc_pos[i]] : 0;
+                ww[u] = in ? hw[inc[i]] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                g += (i64)ww[u] * (i64)((cc[u] & 1) - ((cc[u] >> 1) & 1));
+                ls += (cc[u] >> 2) & 1;
+                gd += (cc[u] >> 3) & 1;
+            }
+        }
+        g = wave_sum(g);
+        ls = wave_sum(ls);
+        gd = wave_sum(gd);
+        if (lane == 0) {
+            gseq[q] = g;
+            dds[q] = -ls;
+            ddd[q] = gd;
+        }
     }
 }
 
@@ -768,8 +985,9 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     if (!reuse) {
         const int R = (int)std::min<i64>(16384, std::max<i64>(64, nparts));
         const size_t lds = sizeof(u32) * (size_t)R;
-        const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 1024))));
-        LAUNCH(c, KF_GAINS, k_gains, std::min<i64>(N, (i64)c->num_cu * per_cu * 2), 256, lds, N, nparts, L.inc_off(),
+        const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 3 * 1024))));
+        LAUNCH(c, KF_GAINS, k_gains, std::min<i64>(N, (i64)c->num_cu * per_cu * 2), kGainsWaves * kWave, lds, N,
+               nparts, L.inc_off(),
                L.inc(), L.he_off(), f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, mdst_any,
                mgain_any, mdst_sa, mgain_sa, R);
     }
@@ -825,7 +1043,10 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     fill_i32(c, succ, -1, M);
     LAUNCH(c, KF_CHAINS, k_set_flag, 1, 1, 0, rs);
     const int wblocks = grid_for(M, 4, c->num_cu * 16);
-    for (int round = 0; round < kChainRounds; ++round) {
+    if (M <= kChainSingleMax)
+        LAUNCH(c, KF_CHAINS, k_chain_rounds, 1, 1024, 0, (i32)M, rs, pred, succ, pl, pls, cl, accG, accN, spd, segb,
+               sege, sg, snw, snin, snode, prop, propG);
+    for (int round = 0; round < kChainRounds && M > kChainSingleMax; ++round) {
         LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
         scan_excl_i32(c, pl, pls, M);
         LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
@@ -848,8 +1069,10 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i32 *J0 = wsp<i32>(c, WS_J0, M), *J1 = wsp<i32>(c, WS_J1, M);
     i32 *MN0 = wsp<i32>(c, WS_MN0, M), *MN1 = wsp<i32>(c, WS_MN1, M);
     LAUNCH(c, KF_RANK, k_cyc_init, nbM, 256, 0, (i32)M, succ, snode, J0, MN0);
+    if (M <= kJumpSingleMax)
+        LAUNCH(c, KF_RANK, k_cyc_steps, 1, 1024, 0, (i32)M, K, J0, MN0, J1, MN1);
     for (int it = 0; it < K; ++it) {
-        LAUNCH(c, KF_RANK, k_cyc_step, nbM, 256, 0, (i32)M, J0, MN0, J1, MN1);
+        if (M > kJumpSingleMax) LAUNCH(c, KF_RANK, k_cyc_step, nbM, 256, 0, (i32)M, J0, MN0, J1, MN1);
         std::swap(J0, J1);
         std::swap(MN0, MN1);
     }
@@ -858,8 +1081,10 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i32 *H0 = wsp<i32>(c, WS_H0, M), *H1 = wsp<i32>(c, WS_H1, M);
     i32* head = wsp<i32>(c, WS_HEAD, M);
     LAUNCH(c, KF_RANK, k_heads, nbM, 256, 0, (i32)M, J0, MN0, pred, snode, P0, R0, H0, head);
+    if (M <= kJumpSingleMax)
+        LAUNCH(c, KF_RANK, k_rank_steps, 1, 1024, 0, (i32)M, K, P0, R0, H0, P1, R1, H1);
     for (int it = 0; it < K; ++it) {
-        LAUNCH(c, KF_RANK, k_rank_step, nbM, 256, 0, (i32)M, P0, R0, H0, P1, R1, H1);
+        if (M > kJumpSingleMax) LAUNCH(c, KF_RANK, k_rank_step, nbM, 256, 0, (i32)M, P0, R0, H0, P1, R1, H1);
         std::swap(P0, P1);
         std::swap(R0, R1);
         std::swap(H0, H1);
@@ -906,15 +1131,15 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i64* evdd = wsp<i64>(c, WS_EVDD, M2);
     i32* dds = wsp<i32>(c, WS_DDS, M);
     i32* ddd = wsp<i32>(c, WS_DDD, M);
-    HIPC(hipMemsetAsync(gseq, 0, sizeof(i64) * M, c->stream));
-    HIPC(hipMemsetAsync(dds, 0, sizeof(i32) * M, c->stream));
-    HIPC(hipMemsetAsync(ddd, 0, sizeof(i32) * M, c->stream));
+    unsigned char* code = wsp<unsigned char>(c, WS_CODE, (size_t)(L.P > 0 ? L.P : 1));
     if (L.E > 0) {
-        const int cap = c->max_card;
-        LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, sizeof(i32) * 4 * cap,
-               L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), c->hw(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len,
-               (unsigned long long*)gseq, dds, ddd, cap);
+        const int cap = std::max(1, c->max_card);
+        LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave,
+               (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho,
+               mdst, f.part, f.cnt, f.cin, f.len, code, cap);
     }
+    LAUNCH(c, KF_INSEQ, k_inseq_movers, grid_for(M, 4, c->num_cu * 16), 256, 0, (i32)M, seqn, L.inc_off(), L.inc(),
+           L.inc_pos(), c->hw(), code, gseq, dds, ddd);
     LAUNCH(c, KF_EVENTS, k_events_build, nbM, 256, 0, (i32)M, seqn, seqs, seqd, L.nw(), dds, ddd, evk, evds, evdd);
     iota_i32(c, evi, M2);
     sort_pairs_u32(c, evk, evk2, evi, evi2, M2, bits_for((u64)nparts));
