@@ -125,7 +125,10 @@ class Graph:
 
     def __del__(self):
         if getattr(self, "_own", False) and getattr(self, "h", None):
-            lib().hgpo_graph_free(self.h)
+            try:
+                lib().hgpo_graph_free(self.h)
+            except Exception:  # interpreter teardown: the library may already be gone
+                pass
             self.h = None
 
     # -- structure ---------------------------------------------------------

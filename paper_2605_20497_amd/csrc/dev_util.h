@@ -56,6 +56,25 @@ __device__ __forceinline__ T load_l2(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Value of lane `src` (wave-uniform) broadcast through scalar registers: unlike
+// __shfl, no LDS permute traffic.
+__device__ __forceinline__ int bcast(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ unsigned bcast(unsigned v, int src) {
+    return (unsigned)__builtin_amdgcn_readlane((int)v, src);
+}
+__device__ __forceinline__ long long bcast(long long v, int src) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)v >> 32), src);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ long bcast(long v, int src) { return (long)bcast((long long)v, src); }
+__device__ __forceinline__ unsigned long long bcast(unsigned long long v, int src) {
+    return (unsigned long long)bcast((long long)v, src);
+}
+__device__ __forceinline__ unsigned long bcast(unsigned long v, int src) {
+    return (unsigned long)bcast((long long)v, src);
+}
+
 // Orders shared-memory writes of one wave before later reads of other lanes of
 // the same wave.
 __device__ __forceinline__ void wave_sync() {
@@ -160,13 +179,40 @@ __device__ __forceinline__ u64 splitmix_mix(u64 z) {
     return z ^ (z >> 31);
 }
 
+// Remainder by an invariant 64-bit divisor d >= 1 with one multiply-high
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Fig. 4.1): with l = ceil(log2 d) and
+// m = floor(2^64 (2^l - d) / d) + 1, q = (t + ((n - t) >> min(l,1))) >> max(l-1,0)
+// where t = mulhi(m, n), is floor(n / d) for every 64-bit n.
+struct DivU64 {
+    u64 d, m;
+    u32 sh1, sh2;
+};
+
+__device__ __forceinline__ DivU64 divu64_make(u64 d) {
+    u32 l = 0;
+    while (l < 64 && (1ull << l) < d) ++l;  // ceil(log2 d)
+    DivU64 r;
+    r.d = d;
+    const unsigned __int128 two_l = (unsigned __int128)1 << l;
+    r.m = (u64)((((unsigned __int128)(two_l - d)) << 64) / d) + 1;
+    r.sh1 = l < 1 ? l : 1;
+    r.sh2 = l > 0 ? l - 1 : 0;
+    return r;
+}
+
+__device__ __forceinline__ u64 divu64_rem(u64 n, const DivU64& f) {
+    const u64 t = __umul64hi(f.m, n);
+    const u64 q = (t + ((n - t) >> f.sh1)) >> f.sh2;
+    return n - q * f.d;
+}
+
 // Symmetric histogram noise of Sec. V-C: hash of the unordered pair {a, b}
-// and the seed, reduced into [0, cap].
-__device__ __forceinline__ u64 pair_noise(u64 seed, i32 a, i32 b, u64 cap) {
-    if (cap == 0) return 0;
+// and the seed, reduced into [0, cap]; `f` divides by cap + 1.
+__device__ __forceinline__ u64 pair_noise(u64 seed, i32 a, i32 b, const DivU64& f) {
     const u64 lo = (u64)(u32)(a < b ? a : b);
     const u64 hi = (u64)(u32)(a < b ? b : a);
-    return splitmix_mix(seed ^ splitmix_mix((lo << 32) | hi)) % (cap + 1);
+    return divu64_rem(splitmix_mix(seed ^ splitmix_mix((lo << 32) | hi)), f);
 }
 
 // Normalised h-edge weight omega(e)/|e| in 16-bit fixed point, at least 1.

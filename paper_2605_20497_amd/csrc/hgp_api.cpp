@@ -94,7 +94,7 @@ void Ctx::release(Buf& b) {
 }
 
 void Ctx::free_level(Level& L) {
-    for (Buf* b : {&L.b_he_off, &L.b_he_nsrc, &L.b_pins, &L.b_nw, &L.b_inc_off, &L.b_inc_nin, &L.b_inc, &L.b_inc_pos, &L.b_gamma,
+    for (Buf* b : {&L.b_he_off, &L.b_he_nsrc, &L.b_pins, &L.b_nw, &L.b_inc_off, &L.b_inc_nin, &L.b_inc, &L.b_inc_pos, &L.b_pins16, &L.b_gamma,
                    &L.b_cand, &L.b_score, &L.b_match})
         release(*b);
 }

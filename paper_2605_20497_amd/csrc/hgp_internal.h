@@ -65,6 +65,7 @@ struct Level {
     i64 P = 0;
     i64 pairs = 0;
     Buf b_he_off, b_he_nsrc, b_pins, b_nw, b_inc_off, b_inc_nin, b_inc, b_inc_pos, b_gamma, b_cand, b_score, b_match;
+    Buf b_pins16;  // 16-bit copy of pins when N <= 65,536 (read by the proposal), else empty
     i64* he_off() const { return (i64*)b_he_off.p; }
     i32* he_nsrc() const { return (i32*)b_he_nsrc.p; }
     i32* pins() const { return (i32*)b_pins.p; }
@@ -86,6 +87,7 @@ struct Prof {
 };
 
 struct Ctx {
+    i64 max_nbound = 0;  // largest neighbour bound of the level being coarsened
     hgp_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;

@@ -23,24 +23,32 @@ enum {
 __global__ __launch_bounds__(256) void k_node_tsum(i32 N, const i64* __restrict__ inc_off,
                                                    const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
                                                    const i64* __restrict__ he_off, const i32* __restrict__ hw,
-                                                   unsigned long long* stats) {
+                                                   const i32* __restrict__ nw, unsigned long long* stats) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
-    unsigned long long mx = 0, mn = 0;
+    unsigned long long mx = 0, mn = 0, mw = 0, mb = 0;
     for (i64 n = (i64)blockIdx.x * wpb + wave_id(); n < N; n += (i64)gridDim.x * wpb) {
-        u64 s = 0;
+        u64 s = 0, nb = 0;
         for (i64 k = inc_off[n] + lane; k < inc_off[n + 1]; k += kWave) {
             const i32 e = inc[k];
-            s += norm_weight(hw[e], he_off[e + 1] - he_off[e]);
+            const i64 card = he_off[e + 1] - he_off[e];
+            s += norm_weight(hw[e], card);
+            nb += (u64)(card - 1);
         }
         s = wave_sum(s);
+        nb = wave_sum(nb);
         mx = mx > s ? mx : s;
+        mb = mb > nb ? mb : nb;
         const unsigned long long ni = (unsigned long long)inc_nin[n];
         mn = mn > ni ? mn : ni;
+        const unsigned long long wn = (unsigned long long)nw[n];
+        mw = mw > wn ? mw : wn;
     }
     if (lane == 0) {
         atomicMax(&stats[0], mx);
         atomicMax(&stats[1], mn);
+        atomicMax(&stats[11], mw);
+        atomicMax(&stats[12], mb);  // largest neighbour bound sum_{e in I(n)} (|e| - 1)
     }
 }
 
@@ -64,8 +72,23 @@ __global__ __launch_bounds__(256) void k_edge_tsum(i32 E, const i64* __restrict_
 }
 
 // Noise cap: a tenth of the mean normalised weight of h-edges with >= 2 pins.
+// stats[8..10]: the divide-by-(cap + 1) constants used by the noise.
 __global__ void k_noise_cap(unsigned long long* stats) {
-    stats[4] = stats[3] ? stats[2] / (10ull * stats[3]) : 0ull;
+    const u64 cap = stats[3] ? stats[2] / (10ull * stats[3]) : 0ull;
+    stats[4] = cap;
+    const DivU64 f = divu64_make(cap + 1);
+    stats[8] = f.m;
+    stats[9] = ((u64)f.sh2 << 32) | f.sh1;
+    stats[10] = f.d;
+}
+
+__device__ __forceinline__ DivU64 noise_div(const unsigned long long* stats) {
+    DivU64 f;
+    f.m = stats[8];
+    f.sh1 = (u32)stats[9];
+    f.sh2 = (u32)(stats[9] >> 32);
+    f.d = stats[10];
+    return f;
 }
 
 // Candidate proposal (Sec. V-C): one block per node.  The block sweeps n's
@@ -87,6 +110,7 @@ __global__ void k_noise_cap(unsigned long long* stats) {
 // wave keeps many loads outstanding whatever the h-edge sizes.
 constexpr int kProposeU = 8;
 constexpr int kProposeWaves = 4;
+constexpr int kScanU = 8;  // bins per thread per step of the bin scan
 // Batches whose segments average at least kLongSegment pins are instead swept
 // kProposeG h-edges at a time with kProposeGU loads per h-edge and lane.
 constexpr int kLongSegment = 64;
@@ -103,10 +127,10 @@ struct SegTable {
     BIN add_in[kProposeWaves][kWave];   // per destination pin
 };
 
-template <typename BIN, int PI>
+template <typename BIN, int PI, typename PIN>
 __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
     i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
-    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const PIN* __restrict__ pins,
     const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
     const unsigned long long* __restrict__ stats, int ib, i32* cand, u64* score, int R,
     const i32* __restrict__ bnd) {
@@ -115,7 +139,12 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
     __shared__ SegTable<BIN> tab;
+    // Largest PI-th best score of any thread's list: the block holds PI valid
+    // candidates scoring at least this, so a bin scoring less cannot enter the
+    // block's top PI and is skipped without a validity check.
+    __shared__ unsigned long long s_floor;
     const u64 cap = stats[4];
+    const DivU64 ndiv = noise_div(stats);
     const int npass = (int)((N + R - 1) / R);
     const BIN imask = (((BIN)1) << ib) - 1;
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
@@ -132,6 +161,10 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i32 nin_n = inc_nin[n];
         const i64 nw_n = nw[n];
+        if (threadIdx.x == 0) s_floor = 0;  // read after the sweep's barrier
+        // When even the heaviest and most-connected node fits with n, every
+        // pair (n, m) is valid and the scan needs no per-neighbour loads.
+        const int all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
         // h-edges per wave batch: spread the node's h-edges evenly over the waves.
         const i64 deg = b - a;
         const i64 chunk = deg <= (i64)nwv * kWave ? (deg + nwv - 1) / nwv : (i64)kWave;
@@ -177,13 +210,13 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                         for (int g = 0; g < kProposeG; ++g) {
                             const int src = min(i0 + g, kWave - 1);
                             const int on = (int)(i0 + g < nb);
-                            sb[g] = __shfl(e0, src, kWave);
-                            db[g] = __shfl(dlo, src, kWave);
-                            const i32 s1 = __shfl(cs, src, kWave), d1 = __shfl(cd, src, kWave);
+                            sb[g] = bcast(e0, src);
+                            db[g] = bcast(dlo, src);
+                            const i32 s1 = bcast(cs, src), d1 = bcast(cd, src);
                             ss[g] = on ? s1 : 0;
                             dl[g] = on ? d1 : 0;
-                            sa[g] = __shfl(add, src, kWave);
-                            sai[g] = __shfl(add_in, src, kWave);
+                            sa[g] = bcast(add, src);
+                            sai[g] = bcast(add_in, src);
                             maxs = max(maxs, ss[g]);
                             maxd = max(maxd, dl[g]);
                         }
@@ -192,7 +225,7 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
 #pragma unroll
                             for (int g = 0; g < kProposeG; ++g) {
                                 const i32 q = q0 + lane;
-                                mm[g] = q < ss[g] ? pins[sb[g] + q] : n;
+                                mm[g] = q < ss[g] ? (i32)pins[sb[g] + q] : n;
                             }
 #pragma unroll
                             for (int g = 0; g < kProposeG; ++g) {
@@ -207,7 +240,7 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
 #pragma unroll
                                 for (int u = 0; u < kProposeGU; ++u) {
                                     const i32 q = q0 + u * kWave + lane;
-                                    mm[g][u] = q < dl[g] ? pins[db[g] + q] : n;
+                                    mm[g][u] = q < dl[g] ? (i32)pins[db[g] + q] : n;
                                 }
 #pragma unroll
                             for (int g = 0; g < kProposeG; ++g)
@@ -243,7 +276,7 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                         const int is_src = (int)(j < tab.src_end[wv][cur]);
                         const i64 pos = in ? (is_src ? tab.sbase[wv][cur] : tab.dbase[wv][cur]) + j : 0;
                         ad[u] = is_src ? tab.add[wv][cur] : tab.add_in[wv][cur];
-                        mm[u] = in ? pins[pos] : n;
+                        mm[u] = in ? (i32)pins[pos] : n;
                     }
 #pragma unroll
                     for (int u = 0; u < kProposeU; ++u) {
@@ -254,32 +287,61 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                 wave_sync();  // the table is rewritten by the next batch
             }
             __syncthreads();
+            // Bin scan, kScanU bins per thread at a time: bins that might enter
+            // the thread's list (judged against the list as it stood at the
+            // start of the batch, so possibly more than needed) get their
+            // validity operands loaded together; insertion then keeps the
+            // exact best PI whatever the order.
             const int used = hi - lo;
-            for (int sidx = threadIdx.x; sidx < used; sidx += blockDim.x) {
-                const BIN v = bins[sidx];
-                if (v == 0) continue;
-                bins[sidx] = 0;
-                const i32 m = lo + sidx;
-                const u64 eta = (u64)(v >> ib);
-                const i64 inter = (i64)(v & imask);
+            for (int s0 = threadIdx.x; s0 < used; s0 += kScanU * (int)blockDim.x) {
+                u64 sc[kScanU];
+                i64 itr[kScanU];
+                int pick[kScanU];
                 const bool full = bm[PI - 1] >= 0;
-                if ((int)full & (int)(eta + cap < bs[PI - 1])) continue;
-                const u64 sc = eta + pair_noise(seed, n, m, cap);
-                if ((int)full & (int)!lex_gt(sc, m, bs[PI - 1], bm[PI - 1])) continue;
-                const i64 nw_m = nw[m], nin_m = inc_nin[m];
-                if ((int)(nw_n + nw_m > omega) | (int)((i64)nin_n + nin_m - inter > delta)) continue;
-                u64 cs = sc;
-                i32 cm = m;
+                const u64 b_s = bs[PI - 1];
+                const i32 b_m = bm[PI - 1];
+                const u64 fl = s_floor;
 #pragma unroll
-                for (int r = 0; r < PI; ++r) {
-                    const bool better = lex_better(cs, cm, bs[r], bm[r]);
-                    const u64 ts = bs[r];
-                    const i32 tm = bm[r];
-                    bs[r] = better ? cs : ts;
-                    bm[r] = better ? cm : tm;
-                    cs = better ? ts : cs;
-                    cm = better ? tm : cm;
+                for (int u = 0; u < kScanU; ++u) {
+                    const int sidx = s0 + u * (int)blockDim.x;
+                    const int in = (int)(sidx < used);
+                    const BIN v = in ? bins[sidx] : (BIN)0;
+                    if (v != 0) bins[sidx] = 0;
+                    const u64 eta = (u64)(v >> ib);
+                    itr[u] = (i64)(v & imask);
+                    const int maybe = (int)(v != 0) & !((int)full & (int)(eta + cap < b_s)) & (int)(eta + cap >= fl);
+                    const i32 m = lo + sidx;
+                    sc[u] = maybe ? eta + pair_noise(seed, n, m, ndiv) : 0;
+                    pick[u] = maybe & !((int)full & (int)!lex_gt(sc[u], m, b_s, b_m)) & (int)(sc[u] >= fl);
                 }
+                i64 nwm[kScanU], ninm[kScanU];
+#pragma unroll
+                for (int u = 0; u < kScanU; ++u) {
+                    const int ld = pick[u] & !all_valid;
+                    const i32 m = ld ? lo + s0 + u * (int)blockDim.x : 0;
+                    nwm[u] = ld ? (i64)nw[m] : 0;
+                    ninm[u] = ld ? (i64)inc_nin[m] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kScanU; ++u) {
+                    const int ok = pick[u] & (int)(nw_n + nwm[u] <= omega) &
+                                   (int)((i64)nin_n + ninm[u] - itr[u] <= delta);
+                    if (ok) {  // ok is computed bitwise; the insertion itself is branch-free
+                        u64 cs = sc[u];
+                        i32 cm = lo + s0 + u * (int)blockDim.x;
+#pragma unroll
+                        for (int r = 0; r < PI; ++r) {
+                            const bool better = lex_better(cs, cm, bs[r], bm[r]);
+                            const u64 ts = bs[r];
+                            const i32 tm = bm[r];
+                            bs[r] = better ? cs : ts;
+                            bm[r] = better ? cm : tm;
+                            cs = better ? ts : cs;
+                            cm = better ? tm : cm;
+                        }
+                    }
+                }
+                if ((int)(bm[PI - 1] >= 0) & (int)(bs[PI - 1] > fl)) atomicMax(&s_floor, (unsigned long long)bs[PI - 1]);
             }
             __syncthreads();
         }
@@ -348,6 +410,7 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     __shared__ i32 red_m[16];
     __shared__ u64 red_b[16];
     const u64 cap = stats[4];
+    const DivU64 ndiv = noise_div(stats);
     const BIN imask = (((BIN)1) << ib) - 1;
     const u32 cmask = (u32)C - 1;
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
@@ -371,8 +434,10 @@ __global__ __launch_bounds__(256) void k_propose_hash(
             bound += (u64)(he_off[e + 1] - he_off[e] - 1);
         }
         bound = block_sum(bound, red_b);
-        u64 B = (bound + (u64)(C / 2) - 1) / (u64)(C / 2);
-        if (B == 0) B = 1;
+        // Passes split the neighbours by a hash of their id; any split gives the
+        // same result, so the count is a power of two (a mask, not a division).
+        u64 B = 1;
+        while (B * (u64)(C / 2) < bound) B <<= 1;
         u64 bs[PI];
         i32 bm[PI];
         for (;;) {  // restarts with more passes if a pass overflows the table
@@ -399,7 +464,7 @@ __global__ __launch_bounds__(256) void k_propose_hash(
                         const int sin = __shfl(ein, i, kWave);
                         for (i64 j = s0 + lane; j < s1; j += kWave) {
                             const i32 m = pins[j];
-                            const int mine = (int)(m != n) & (int)((u64)pass_hash((u32)m) % B == pass);
+                            const int mine = (int)(m != n) & (int)(((u64)pass_hash((u32)m) & (B - 1)) == pass);
                             if (!mine) continue;
                             const BIN v = sadd + ((sin & (int)(j >= sd)) ? (BIN)1 : (BIN)0);
                             u32 sl = slot_hash((u32)m) & cmask;
@@ -445,7 +510,7 @@ __global__ __launch_bounds__(256) void k_propose_hash(
                     const i64 inter = (i64)(v & imask);
                     const bool full = bm[PI - 1] >= 0;
                     if ((int)full & (int)(eta + cap < bs[PI - 1])) continue;
-                    const u64 sc = eta + pair_noise(seed, n, m, cap);
+                    const u64 sc = eta + pair_noise(seed, n, m, ndiv);
                     if ((int)full & (int)!lex_gt(sc, m, bs[PI - 1], bm[PI - 1])) continue;
                     const i64 nw_m = nw[m], nin_m = inc_nin[m];
                     if ((int)(nw_n + nw_m > omega) | (int)((i64)nin_n + nin_m - inter > delta)) continue;
@@ -868,8 +933,14 @@ template <typename BIN>
 void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, i32* cand,
                     u64* score) {
     // Dense id-range histogram while the node ids fit in a few passes over
-    // 64 KiB of bins; the hash table beyond.
-    if ((i64)L.N > 4 * (i64)(65536 / (int)sizeof(BIN)) || c->force_hash_propose) {
+    // 64 KiB of bins.  Beyond, the hashed table when every neighbourhood fits
+    // it in a few passes (each pass re-reads all of a node's pins), else dense
+    // passes, which read each destination pin once.
+    const i64 dense_passes = ceil_div((i64)L.N, (i64)(65536 / (int)sizeof(BIN)));
+    i64 hash_passes = 1;
+    while (hash_passes * 2048 < c->max_nbound) hash_passes <<= 1;
+    const bool hashed = dense_passes > 4 && (hash_passes <= std::max<i64>(4, dense_passes / 4) || dense_passes > 256);
+    if (hashed || c->force_hash_propose) {
         launch_propose_hash<BIN>(c, L, Pi, stats, ib, cand, score);
         return;
     }
@@ -889,11 +960,19 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
         LAUNCH(c, KF_LEVEL_STATS, k_pass_bounds, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, L.he_off(),
                L.he_nsrc(), L.pins(), R, npass, bnd);
     }
+    // Ids of at most 65,536 nodes are read from the level's 16-bit pin
+    // mirror: half the bytes per pin visit.
+    const unsigned short* pins16 = (const unsigned short*)L.b_pins16.p;
 #define HGP_PROP(PIV)                                                                                              \
     case PIV:                                                                                                      \
-        LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV>), grid, kProposeWaves * kWave, lds, L.N, L.inc_off(), L.inc_nin(), L.inc(),     \
-               L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib,     \
-               cand, score, R, bnd);                                                                               \
+        if (pins16)                                                                                                \
+            LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV, unsigned short>), grid, kProposeWaves * kWave, lds, L.N,    \
+                   L.inc_off(), L.inc_nin(), L.inc(), L.he_off(), L.he_nsrc(), pins16, c->hw(), L.nw(), c->omega,  \
+                   c->delta, c->opt.seed, stats, ib, cand, score, R, bnd);                                         \
+        else                                                                                                       \
+            LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV, i32>), grid, kProposeWaves * kWave, lds, L.N, L.inc_off(),  \
+                   L.inc_nin(), L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta,   \
+                   c->opt.seed, stats, ib, cand, score, R, bnd);                                                   \
         break;
     switch (Pi) {
         HGP_PROP(1) HGP_PROP(2) HGP_PROP(3) HGP_PROP(4) HGP_PROP(5) HGP_PROP(6) HGP_PROP(7) HGP_PROP(8)
@@ -909,17 +988,18 @@ void coarsen_level(Ctx* c, int lv) {
     const i32 N = L.N;
     const int Pi = c->opt.pi;
     const int nb = grid_for(N, 256, c->num_cu * 8);
-    unsigned long long* stats = wsp<unsigned long long>(c, WS_STATS, 8);
-    HIPC(hipMemsetAsync(stats, 0, 8 * sizeof(u64), c->stream));
+    unsigned long long* stats = wsp<unsigned long long>(c, WS_STATS, 16);
+    HIPC(hipMemsetAsync(stats, 0, 16 * sizeof(u64), c->stream));
     LAUNCH(c, KF_LEVEL_STATS, k_node_tsum, grid_for(N, 4, c->num_cu * 16), 256, 0, N, L.inc_off(), L.inc_nin(),
-           L.inc(), L.he_off(), c->hw(), stats);
+           L.inc(), L.he_off(), c->hw(), L.nw(), stats);
     if (L.E > 0)
         LAUNCH(c, KF_LEVEL_STATS, k_edge_tsum, grid_for(L.E, 256, c->num_cu * 4), 256, 0, L.E, L.he_off(), c->hw(),
                stats);
     LAUNCH(c, KF_LEVEL_STATS, k_noise_cap, 1, 1, 0, stats);
-    i64 st[2];
-    read_back(c, stats, st, 2, 8);
+    i64 st[16];
+    read_back(c, stats, st, 16, 8);
     const u64 max_tsum = (u64)st[0], max_nin = (u64)st[1];
+    c->max_nbound = (i64)st[12];
 
     Level& Lm = c->levels[lv];
     Lm.b_cand = c->alloc(sizeof(i32) * (size_t)N * Pi);

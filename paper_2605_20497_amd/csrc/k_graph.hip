@@ -109,6 +109,11 @@ __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__
     }
 }
 
+__global__ void k_pins16(i64 P, const i32* __restrict__ pins, unsigned short* p16) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
+        p16[i] = (unsigned short)pins[i];
+}
+
 // h-edge of every incidence entry from its pin position.
 __global__ void k_inc_edges(i64 P, const i32* __restrict__ inc_pos, const i32* __restrict__ pin_edge, i32* inc) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
@@ -282,6 +287,11 @@ void build_incidence(Ctx* c, Level& L) {
     // Stable sort by (node, source flag): per node its inbound h-edges first,
     // each group in ascending h-edge order, since pins are stored by h-edge.
     sort_pairs_u32(c, keys, keys_out, vals, L.inc_pos(), P, bits_for(2ull * (u64)L.N));
+    if (L.N <= 65536 && P > 0) {
+        L.b_pins16 = c->alloc(sizeof(unsigned short) * (size_t)P);
+        LAUNCH(c, KF_TRANSPOSE, k_pins16, grid_for(P, 256, c->num_cu * 8), 256, 0, P, (const i32*)L.pins(),
+               (unsigned short*)L.b_pins16.p);
+    }
     if (P > 0)
         LAUNCH(c, KF_TRANSPOSE, k_inc_edges, grid_for(P, 256, c->num_cu * 8), 256, 0, P, (const i32*)L.inc_pos(),
                (const i32*)pin_edge, L.inc());

@@ -20,7 +20,7 @@ enum {
     WS_LRS = 112, WS_CSTART = 113, WS_SEQN = 114, WS_SEQS = 115, WS_SEQD = 116, WS_POSN = 117, WS_GSEQ = 118,
     WS_EVK = 119, WS_EVK2 = 120, WS_EVI = 121, WS_EVI2 = 122, WS_EVDS = 123, WS_EVDD = 124, WS_ES = 125,
     WS_ED = 126, WS_SEX = 127, WS_DEX = 128, WS_SEGST = 129, WS_DVQ = 130, WS_CEX = 131, WS_VEX = 132,
-    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137, WS_CODE = 138
+    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137, WS_CODE = 138, WS_PHI_PART16 = 139
 };
 
 // rstats: [0] active chain rounds flag, [1] links this round, [2] total links,
@@ -106,9 +106,10 @@ constexpr int kGainsG = 4;
 constexpr int kGainsU = 4;
 constexpr int kGainsWaves = 4;
 
+template <typename PART>
 __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
     i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
-    const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ len,
+    const PART* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ len,
     const i32* __restrict__ hw, const i32* __restrict__ nw, const i32* __restrict__ rho,
     const i64* __restrict__ psize, i64 omega, i32* move_dst, i64* move_gain, i32* move_dst_sa,
     i64* move_gain_sa, int R) {
@@ -156,10 +157,10 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
 #pragma unroll
                     for (int g = 0; g < kGainsG; ++g) {
                         const int src = min(i0 + g, kWave - 1);
-                        sb[g] = __shfl(r0, src, kWave);
-                        const i32 l = __shfl(L, src, kWave);
+                        sb[g] = bcast(r0, src);
+                        const i32 l = bcast(L, src);
                         sl[g] = i0 + g < nb ? l : 0;
-                        sw[g] = (u32)__shfl(w, src, kWave);
+                        sw[g] = (u32)bcast(w, src);
                         maxl = max(maxl, sl[g]);
                     }
                     for (i32 q0 = 0; q0 < maxl; q0 += kGainsU * kWave) {
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
 #pragma unroll
                             for (int u = 0; u < kGainsU; ++u) {
                                 const i32 q = q0 + u * kWave + lane;
-                                pp[g][u] = q < sl[g] ? part[sb[g] + q] : -1;
+                                pp[g][u] = q < sl[g] ? (i32)part[sb[g] + q] : -1;
                             }
 #pragma unroll
                         for (int g = 0; g < kGainsG; ++g)
@@ -928,7 +929,13 @@ int bits_for(u64 v) {
 struct PhiBufs {
     i32 *part, *cnt, *cin, *len;
     i64 *psize, *pD;
+    unsigned short* part16;  // 16-bit copy of part when nparts <= 65,536, else null
 };
+
+__global__ void k_narrow16(i64 P, const i32* __restrict__ v, unsigned short* v16) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
+        v16[i] = (unsigned short)v[i];
+}
 
 PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
     PhiBufs f;
@@ -938,6 +945,7 @@ PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
     f.len = wsp<i32>(c, WS_PHI_LEN, (size_t)L.E + 1);
     f.psize = wsp<i64>(c, WS_PSIZE, nparts);
     f.pD = wsp<i64>(c, WS_PD, nparts);
+    f.part16 = nparts <= 65536 ? wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1) : nullptr;
     return f;
 }
 
@@ -950,6 +958,11 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
     f.psize = wsp<i64>(c, WS_PSIZE, nparts);
     f.pD = wsp<i64>(c, WS_PD, nparts);
     build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len);
+    f.part16 = nullptr;
+    if (nparts <= 65536 && L.P > 0) {
+        f.part16 = wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1);
+        LAUNCH(c, KF_PHI, k_narrow16, grid_for(L.P, 256, c->num_cu * 8), 256, 0, L.P, (const i32*)f.part, f.part16);
+    }
     HIPC(hipMemsetAsync(f.psize, 0, sizeof(i64) * nparts, c->stream));
     HIPC(hipMemsetAsync(f.pD, 0, sizeof(i64) * nparts, c->stream));
     LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), f.psize);
@@ -986,10 +999,15 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const int R = (int)std::min<i64>(16384, std::max<i64>(64, nparts));
         const size_t lds = sizeof(u32) * (size_t)R;
         const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 3 * 1024))));
-        LAUNCH(c, KF_GAINS, k_gains, std::min<i64>(N, (i64)c->num_cu * per_cu * 2), kGainsWaves * kWave, lds, N,
-               nparts, L.inc_off(),
-               L.inc(), L.he_off(), f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, mdst_any,
-               mgain_any, mdst_sa, mgain_sa, R);
+        const int grid = (int)std::min<i64>(N, (i64)c->num_cu * per_cu * 2);
+        if (f.part16)  // half the bytes per row visit
+            LAUNCH(c, KF_GAINS, k_gains<unsigned short>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(),
+                   L.inc(), L.he_off(), (const unsigned short*)f.part16, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize,
+                   c->omega, mdst_any, mgain_any, mdst_sa, mgain_sa, R);
+        else
+            LAUNCH(c, KF_GAINS, k_gains<i32>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
+                   L.he_off(), (const i32*)f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, mdst_any,
+                   mgain_any, mdst_sa, mgain_sa, R);
     }
     i32* mdst = size_aware ? mdst_sa : mdst_any;
     i64* mgain = size_aware ? mgain_sa : mgain_any;

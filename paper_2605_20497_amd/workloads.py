@@ -185,9 +185,10 @@ def config3a(seed: int = 0) -> Hypergraph:
 # ---------------------------------------------------------------------------
 
 def conv_snn(layers: int, hw: int, channels: int, mean_fanout: float, seed: int = 0,
-             omega: int = 0, delta: int = 0, name: str = "") -> Hypergraph:
+             omega: int = 0, delta: int = 0, name: str = "", progress=None) -> Hypergraph:
     """Node (l, y, x, c) drives clamp(Poisson(mean), 1, |W|) distinct destinations in
-    layer (l+1) mod layers at |y'-y|<=1, |x'-x|<=1, any channel (|W| <= 9*channels)."""
+    layer (l+1) mod layers at |y'-y|<=1, |x'-x|<=1, any channel (|W| <= 9*channels).
+    `progress(done, total)` is called after each block of rows when given."""
     rng = np.random.default_rng(seed)
     per_layer = hw * hw * channels
     n = layers * per_layer
@@ -231,13 +232,15 @@ def conv_snn(layers: int, hw: int, channels: int, mean_fanout: float, seed: int 
         row_pins[:, 1:] = ids
         m = np.concatenate([np.ones((rows, 1), bool), valid], axis=1)
         pins[he_off[c0]:he_off[c1]] = row_pins[m].astype(np.int32)
+        if progress is not None and (c1 == n or (c1 // chunk) % 32 == 0):
+            progress(c1, n)
     return Hypergraph(n, he_off, np.ones(n, np.int32), pins, np.ones(n, np.int32),
                       np.ones(n, np.int32), omega=omega, delta=delta, name=name)
 
 
-def config3b(seed: int = 0) -> Hypergraph:
+def config3b(seed: int = 0, progress=None) -> Hypergraph:
     """7 layers of 176x176x32 (6,938,624 nodes), Poisson(82) fanout: ~577M pins."""
-    return conv_snn(7, 176, 32, 82.0, seed, omega=1 << 12, delta=1 << 16, name="conv-6.9m")
+    return conv_snn(7, 176, 32, 82.0, seed, omega=1 << 12, delta=1 << 16, name="conv-6.9m", progress=progress)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,114 @@
+"""Full-size runs of the larger workloads on the HIP path (netlist 500k with
+k = 64, layered 256k, conv 6.9M), checked where the oracle can follow:
+
+- the oracle's evaluation of the GPU partition (connectivity, cut nets,
+  largest part size and inbound count, violations) is recomputed from scratch
+  on the CPU and must match the library's, with zero violations;
+- level-0 candidates and scores of a seeded sample of nodes must equal the
+  oracle's proposal for those nodes, computed one by one;
+- the level-0 matching is symmetric, and every matched pair fits Omega and
+  Delta, with |in(n) U in(m)| from the oracle's pair values;
+- the first cluster map numbers clusters by their smallest member and puts
+  exactly the matched pairs together.
+
+Whole-run bit-exact digests for the workloads the oracle can finish are
+compared in test_gpu_golden.py."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_20497_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = 48
+
+
+def _gen(name):
+    t0 = time.time()
+    if name == "conv-6.9m":
+        hg = W.config3b(progress=lambda d, n: print("generated %d/%d rows (%.0f s)" % (d, n, time.time() - t0),
+                                                    flush=True))
+    else:
+        hg = W.CONFIGS[name]()
+    print("case", name, "N", hg.n_nodes, "E", hg.n_hedges, "P", hg.n_pins, flush=True)
+    return hg
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name", ["netlist-500k", "layered-256k-e256", "conv-6.9m"])
+def test_full_size_properties(name):
+    import torch
+    from paper_2605_20497_amd import Partitioner
+    hg = _gen(name)
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(x).to(dev) for x in (hg.he_off, hg.he_nsrc, hg.pins, hg.hedge_w, hg.node_w)]
+    g = Partitioner(pi=4, theta=16, seed=0)
+    g.hgp_load_csr_device(hg.n_nodes, *t)
+    g.hgp_set_limits(hg.omega, hg.delta, hg.k)
+    t1 = time.time()
+    nl = g.hgp_coarsen()
+    print("coarsened", nl, "levels (%.1f s)" % (time.time() - t1), flush=True)
+    t1 = time.time()
+    g.hgp_refine()
+    print("refined (%.1f s)" % (time.time() - t1), flush=True)
+    del t
+    levels = g.hgp_get_levels()
+    rho, nparts = g.hgp_get_partition()
+    ev = g.hgp_evaluate()
+    cand, score, match = g.hgp_get_proposal(0)
+    gamma0 = g.hgp_get_cluster_map(0) if nl > 1 else None
+    g.close()
+
+    # level sizes shrink by exactly the merged pairs
+    for lv in range(nl - 1):
+        assert levels[lv + 1, 0] == levels[lv, 0] - levels[lv, 3]
+        assert levels[lv + 1, 2] <= levels[lv, 2]
+
+    og = oracle.Graph(hg)
+    print("oracle graph built", flush=True)
+    oev = og.evaluate(rho, nparts, hg.omega, hg.delta)
+    for key in ("conn", "cutnet", "max_size", "max_inbound", "violations"):
+        assert ev[key] == oev[key], key
+    assert ev["violations"] == 0
+    if hg.k:
+        assert ev["n_parts"] <= hg.k
+
+    rng = np.random.default_rng(7)
+    nodes = np.sort(rng.choice(hg.n_nodes, size=SAMPLE, replace=False)).astype(np.int32)
+    ocand, oscore = og.propose(hg.omega, hg.delta, seed=0, Pi=4, nodes=nodes)
+    assert np.array_equal(cand[nodes], ocand)
+    assert np.array_equal(score[nodes], oscore)
+    print("sampled proposals match", flush=True)
+
+    idx = np.arange(hg.n_nodes)
+    m = match
+    assert np.all((m == -1) | ((m >= 0) & (m < hg.n_nodes)))
+    paired = np.nonzero(m >= 0)[0]
+    assert np.array_equal(m[m[paired]], paired), "matching not symmetric"
+    assert not np.any(m[paired] == paired)
+    firsts = paired[paired < m[paired]]
+    nin = np.zeros(hg.n_nodes, np.int64)
+    dst_counts = np.diff(hg.he_off) - hg.he_nsrc
+    src_mask = np.zeros(hg.n_pins, bool)
+    starts = hg.he_off[:-1]
+    for s in range(int(hg.he_nsrc.max()) if hg.n_hedges else 0):
+        sel = hg.he_nsrc > s
+        src_mask[starts[sel] + s] = True
+    np.add.at(nin, hg.pins[~src_mask], 1)
+    assert int(nin.sum()) == int(dst_counts.sum())
+    check = firsts if firsts.size <= 4096 else rng.choice(firsts, size=4096, replace=False)
+    for a in check:
+        b = int(m[a])
+        assert int(hg.node_w[a]) + int(hg.node_w[b]) <= hg.omega
+        _, inter = og.pair(int(a), int(b))
+        assert int(nin[a]) + int(nin[b]) - int(inter) <= hg.delta
+    print("matching checked (%d pairs)" % firsts.size, flush=True)
+
+    if gamma0 is not None:
+        rep = np.where(m >= 0, np.minimum(idx, m), idx)
+        reps = np.unique(rep)
+        assert reps.size == levels[1, 0]
+        assert np.array_equal(gamma0, np.searchsorted(reps, rep))
