@@ -48,6 +48,10 @@ def _args():
     ap.add_argument("--cpu-nodes", type=int, default=4096)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain job stream leg")
+    ap.add_argument("--batch-jobs", type=int, default=64)
+    ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--batch-max-nodes", type=int, default=32768)
     return ap.parse_args()
 
 
@@ -89,6 +93,44 @@ def cpu_baseline(args):
     return {"value": hg.n_pins / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
             "sample": "rand-%d-e192 (%d nodes, %d pins, Omega=%d, Delta=4096), full coarsen+refine, %d levels, "
                       "%.1f s on one host core" % (n, n, hg.n_pins, omega, res.nlevels, dt)}
+
+
+def batched_leg(args):
+    """Job stream (the five workload families, log-uniform 2,048 to
+    batch_max_nodes nodes): the plain one-at-a-time rate with every job
+    waiting from the start, then Poisson arrivals at 1.5x that rate served
+    by one worker (plain) and by batch_workers concurrent workers (batched).
+    Latency = arrival to partition on the host."""
+    import numpy as np
+    import paper_2605_20497_amd as pkg
+    from paper_2605_20497_amd import workloads as W
+    jobs, _ = W.job_stream(args.batch_jobs, 2048, args.batch_max_nodes, seed=0)
+    pkg.hgp_run_jobs(jobs[:4], workers=1)  # warm-up
+    closed = pkg.hgp_run_jobs(jobs, workers=1)
+    span = max(r["end_s"] for r in closed)
+    rate = 1.5 * len(jobs) / span
+    arng = np.random.default_rng(12345)
+    arrivals = np.cumsum(arng.exponential(1.0 / rate, size=len(jobs)))
+
+    def summary(res, workers):
+        lat = np.array([r["end_s"] - a for r, a in zip(res, arrivals)])
+        end = max(r["end_s"] for r in res)
+        return {"workers": workers, "jobs_per_s": round(len(res) / (end - arrivals[0]), 2),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)}
+
+    closed_b = pkg.hgp_run_jobs(jobs, workers=args.batch_workers)
+    span_b = max(r["end_s"] for r in closed_b)
+    plain = pkg.hgp_run_jobs(jobs, workers=1, arrivals=arrivals)
+    batched = pkg.hgp_run_jobs(jobs, workers=args.batch_workers, arrivals=arrivals)
+    ok = all(p["status"] == 0 and b["status"] == 0 and np.array_equal(p["rho"], b["rho"])
+             for p, b in zip(plain, batched))
+    return {"jobs": len(jobs), "pins": int(sum(j.n_pins for j in jobs)),
+            "sizes": "2048-%d nodes, random e32/e192, layered, conv, netlist" % args.batch_max_nodes,
+            "plain_closed_jobs_per_s": round(len(jobs) / span, 2),
+            "batched_closed_jobs_per_s": round(len(jobs) / span_b, 2), "arrival_rate_per_s": round(rate, 2),
+            "plain": summary(plain, 1), "batched": summary(batched, args.batch_workers),
+            "bit_exact_vs_plain": bool(ok)}
 
 
 def main():
@@ -200,9 +242,11 @@ def main():
         "kernel_time_share": round(total_ns / args.steps * 1e-9 / dt, 4) if dt > 0 else None,
         "roofline": roof,
     }
+    part.close()
+    if not args.no_batch:
+        out["batched"] = batched_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
-    part.close()
     print(json.dumps(out))
 
 

@@ -203,6 +203,50 @@ hgp_status hgp_reset_kernel_stats(hgp_ctx* ctx);
  * refine ns of level l. */
 hgp_status hgp_level_times(hgp_ctx* ctx, int64_t* out, int64_t cap);
 
+/*
+ * One partitioning job for hgp_run_jobs.  Inputs are host arrays laid out as
+ * for hgp_load_csr (hedge_w / node_w may be NULL for unit weights); the
+ * caller owns them and they must stay valid during the call.  Outputs are
+ * written by the library.
+ */
+typedef struct hgp_job {
+    int32_t n_nodes;
+    int32_t n_hedges;
+    const int64_t* he_off;
+    const int32_t* he_nsrc;
+    const int32_t* pins;
+    const int32_t* hedge_w;
+    const int32_t* node_w;
+    int64_t omega, delta;
+    int32_t k;
+    double arrival_s;     /* seconds after the call starts at which the job may be admitted */
+    int32_t* rho;         /* out (host, n_nodes entries, may be NULL): the partition */
+    int32_t n_parts;      /* out: non-empty partitions */
+    int32_t n_levels;     /* out: hierarchy levels */
+    int64_t conn;         /* out: connectivity of the result (Eq. connectivity) */
+    int64_t violations;   /* out: partitions breaking Omega or Delta */
+    double start_s;       /* out: admission time, seconds after the call starts */
+    double end_s;         /* out: completion time (partition on the host) */
+    int64_t footprint;    /* out: the device-memory estimate used for admission, bytes */
+    hgp_status status;    /* out: HGP_OK, or the error of the job's first failing call */
+} hgp_job;
+
+/*
+ * Runs n_jobs partitioning jobs (Sec. III: coarsening, initial partitioning,
+ * refinement, each job alone) on one GPU with `workers` concurrent contexts,
+ * each on a stream of its own (1 = one job at a time).  Jobs must be sorted by
+ * arrival_s; they are admitted in that order, each when its arrival time has
+ * passed, a worker is free and its footprint estimate fits into hbm_budget
+ * bytes beside the jobs in flight (a job larger than the budget runs alone);
+ * hbm_budget <= 0 uses 60% of the device's free memory.  opt gives the device,
+ * pi, theta, seed and flags; its stream and allocator must be unset (workers
+ * allocate stream-ordered from the device's pool).  Returns HGP_E_INVALID for
+ * bad arguments and the first context-creation error if any; per-job failures
+ * are reported in jobs[i].status.  Results equal those of separate runs.
+ */
+hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_t n_jobs, int32_t workers,
+                        int64_t hbm_budget);
+
 #ifdef __cplusplus
 }
 #endif

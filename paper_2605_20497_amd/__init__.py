@@ -37,6 +37,14 @@ class hgp_eval(C.Structure):
                 ("max_inbound", C.c_int64), ("violations", C.c_int64), ("n_parts", C.c_int64)]
 
 
+class hgp_job(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_hedges", C.c_int32), ("he_off", C.c_void_p), ("he_nsrc", C.c_void_p),
+                ("pins", C.c_void_p), ("hedge_w", C.c_void_p), ("node_w", C.c_void_p), ("omega", C.c_int64),
+                ("delta", C.c_int64), ("k", C.c_int32), ("arrival_s", C.c_double), ("rho", C.c_void_p),
+                ("n_parts", C.c_int32), ("n_levels", C.c_int32), ("conn", C.c_int64), ("violations", C.c_int64),
+                ("start_s", C.c_double), ("end_s", C.c_double), ("footprint", C.c_int64), ("status", C.c_int)]
+
+
 class HgpError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
@@ -82,6 +90,7 @@ def lib():
             "hgp_kernel_stats": (C.c_int, [P, C.POINTER(C.c_char_p), P, P, C.POINTER(i32)]),
             "hgp_reset_kernel_stats": (C.c_int, [P]),
             "hgp_level_times": (C.c_int, [P, P, i64]),
+            "hgp_run_jobs": (C.c_int, [C.POINTER(hgp_options), C.POINTER(hgp_job), i64, i32, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -94,7 +103,46 @@ def lib():
 EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
             "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
             "hgp_get_proposal", "hgp_get_level_graph", "hgp_get_partition", "hgp_get_phi", "hgp_evaluate",
-            "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_level_times"]
+            "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_level_times", "hgp_run_jobs"]
+
+
+def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16, seed=0, device=0, flags=0):
+    """Runs a list of hypergraphs (workloads.Hypergraph, with their omega,
+    delta and k) as jobs on `workers` concurrent contexts; `arrivals` are the
+    seconds after the start at which each may be admitted (sorted; default
+    all 0).  Returns one dict per job: rho, n_parts, n_levels, conn,
+    violations, start_s, end_s, footprint, status."""
+    n = len(graphs)
+    arr = [0.0] * n if arrivals is None else [float(a) for a in arrivals]
+    jobs = (hgp_job * max(n, 1))()
+    keep = []
+    rhos = []
+    for i, hg in enumerate(graphs):
+        cols = [np.ascontiguousarray(hg.he_off, np.int64), np.ascontiguousarray(hg.he_nsrc, np.int32),
+                np.ascontiguousarray(hg.pins, np.int32), np.ascontiguousarray(hg.hedge_w, np.int32),
+                np.ascontiguousarray(hg.node_w, np.int32)]
+        keep.append(cols)
+        rho = np.zeros(hg.n_nodes, np.int32)
+        rhos.append(rho)
+        j = jobs[i]
+        j.n_nodes, j.n_hedges = hg.n_nodes, hg.n_hedges
+        j.he_off, j.he_nsrc, j.pins, j.hedge_w, j.node_w = (c.ctypes.data for c in cols)
+        j.omega, j.delta, j.k = int(hg.omega), int(hg.delta), int(hg.k)
+        j.arrival_s = arr[i]
+        j.rho = rho.ctypes.data
+    opt = hgp_options()
+    lib().hgp_default_options(C.byref(opt))
+    opt.device, opt.pi, opt.theta, opt.seed, opt.flags = device, pi, theta, seed, flags
+    st = lib().hgp_run_jobs(C.byref(opt), jobs, n, int(workers), int(hbm_budget))
+    if st != 0:
+        raise HgpError(st, "hgp_run_jobs failed")
+    out = []
+    for i in range(n):
+        j = jobs[i]
+        out.append({"rho": rhos[i], "n_parts": j.n_parts, "n_levels": j.n_levels, "conn": j.conn,
+                    "violations": j.violations, "start_s": j.start_s, "end_s": j.end_s,
+                    "footprint": j.footprint, "status": j.status})
+    return out
 
 
 def _p(a):
