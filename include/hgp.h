@@ -63,8 +63,11 @@ typedef struct hgp_options {
     uint64_t seed;         /* seed of the symmetric histogram noise (Sec. V-C); default 0 */
     int32_t profile;       /* 1 = time every kernel launch with HIP events (see hgp_kernel_stats) */
     int32_t flags;         /* bit 0: use the sparse (hash-table) candidate proposal at every level;
-                              by default it serves only levels with more than 65,536 nodes */
-    int32_t reserved[6];
+                              by default it serves only levels whose ids need many dense id-range
+                              passes while every neighbourhood fits a few hashed passes */
+    uint32_t profile_families; /* with profile = 1: bit i times only kernel family i (the order of
+                                * hgp_kernel_stats' names); 0 = every family */
+    int32_t reserved[5];
 } hgp_options;
 
 /* Fills `opt` with the defaults above. */

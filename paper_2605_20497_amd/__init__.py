@@ -29,7 +29,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 class hgp_options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", C.c_void_p), ("pi", C.c_int32), ("theta", C.c_int32), ("seed", C.c_uint64),
-                ("profile", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("profile", C.c_int32), ("flags", C.c_int32), ("profile_families", C.c_uint32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class hgp_eval(C.Structure):
@@ -99,6 +100,11 @@ def lib():
         _lib = L
     return _lib
 
+
+# Kernel families in the library's order (hgp_kernel_stats names).
+KERNEL_FAMILIES = ["validate", "transpose", "radix_sort", "scan", "level_stats", "propose", "match", "isolated",
+                   "gamma", "contract_edges", "pack", "phi", "part_stats", "gains", "moves", "chains", "rank",
+                   "inseq", "events", "select", "apply", "project", "eval", "misc"]
 
 EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
             "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
@@ -172,12 +178,14 @@ class Partitioner:
     """One library context on one device and torch stream."""
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
-                 use_torch: bool = True, stream=None, sparse_proposal: bool = False):
+                 use_torch: bool = True, stream=None, sparse_proposal: bool = False, profile_families=()):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
         opt.device, opt.pi, opt.theta, opt.seed, opt.profile = device, pi, theta, seed, int(profile)
         opt.flags = 1 if sparse_proposal else 0
+        # kernel families to time (names as in hgp_kernel_stats); empty = all
+        opt.profile_families = sum(1 << KERNEL_FAMILIES.index(f) for f in profile_families)
         self._keep = []
         self._stream = None
         if use_torch:

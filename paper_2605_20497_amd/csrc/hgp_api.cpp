@@ -51,16 +51,19 @@ static void prof_flush(Ctx* c) {
     P.used = 0;
 }
 
+static bool prof_on(const Ctx* c, int kf) {
+    return c->opt.profile && (c->opt.profile_families == 0 || ((c->opt.profile_families >> kf) & 1u));
+}
+
 void prof_begin(Ctx* c, int kf) {
-    (void)kf;
-    if (!c->opt.profile) return;
+    if (!prof_on(c, kf)) return;
     if (c->prof.open.size() > 8192) prof_flush(c);
     c->prof.cur_begin = prof_event(c);
     HIPC(hipEventRecord(c->prof.cur_begin, c->stream));
 }
 
 void prof_end(Ctx* c, int kf) {
-    if (!c->opt.profile) return;
+    if (!prof_on(c, kf)) return;
     hipEvent_t e = prof_event(c);
     HIPC(hipEventRecord(e, c->stream));
     c->prof.open.push_back({kf, {c->prof.cur_begin, e}});

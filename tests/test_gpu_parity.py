@@ -210,3 +210,15 @@ def test_error_paths():
     g.hgp_coarsen()
     g.hgp_refine()
     g.close()
+
+
+def test_profile_family_mask():
+    from paper_2605_20497_amd import KERNEL_FAMILIES, Partitioner
+    hg = W.random_snn(1024, 15, 3)
+    g = Partitioner(profile=True, profile_families=("propose",))
+    g.partition(hg, 64, 256)
+    st = g.hgp_kernel_stats()
+    assert list(st) == KERNEL_FAMILIES
+    assert st["propose"][0] > 0
+    assert all(v[0] == 0 for k, v in st.items() if k != "propose")
+    g.close()
