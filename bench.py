@@ -34,7 +34,7 @@ LDS_UPDATE_PEAK_GOPS = 256 * 32 * 2.4
 TRAFFIC_SOURCES = ["paper_2605_20497_amd/csrc/k_coarsen.hip", "paper_2605_20497_amd/csrc/dev_util.h",
                    "paper_2605_20497_amd/csrc/hgp_internal.h"]
 TRAFFIC = {  # {sources_sha256: bytes per k_propose launch}
-    "f21b196745d97b186fcf36500a9628956c76aa6e7e016851e86e556dc5656930": 8871307888,
+    "ad259e73a71af4bd94eb9131f9627bbe1381be6e6ab47802a6d7a42249a700ea": 4027845045,
 }
 
 
