@@ -64,7 +64,10 @@ typedef struct hgp_options {
     int32_t profile;       /* 1 = time every kernel launch with HIP events (see hgp_kernel_stats) */
     int32_t flags;         /* bit 0: use the sparse (hash-table) candidate proposal at every level;
                               by default it serves only levels whose ids need many dense id-range
-                              passes while every neighbourhood fits a few hashed passes */
+                              passes while every neighbourhood fits a few hashed passes.
+                              bit 1: use the dense (MFMA product) proposal wherever it fits;
+                              bit 2: never use it; by default it is chosen per level by an
+                              estimate of both proposals' time.  Results are identical. */
     uint32_t profile_families; /* with profile = 1: bit i times only kernel family i (the order of
                                 * hgp_kernel_stats' names); 0 = every family */
     int32_t reserved[5];

@@ -23,7 +23,7 @@ void hip_check(hipError_t e, const char* what) {
 static const char* const kKfNames[KF_COUNT] = {
     "validate", "transpose", "radix_sort", "scan", "level_stats", "propose", "match", "isolated",
     "gamma", "contract_edges", "pack", "phi", "part_stats", "gains", "moves", "chains",
-    "rank", "inseq", "events", "select", "apply", "project", "eval", "misc"};
+    "rank", "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense"};
 
 const char* kf_name(int kf) { return (kf >= 0 && kf < KF_COUNT) ? kKfNames[kf] : "?"; }
 

@@ -35,7 +35,7 @@ void hip_check(hipError_t e, const char* what);
 enum Kf {
     KF_VALIDATE, KF_TRANSPOSE, KF_SORT, KF_SCAN, KF_LEVEL_STATS, KF_PROPOSE, KF_MATCH, KF_ISOLATED,
     KF_GAMMA, KF_CONTRACT_EDGES, KF_PACK, KF_PHI, KF_PART_STATS, KF_GAINS, KF_MOVES, KF_CHAINS,
-    KF_RANK, KF_INSEQ, KF_EVENTS, KF_SELECT, KF_APPLY, KF_PROJECT, KF_EVAL, KF_MISC, KF_COUNT
+    KF_RANK, KF_INSEQ, KF_EVENTS, KF_SELECT, KF_APPLY, KF_PROJECT, KF_EVAL, KF_MISC, KF_PROPOSE_DENSE, KF_COUNT
 };
 const char* kf_name(int kf);
 
@@ -172,7 +172,12 @@ void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32*
 // ---------------------------------------------------------------------------
 // Coarsening launchers (k_coarsen.hip).
 // ---------------------------------------------------------------------------
-void coarsen_level(Ctx* c, int lv);  // builds levels[lv+1] or leaves levels unchanged if no merge
+void coarsen_level(Ctx* c, int lv);
+// Dense (MFMA) candidate proposal for small levels; see k_dense.hip.
+bool dense_proposal_fits(i32 N, i32 E, u64 max_t);
+bool prefer_dense_proposal(const Ctx* c, i32 N, i32 E, u64 max_t, u64 sum_card_sq);
+void propose_dense(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, u64 max_t, i32* cand,
+                   u64* score);  // builds levels[lv+1] or leaves levels unchanged if no merge
 
 // ---------------------------------------------------------------------------
 // Refinement launchers (k_refine.hip).

@@ -55,19 +55,26 @@ __global__ __launch_bounds__(256) void k_node_tsum(i32 N, const i64* __restrict_
 __global__ __launch_bounds__(256) void k_edge_tsum(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ hw,
                                                    unsigned long long* stats) {
     __shared__ unsigned long long red[16];
-    unsigned long long s = 0, c = 0;
+    unsigned long long s = 0, c = 0, sq = 0, tmax = 0;
     for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (i64)gridDim.x * blockDim.x) {
         const i64 card = he_off[e + 1] - he_off[e];
+        const u64 t = norm_weight(hw[e], card > 0 ? card : 1);
         if (card >= 2) {
-            s += norm_weight(hw[e], card);
+            s += t;
             c += 1;
         }
+        sq += (u64)card * (u64)card;
+        tmax = tmax > t ? tmax : t;
     }
     s = block_sum(s, red);
     c = block_sum(c, red);
+    sq = block_sum(sq, red);
+    tmax = wave_max(tmax);
+    if (lane_id() == 0) atomicMax(&stats[14], tmax);  // largest normalised weight
     if (threadIdx.x == 0) {
         atomicAdd(&stats[2], s);
         atomicAdd(&stats[3], c);
+        atomicAdd(&stats[13], sq);  // sum_e |e|^2: pin visits of the sparse proposal
     }
 }
 
@@ -1011,7 +1018,12 @@ void coarsen_level(Ctx* c, int lv) {
 
     // Histogram bins pack (eta << ib) | inter; pick the narrowest that holds both.
     const int ib = std::max(1, bits_for(max_nin));
-    if (ib < 32 && bits_for(max_tsum) <= 32 - ib)
+    const u64 max_t = (u64)st[14], sum_card_sq = (u64)st[13];
+    const bool dense_ok = bits_for(max_tsum) <= 64 - ib && !c->force_hash_propose && !(c->opt.flags & 4) &&
+                          dense_proposal_fits(N, L.E, max_t);
+    if (dense_ok && ((c->opt.flags & 2) || prefer_dense_proposal(c, N, L.E, max_t, sum_card_sq)))
+        propose_dense(c, L, Pi, stats, ib, max_t, cand, score);
+    else if (ib < 32 && bits_for(max_tsum) <= 32 - ib)
         launch_propose<u32>(c, L, Pi, stats, ib, cand, score);
     else if (bits_for(max_tsum) <= 64 - ib)
         launch_propose<unsigned long long>(c, L, Pi, stats, ib, cand, (u64*)score);

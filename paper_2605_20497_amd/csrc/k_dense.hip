@@ -1,0 +1,398 @@
+// Candidate proposal for small levels as matrix products on the MFMA units
+// (Sec. V-C).  With H the node x h-edge incidence (1 where n is a pin of e),
+// H_in its destination part and T = diag(t(e)), the histogram values of every
+// pair are eta = H T H^T and inter = H_in H_in^T.  Once a level has a few
+// thousand nodes, nearly every pair shares an h-edge and the products are
+// dense; they are computed exactly in int8 x int8 -> int32 MFMA by splitting
+// t(e) into 7-bit digit planes.  The candidates are then selected from each
+// node's dense row by the same rules as the histogram kernel: score = eta +
+// noise, validity through sizes and |in(n)| + |in(m)| - inter, top PI by
+// (score desc, id desc).
+#include <algorithm>
+
+#include "dev_util.h"
+
+namespace hgp {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kTile = 128;      // output rows and columns per workgroup
+constexpr int kMaxPlanes = 3;   // 7-bit digit planes of t(e): t < 2^21
+constexpr int kSelU = 8;        // row entries per thread per step of the selection
+
+enum { WS_DN_A = 170, WS_DN_D = 171, WS_DN_DIG = 172, WS_DN_PART = 173 };
+
+// Bit rows, one block per node: bit e of row n is set iff n is a pin of e
+// (A) or a destination of e (D).  Rows are W4 words (a multiple of 4); rows
+// from N to the padded count are zero.
+__global__ __launch_bounds__(256) void k_dense_bits(i32 N, i32 Npad, i32 W4, const i64* __restrict__ inc_off,
+                                                    const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+                                                    u32* A, u32* D) {
+    extern __shared__ u32 row[];  // 2 * W4 words
+    for (i32 n = blockIdx.x; n < Npad; n += gridDim.x) {
+        for (int i = threadIdx.x; i < 2 * W4; i += blockDim.x) row[i] = 0;
+        __syncthreads();
+        if (n < N) {
+            const i64 a = inc_off[n], b = inc_off[n + 1];
+            const i32 nin = inc_nin[n];
+            for (i64 k = a + threadIdx.x; k < b; k += blockDim.x) {
+                const i32 e = inc[k];
+                atomicOr(&row[e >> 5], 1u << (e & 31));
+                if (k - a < nin) atomicOr(&row[W4 + (e >> 5)], 1u << (e & 31));  // inbound entries come first
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < W4; i += blockDim.x) {
+            A[(i64)n * W4 + i] = row[i];
+            D[(i64)n * W4 + i] = row[W4 + i];
+        }
+        __syncthreads();
+    }
+}
+
+// Digit planes of the normalised weights: dig[p][e] = (t(e) >> 7p) & 127.
+__global__ void k_dense_digits(i32 E, i32 Epad, int NP, const i64* __restrict__ he_off, const i32* __restrict__ hw,
+                               signed char* dig) {
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < Epad; e += (i64)gridDim.x * blockDim.x) {
+        const u64 t = e < E ? norm_weight(hw[e], he_off[e + 1] - he_off[e]) : 0;
+        for (int p = 0; p < NP; ++p) dig[(i64)p * Epad + e] = (signed char)((t >> (7 * p)) & 127);
+    }
+}
+
+// 16 bits -> 16 bytes of 0 / 1, bit j into byte j (four nibbles, each spread
+// by one multiply: the shifted copies do not overlap, so nothing carries).
+// Both factors fit 24 bits, so the full-rate 24-bit multiply is exact.
+__device__ __forceinline__ v4i spread16(u32 bits) {
+    v4i r;
+    r.x = (int)(__umul24((bits >> 0) & 15u, 0x00204081u) & 0x01010101u);
+    r.y = (int)(__umul24((bits >> 4) & 15u, 0x00204081u) & 0x01010101u);
+    r.z = (int)(__umul24((bits >> 8) & 15u, 0x00204081u) & 0x01010101u);
+    r.w = (int)(__umul24((bits >> 12) & 15u, 0x00204081u) & 0x01010101u);
+    return r;
+}
+
+__device__ __forceinline__ u32 word_of(const uint4& q, int s) {
+    return s == 0 ? q.x : s == 1 ? q.y : s == 2 ? q.z : q.w;
+}
+
+// One workgroup per (upper-triangle tile pair, K split): 4 waves, each a
+// 64 x 64 block of the 128 x 128 tile as 2 x 2 MFMA blocks of 32 x 32, for NP
+// digit planes of eta and one plane of inter.  The h-edges are taken 128 at a
+// time (4 words per bit row): the workgroup stages the tile's 2 x 128 rows of
+// A and D bits and the digits of those h-edges in shared memory, double
+// buffered, so the next chunk's loads overlap the current chunk's products.
+// Lane l holds row (l mod 32) of its A-side block and column (l mod 32) of its
+// B-side block, for the 16 h-edges 16*(l / 32) .. +15 of each 32-edge step;
+// accumulator entry i is output (8*(i/4) + 4*(l/32) + i mod 4, l mod 32).  The
+// packed partial (eta << ib) | inter of each pair is written for both
+// orientations into the split's own N x N slice.
+template <int NP>
+__global__ __launch_bounds__(256) void k_dense_gemm(int ntile, i32 W4, i32 wsplit, const u32* __restrict__ A,
+                                                    const u32* __restrict__ D, const signed char* __restrict__ dig,
+                                                    i32 Epad, u64* part, i64 Npad, int ib) {
+    __shared__ uint4 sbits[2][4][kTile];   // [buffer][A rows, D rows, A cols, D cols][tile row]
+    __shared__ uint4 sdig[2][NP][8];       // [buffer][plane][16-byte group of the 128 h-edges]
+    int ti = 0, rem = blockIdx.x;
+    while (rem >= ntile - ti) {
+        rem -= ntile - ti;
+        ++ti;
+    }
+    const int tj = ti + rem;
+    const i32 wbeg = blockIdx.y * wsplit;
+    const i32 wend = min(W4, wbeg + wsplit);
+    const int t = threadIdx.x;
+    const int wv = t >> 6, l = t & 63, lr = l & 31, kh = l >> 5;
+    const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;  // the wave's block within the tile
+    const i64 R0 = (i64)ti * kTile, C0 = (i64)tj * kTile;
+    // staging: thread t moves rows t and t + 256 of the 512 (matrix, row) pairs
+    auto src = [&](int q, i32 w) -> const uint4* {
+        const int which = q >> 7, row = q & (kTile - 1);
+        const u32* M = (which & 1) ? D : A;
+        const i64 base = (which < 2 ? R0 : C0) + row;
+        return (const uint4*)&M[base * W4 + w];
+    };
+    v16i acc[NP + 1][2][2];
+#pragma unroll
+    for (int p = 0; p <= NP; ++p)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[p][a][b][i] = 0;
+    if (wbeg < wend) {
+        const uint4 x0 = *src(t, wbeg), x1 = *src(t + 256, wbeg);
+        sbits[0][t >> 7][t & (kTile - 1)] = x0;
+        sbits[0][(t + 256) >> 7][(t + 256) & (kTile - 1)] = x1;
+        if (t < NP * 8) sdig[0][t >> 3][t & 7] = *(const uint4*)&dig[(i64)(t >> 3) * Epad + (i64)wbeg * 32 + (t & 7) * 16];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (i32 w = wbeg; w < wend; w += 4) {
+        const bool more = w + 4 < wend;
+        uint4 y0, y1, yd;
+        if (more) {
+            y0 = *src(t, w + 4);
+            y1 = *src(t + 256, w + 4);
+            if (t < NP * 8) yd = *(const uint4*)&dig[(i64)(t >> 3) * Epad + (i64)(w + 4) * 32 + (t & 7) * 16];
+        }
+        uint4 ar[2], dr[2], ac[2], dc[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            ar[b] = sbits[cur][0][wr + b * 32 + lr];
+            dr[b] = sbits[cur][1][wr + b * 32 + lr];
+            ac[b] = sbits[cur][2][wc + b * 32 + lr];
+            dc[b] = sbits[cur][3][wc + b * 32 + lr];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            v4i dg[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const uint4 q = sdig[cur][p][2 * s + kh];
+                dg[p] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+            }
+            v4i fa[2], fd[2], fdc[2], fb[NP][2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                fa[b] = spread16((word_of(ar[b], s) >> (16 * kh)) & 0xFFFFu);
+                fd[b] = spread16((word_of(dr[b], s) >> (16 * kh)) & 0xFFFFu);
+                fdc[b] = spread16((word_of(dc[b], s) >> (16 * kh)) & 0xFFFFu);
+                const v4i x = spread16((word_of(ac[b], s) >> (16 * kh)) & 0xFFFFu);
+                const v4i m = (x << 8) - x;  // 0x00 / 0xFF bytes
+#pragma unroll
+                for (int p = 0; p < NP; ++p) fb[p][b] = m & dg[p];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                    for (int p = 0; p < NP; ++p)
+                        acc[p][a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[p][b], acc[p][a][b], 0, 0, 0);
+                    acc[NP][a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fd[a], fdc[b], acc[NP][a][b], 0, 0, 0);
+                }
+        }
+        if (more) {
+            sbits[cur ^ 1][t >> 7][t & (kTile - 1)] = y0;
+            sbits[cur ^ 1][(t + 256) >> 7][(t + 256) & (kTile - 1)] = y1;
+            if (t < NP * 8) sdig[cur ^ 1][t >> 3][t & 7] = yd;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    const i64 r0 = R0 + wr, c0 = C0 + wc;
+    u64* out = part + (i64)blockIdx.y * Npad * Npad;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const i64 r = r0 + a * 32 + 8 * (i / 4) + 4 * kh + (i % 4);
+                const i64 c = c0 + b * 32 + lr;
+                u64 eta = 0;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) eta += (u64)(u32)acc[p][a][b][i] << (7 * p);
+                const u64 v = (eta << ib) | (u64)(u32)acc[NP][a][b][i];
+                out[r * Npad + c] = v;
+                out[c * Npad + r] = v;
+            }
+}
+
+// Candidate selection from the dense rows, one block per node; the bin-scan
+// rules of the histogram kernel (block-wide pruning floor, all-valid fast
+// path, exact top PI, block merge).
+template <int PI>
+__global__ __launch_bounds__(256) void k_dense_select(i32 N, i64 Npad, int ksplit, const u64* __restrict__ part,
+                                                      const i32* __restrict__ inc_nin, const i32* __restrict__ nw,
+                                                      i64 omega, i64 delta, u64 seed,
+                                                      const unsigned long long* __restrict__ stats, int ib,
+                                                      i32* cand, u64* score) {
+    __shared__ u64 red_s[16];
+    __shared__ i32 red_m[16];
+    __shared__ unsigned long long s_floor;
+    const u64 cap = stats[4];
+    DivU64 ndiv;
+    ndiv.m = stats[8];
+    ndiv.sh1 = (u32)stats[9];
+    ndiv.sh2 = (u32)(stats[9] >> 32);
+    ndiv.d = stats[10];
+    const u64 imask = (1ull << ib) - 1;
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+        const i32 nin_n = inc_nin[n];
+        const i64 nw_n = nw[n];
+        const int all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
+        if (threadIdx.x == 0) s_floor = 0;
+        __syncthreads();
+        u64 bs[PI];
+        i32 bm[PI];
+#pragma unroll
+        for (int r = 0; r < PI; ++r) {
+            bs[r] = 0;
+            bm[r] = -1;
+        }
+        const u64* rowp = part + (i64)n * Npad;
+        for (i32 s0 = threadIdx.x; s0 < N; s0 += kSelU * (i32)blockDim.x) {
+            u64 sc[kSelU];
+            i64 itr[kSelU];
+            int pick[kSelU];
+            const bool full = bm[PI - 1] >= 0;
+            const u64 b_s = bs[PI - 1];
+            const i32 b_m = bm[PI - 1];
+            const u64 fl = s_floor;
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const i32 m = s0 + u * (i32)blockDim.x;
+                const int in = (int)(m < N) & (int)(m != n);
+                u64 v = 0;
+                for (int k = 0; k < ksplit; ++k) v += in ? rowp[(i64)k * Npad * Npad + m] : 0ull;
+                const u64 eta = v >> ib;
+                itr[u] = (i64)(v & imask);
+                const int maybe = (int)(v != 0) & !((int)full & (int)(eta + cap < b_s)) & (int)(eta + cap >= fl);
+                sc[u] = maybe ? eta + pair_noise(seed, n, m, ndiv) : 0;
+                pick[u] = maybe & !((int)full & (int)!lex_gt(sc[u], m, b_s, b_m)) & (int)(sc[u] >= fl);
+            }
+            i64 nwm[kSelU], ninm[kSelU];
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const int ld = pick[u] & !all_valid;
+                const i32 m = ld ? s0 + u * (i32)blockDim.x : 0;
+                nwm[u] = ld ? (i64)nw[m] : 0;
+                ninm[u] = ld ? (i64)inc_nin[m] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const int ok = pick[u] & (int)(nw_n + nwm[u] <= omega) &
+                               (int)((i64)nin_n + ninm[u] - itr[u] <= delta);
+                if (ok) {  // ok is computed bitwise; the insertion itself is branch-free
+                    u64 cs = sc[u];
+                    i32 cm = s0 + u * (i32)blockDim.x;
+#pragma unroll
+                    for (int r = 0; r < PI; ++r) {
+                        const bool better = lex_better(cs, cm, bs[r], bm[r]);
+                        const u64 ts = bs[r];
+                        const i32 tm = bm[r];
+                        bs[r] = better ? cs : ts;
+                        bm[r] = better ? cm : tm;
+                        cs = better ? ts : cs;
+                        cm = better ? tm : cm;
+                    }
+                }
+            }
+            if ((int)(bm[PI - 1] >= 0) & (int)(bs[PI - 1] > fl)) atomicMax(&s_floor, (unsigned long long)bs[PI - 1]);
+        }
+        __syncthreads();
+        for (int r = 0; r < PI; ++r) {
+            u64 hs = bs[0];
+            i32 hm = bm[0];
+            wave_lexmax(hs, hm);
+            if (lane == 0) {
+                red_s[wv] = hs;
+                red_m[wv] = hm;
+            }
+            __syncthreads();
+            u64 ws = red_s[0];
+            i32 wm = red_m[0];
+            for (int w = 1; w < nwv; ++w) {
+                const u64 s2 = red_s[w];
+                const i32 m2 = red_m[w];
+                const bool t = lex_gt(s2, m2, ws, wm);
+                ws = t ? s2 : ws;
+                wm = t ? m2 : wm;
+            }
+            __syncthreads();
+            if ((int)(wm >= 0) & (int)(bm[0] == wm)) {
+#pragma unroll
+                for (int q = 0; q + 1 < PI; ++q) {
+                    bs[q] = bs[q + 1];
+                    bm[q] = bm[q + 1];
+                }
+                bs[PI - 1] = 0;
+                bm[PI - 1] = -1;
+            }
+            if (threadIdx.x == 0) {
+                cand[(i64)n * PI + r] = wm;
+                score[(i64)n * PI + r] = wm >= 0 ? ws : 0;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int dense_planes(u64 max_t) {
+    int p = 1;
+    while (p <= kMaxPlanes && (max_t >> (7 * p)) != 0) ++p;
+    return p <= kMaxPlanes ? p : 0;
+}
+
+bool dense_proposal_fits(i32 N, i32 E, u64 max_t) {
+    return N >= 2 && E >= 1 && E <= (1 << 18) && N <= 12288 && dense_planes(max_t) > 0;
+}
+
+// Estimated times of the two proposals: MFMA products over the padded
+// upper triangle at a third of the int8 peak, against the histogram's
+// Sigma |e|^2 updates at the rate it sustains on such levels.
+bool prefer_dense_proposal(const Ctx* c, i32 N, i32 E, u64 max_t, u64 sum_card_sq) {
+    if (!dense_proposal_fits(N, E, max_t)) return false;
+    const double Npad = (double)((N + kTile - 1) / kTile * kTile);
+    const double Epad = (double)(((E + 31) / 32 + 3) / 4 * 4 * 32);
+    const double macs = Npad * (Npad + kTile) / 2.0 * Epad * (dense_planes(max_t) + 1);
+    const double dense_s = macs / (2.5e15 * c->num_cu / 256.0 / 3.0) + 60e-6;
+    const double sparse_s = (double)sum_card_sq / 4.0e11;
+    return dense_s < sparse_s;
+}
+
+void propose_dense(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, u64 max_t, i32* cand,
+                   u64* score) {
+    const i32 N = L.N, E = L.E;
+    const int NP = dense_planes(max_t);
+    const i32 Npad = (N + kTile - 1) / kTile * kTile;
+    const i32 W4 = ((E + 31) / 32 + 3) / 4 * 4;
+    const i32 Epad = W4 * 32;
+    u32* A = wsp<u32>(c, WS_DN_A, (size_t)Npad * W4);
+    u32* D = wsp<u32>(c, WS_DN_D, (size_t)Npad * W4);
+    signed char* dig = wsp<signed char>(c, WS_DN_DIG, (size_t)NP * Epad);
+    LAUNCH(c, KF_PROPOSE_DENSE, k_dense_bits, std::min<i64>(Npad, (i64)c->num_cu * 8), 256, sizeof(u32) * 2 * W4, N, Npad,
+           W4, L.inc_off(), L.inc_nin(), L.inc(), A, D);
+    LAUNCH(c, KF_PROPOSE_DENSE, k_dense_digits, grid_for(Epad, 256, c->num_cu * 4), 256, 0, E, Epad, NP, L.he_off(),
+           c->hw(), dig);
+    const int ntile = Npad / kTile;
+    const int pairs = ntile * (ntile + 1) / 2;
+    // K splits so that the grid covers the device a few times over
+    int ksplit = std::max(1, std::min(W4 / 4, (4 * c->num_cu + pairs - 1) / pairs));
+    ksplit = std::min(ksplit, 16);
+    const i32 wsplit = ((W4 / 4 + ksplit - 1) / ksplit) * 4;
+    ksplit = (W4 + wsplit - 1) / wsplit;
+    u64* part = wsp<u64>(c, WS_DN_PART, (size_t)ksplit * Npad * Npad);
+    const dim3 grid(pairs, ksplit);
+    switch (NP) {
+        case 1:
+            LAUNCH(c, KF_PROPOSE_DENSE, k_dense_gemm<1>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
+            break;
+        case 2:
+            LAUNCH(c, KF_PROPOSE_DENSE, k_dense_gemm<2>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
+            break;
+        default:
+            LAUNCH(c, KF_PROPOSE_DENSE, k_dense_gemm<3>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
+            break;
+    }
+    const int grid_s = (int)std::min<i64>(N, (i64)c->num_cu * 8);
+#define HGP_DSEL(PIV)                                                                                             \
+    case PIV:                                                                                                     \
+        LAUNCH(c, KF_PROPOSE_DENSE, k_dense_select<PIV>, grid_s, 256, 0, N, (i64)Npad, ksplit, (const u64*)part,        \
+               L.inc_nin(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib, cand, score);                    \
+        break;
+    switch (Pi) {
+        HGP_DSEL(1) HGP_DSEL(2) HGP_DSEL(3) HGP_DSEL(4) HGP_DSEL(5) HGP_DSEL(6) HGP_DSEL(7) HGP_DSEL(8)
+        default: fail(HGP_E_INVALID, "pi must be in 1..8");
+    }
+#undef HGP_DSEL
+}
+
+}  // namespace hgp

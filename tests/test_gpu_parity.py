@@ -11,17 +11,18 @@ from paper_2605_20497_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _gpu(Pi=4, theta=16, seed=0, profile=False, sparse=False):
+def _gpu(Pi=4, theta=16, seed=0, profile=False, sparse=False, dense=None):
     from paper_2605_20497_amd import Partitioner
-    return Partitioner(pi=Pi, theta=theta, seed=seed, profile=profile, sparse_proposal=sparse)
+    return Partitioner(pi=Pi, theta=theta, seed=seed, profile=profile, sparse_proposal=sparse,
+                       dense_proposal=dense)
 
 
-def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label="", sparse=False):
+def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label="", sparse=False, dense=None):
     print("case", label, "N", hg.n_nodes, "E", hg.n_hedges, "P", hg.n_pins, "omega", omega, "delta", delta,
-          "k", k, "sparse", sparse, flush=True)
+          "k", k, "sparse", sparse, "dense", dense, flush=True)
     og = oracle.Graph(hg)
     res = og.partition(omega, delta, k=k, Pi=Pi, theta=theta, seed=seed)
-    g = _gpu(Pi, theta, seed, sparse=sparse)
+    g = _gpu(Pi, theta, seed, sparse=sparse, dense=dense)
     g.load(hg)
     g.hgp_set_limits(omega, delta, k)
     nl = g.hgp_coarsen()
@@ -83,6 +84,25 @@ def test_small_random_sparse_proposal(case):
     n, e, card, seed, msrc, mhw, mnw, omega, delta = case
     hg = W.random_small(n, e, card, seed, max_src=msrc, max_hw=mhw, max_nw=mnw)
     _compare_runs(hg, omega, delta, label="sparse-%d" % seed, sparse=True)
+
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=lambda c: "n%d-e%d-s%d" % (c[0], c[1], c[3]))
+def test_small_random_dense_proposal(case):
+    # every level's proposal through the MFMA products
+    n, e, card, seed, msrc, mhw, mnw, omega, delta = case
+    hg = W.random_small(n, e, card, seed, max_src=msrc, max_hw=mhw, max_nw=mnw)
+    _compare_runs(hg, omega, delta, label="dense-%d" % seed, dense=True)
+
+
+def test_dense_proposal_snn_and_config1():
+    hg = W.random_snn(1024, 15, 3)
+    _compare_runs(hg, 64, 256, label="snn-1k-dense", dense=True)
+    hg = W.random_snn(4096, 95, 6)
+    _compare_runs(hg, 256, 1024, label="snn-4k-e96-dense", dense=True)
+    hg = W.layered_snn(4, 512, 31, 128, 0.8, seed=1)
+    _compare_runs(hg, 64, 512, label="layered-2k-dense", dense=True)
+    hg = W.config1()
+    _compare_runs(hg, hg.omega, hg.delta, label="rand-4k-e32-dense", dense=True)
 
 
 def test_sparse_proposal_with_passes():
