@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "dev_util.h"
+#include "top_select.h"
 
 namespace hgp {
 
@@ -104,10 +105,9 @@ __device__ __forceinline__ DivU64 noise_div(const unsigned long long* stats) {
 // m.  Neighbour ids are split into ranges of R that fit the histogram; every
 // range is one pass over the pins.  The pins of one h-edge are distinct, and
 // h-edges run on different waves, so updates are shared-memory atomics.  After
-// each pass, the block scans the bins, adds the symmetric noise, checks
-// validity (Eq. proposal_graph: sizes, and |in(n) ∪ in(m)| through inter), and
-// keeps per thread the best PI valid neighbours by (score desc, id desc); the
-// block merges the thread lists at the end.
+// each pass the block scans the bins and keeps the best PI valid neighbours
+// (Eq. proposal_graph: sizes, and |in(n) ∪ in(m)| through inter) by (score
+// desc, id desc), score = eta + symmetric noise (top_select.h).
 //
 // Pin sweep: each wave owns a batch of up to 64 incident h-edges (one per
 // lane).  Their pin segments for the current pass (all sources, plus the
@@ -117,7 +117,7 @@ __device__ __forceinline__ DivU64 noise_div(const unsigned long long* stats) {
 // wave keeps many loads outstanding whatever the h-edge sizes.
 constexpr int kProposeU = 8;
 constexpr int kProposeWaves = 4;
-constexpr int kScanU = 8;  // bins per thread per step of the bin scan
+constexpr int kScanVec = 2;  // 16-byte vectors of bins per thread per step of the bin scan
 // Batches whose segments average at least kLongSegment pins are instead swept
 // kProposeG h-edges at a time with kProposeGU loads per h-edge and lane.
 constexpr int kLongSegment = 64;
@@ -134,6 +134,27 @@ struct SegTable {
     BIN add_in[kProposeWaves][kWave];   // per destination pin
 };
 
+// The sweep's offset tables and the scan's queues are never live together.
+template <typename BIN>
+union ProposeShared {
+    SegTable<BIN> tab;
+    SelQueue<BIN> q[kProposeWaves];
+};
+
+// Histogram allocation in bins: R rounded up to whole scan vectors of a block.
+__host__ __device__ inline int propose_bins_alloc(int R) { return (R + 255) / 256 * 256; }
+
+template <typename BIN>
+__device__ __forceinline__ BIN vec_bin(const uint4& w, int i);
+template <>
+__device__ __forceinline__ u32 vec_bin<u32>(const uint4& w, int i) {
+    return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
+}
+template <>
+__device__ __forceinline__ unsigned long long vec_bin<unsigned long long>(const uint4& w, int i) {
+    return i == 0 ? ((unsigned long long)w.y << 32 | w.x) : ((unsigned long long)w.w << 32 | w.z);
+}
+
 template <typename BIN, int PI, typename PIN>
 __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
     i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
@@ -141,37 +162,42 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
     const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
     const unsigned long long* __restrict__ stats, int ib, i32* cand, u64* score, int R,
     const i32* __restrict__ bnd) {
+    constexpr int kBinsPerVec = 16 / (int)sizeof(BIN);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     BIN* bins = (BIN*)smem_raw;  // R bins: one pass covers R consecutive neighbour ids
+    uint4* bins4 = (uint4*)smem_raw;
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
-    __shared__ SegTable<BIN> tab;
-    // Largest PI-th best score of any thread's list: the block holds PI valid
-    // candidates scoring at least this, so a bin scoring less cannot enter the
-    // block's top PI and is skipped without a validity check.
+    __shared__ ProposeShared<BIN> sh;
     __shared__ unsigned long long s_floor;
-    const u64 cap = stats[4];
-    const DivU64 ndiv = noise_div(stats);
+    SelNode sn;
+    sn.seed = seed;
+    sn.cap = stats[4];
+    sn.ndiv = noise_div(stats);
+    sn.ib = ib;
+    sn.omega = omega;
+    sn.delta = delta;
+    sn.nw = nw;
+    sn.inc_nin = inc_nin;
+    sn.floor = &s_floor;
     const int npass = (int)((N + R - 1) / R);
-    const BIN imask = (((BIN)1) << ib) - 1;
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
-    for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
+    const int nalloc4 = propose_bins_alloc(R) / kBinsPerVec;
+    for (int i = threadIdx.x; i < nalloc4; i += blockDim.x) bins4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
-        u64 bs[PI];
-        i32 bm[PI];
-#pragma unroll
-        for (int r = 0; r < PI; ++r) {
-            bs[r] = 0;
-            bm[r] = -1;
-        }
+        TopList<PI> top;
+        top.clear();
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i32 nin_n = inc_nin[n];
         const i64 nw_n = nw[n];
+        sn.n = n;
+        sn.nin_n = nin_n;
+        sn.nw_n = nw_n;
         if (threadIdx.x == 0) s_floor = 0;  // read after the sweep's barrier
         // When even the heaviest and most-connected node fits with n, every
         // pair (n, m) is valid and the scan needs no per-neighbour loads.
-        const int all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
+        sn.all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
         // h-edges per wave batch: spread the node's h-edges evenly over the waves.
         const i64 deg = b - a;
         const i64 chunk = deg <= (i64)nwv * kWave ? (deg + nwv - 1) / nwv : (i64)kWave;
@@ -261,12 +287,12 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                     }
                     continue;
                 }
-                tab.start[wv][lane] = excl;
-                tab.src_end[wv][lane] = excl + cs;
-                tab.sbase[wv][lane] = e0 - excl;
-                tab.dbase[wv][lane] = dlo - cs - excl;
-                tab.add[wv][lane] = add;
-                tab.add_in[wv][lane] = add_in;
+                sh.tab.start[wv][lane] = excl;
+                sh.tab.src_end[wv][lane] = excl + cs;
+                sh.tab.sbase[wv][lane] = e0 - excl;
+                sh.tab.dbase[wv][lane] = dlo - cs - excl;
+                sh.tab.add[wv][lane] = add;
+                sh.tab.add_in[wv][lane] = add_in;
                 wave_sync();
                 int cur = 0;
                 for (i32 j0 = 0; j0 < T; j0 += kProposeU * kWave) {
@@ -277,12 +303,12 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                         const i32 j = j0 + u * kWave + lane;
                         const int in = (int)(j < T);
                         while ((int)(cur + 1 < kWave) & in) {
-                            if (tab.start[wv][cur + 1] > j) break;
+                            if (sh.tab.start[wv][cur + 1] > j) break;
                             ++cur;
                         }
-                        const int is_src = (int)(j < tab.src_end[wv][cur]);
-                        const i64 pos = in ? (is_src ? tab.sbase[wv][cur] : tab.dbase[wv][cur]) + j : 0;
-                        ad[u] = is_src ? tab.add[wv][cur] : tab.add_in[wv][cur];
+                        const int is_src = (int)(j < sh.tab.src_end[wv][cur]);
+                        const i64 pos = in ? (is_src ? sh.tab.sbase[wv][cur] : sh.tab.dbase[wv][cur]) + j : 0;
+                        ad[u] = is_src ? sh.tab.add[wv][cur] : sh.tab.add_in[wv][cur];
                         mm[u] = in ? (i32)pins[pos] : n;
                     }
 #pragma unroll
@@ -294,98 +320,34 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                 wave_sync();  // the table is rewritten by the next batch
             }
             __syncthreads();
-            // Bin scan, kScanU bins per thread at a time: bins that might enter
-            // the thread's list (judged against the list as it stood at the
-            // start of the batch, so possibly more than needed) get their
-            // validity operands loaded together; insertion then keeps the
-            // exact best PI whatever the order.
-            const int used = hi - lo;
-            for (int s0 = threadIdx.x; s0 < used; s0 += kScanU * (int)blockDim.x) {
-                u64 sc[kScanU];
-                i64 itr[kScanU];
-                int pick[kScanU];
-                const bool full = bm[PI - 1] >= 0;
-                const u64 b_s = bs[PI - 1];
-                const i32 b_m = bm[PI - 1];
-                const u64 fl = s_floor;
+            // Bin scan: every thread reads kScanVec 16-byte vectors of bins per
+            // step and clears them; bins that can still reach the top PI are
+            // queued and scored 64 at a time (top_select.h).
+            const int nvec = (hi - lo + kBinsPerVec - 1) / kBinsPerVec;
+            u32 qh = 0, qn = 0;
+            for (int v0 = 0; v0 < nvec; v0 += kScanVec * (int)blockDim.x) {
+                uint4 w[kScanVec];
 #pragma unroll
-                for (int u = 0; u < kScanU; ++u) {
-                    const int sidx = s0 + u * (int)blockDim.x;
-                    const int in = (int)(sidx < used);
-                    const BIN v = in ? bins[sidx] : (BIN)0;
-                    if (v != 0) bins[sidx] = 0;
-                    const u64 eta = (u64)(v >> ib);
-                    itr[u] = (i64)(v & imask);
-                    const int maybe = (int)(v != 0) & !((int)full & (int)(eta + cap < b_s)) & (int)(eta + cap >= fl);
-                    const i32 m = lo + sidx;
-                    sc[u] = maybe ? eta + pair_noise(seed, n, m, ndiv) : 0;
-                    pick[u] = maybe & !((int)full & (int)!lex_gt(sc[u], m, b_s, b_m)) & (int)(sc[u] >= fl);
+                for (int j = 0; j < kScanVec; ++j) {
+                    const int vi = v0 + j * (int)blockDim.x + (int)threadIdx.x;
+                    w[j] = vi < nvec ? bins4[vi] : make_uint4(0u, 0u, 0u, 0u);
+                    if (vi < nvec) bins4[vi] = make_uint4(0u, 0u, 0u, 0u);
                 }
-                i64 nwm[kScanU], ninm[kScanU];
+                const BIN vmin = sel_vmin<BIN, PI>(top, sn);
 #pragma unroll
-                for (int u = 0; u < kScanU; ++u) {
-                    const int ld = pick[u] & !all_valid;
-                    const i32 m = ld ? lo + s0 + u * (int)blockDim.x : 0;
-                    nwm[u] = ld ? (i64)nw[m] : 0;
-                    ninm[u] = ld ? (i64)inc_nin[m] : 0;
-                }
+                for (int j = 0; j < kScanVec; ++j) {
+                    const i32 mb = lo + (v0 + j * (int)blockDim.x + (int)threadIdx.x) * kBinsPerVec;
 #pragma unroll
-                for (int u = 0; u < kScanU; ++u) {
-                    const int ok = pick[u] & (int)(nw_n + nwm[u] <= omega) &
-                                   (int)((i64)nin_n + ninm[u] - itr[u] <= delta);
-                    if (ok) {  // ok is computed bitwise; the insertion itself is branch-free
-                        u64 cs = sc[u];
-                        i32 cm = lo + s0 + u * (int)blockDim.x;
-#pragma unroll
-                        for (int r = 0; r < PI; ++r) {
-                            const bool better = lex_better(cs, cm, bs[r], bm[r]);
-                            const u64 ts = bs[r];
-                            const i32 tm = bm[r];
-                            bs[r] = better ? cs : ts;
-                            bm[r] = better ? cm : tm;
-                            cs = better ? ts : cs;
-                            cm = better ? tm : cm;
-                        }
+                    for (int i = 0; i < kBinsPerVec; ++i) {
+                        const BIN v = vec_bin<BIN>(w[j], i);
+                        sel_push(sh.q[wv], qh, qn, (int)(v >= vmin), mb + i, v, top, sn);
                     }
                 }
-                if ((int)(bm[PI - 1] >= 0) & (int)(bs[PI - 1] > fl)) atomicMax(&s_floor, (unsigned long long)bs[PI - 1]);
             }
+            sel_flush(sh.q[wv], qh, qn, top, sn);
             __syncthreads();
         }
-        // Merge the per-thread lists: PI block-wide lexicographic maxima.
-        for (int r = 0; r < PI; ++r) {
-            u64 hs = bs[0];
-            i32 hm = bm[0];
-            wave_lexmax(hs, hm);
-            if (lane == 0) {
-                red_s[wv] = hs;
-                red_m[wv] = hm;
-            }
-            __syncthreads();
-            u64 ws = red_s[0];
-            i32 wm = red_m[0];
-            for (int w = 1; w < nwv; ++w) {
-                const u64 s2 = red_s[w];
-                const i32 m2 = red_m[w];
-                const bool t = lex_gt(s2, m2, ws, wm);
-                ws = t ? s2 : ws;
-                wm = t ? m2 : wm;
-            }
-            __syncthreads();
-            if ((int)(wm >= 0) & (int)(bm[0] == wm)) {
-#pragma unroll
-                for (int q = 0; q + 1 < PI; ++q) {
-                    bs[q] = bs[q + 1];
-                    bm[q] = bm[q + 1];
-                }
-                bs[PI - 1] = 0;
-                bm[PI - 1] = -1;
-            }
-            if (threadIdx.x == 0) {
-                cand[(i64)n * PI + r] = wm;
-                score[(i64)n * PI + r] = wm >= 0 ? ws : 0;
-            }
-        }
+        sel_merge(top, red_s, red_m, cand + (i64)n * PI, score + (i64)n * PI);
     }
 }
 
@@ -416,9 +378,18 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
     __shared__ u64 red_b[16];
-    const u64 cap = stats[4];
-    const DivU64 ndiv = noise_div(stats);
-    const BIN imask = (((BIN)1) << ib) - 1;
+    __shared__ SelQueue<BIN> selq[4];
+    __shared__ unsigned long long s_floor;
+    SelNode sn;
+    sn.seed = seed;
+    sn.cap = stats[4];
+    sn.ndiv = noise_div(stats);
+    sn.ib = ib;
+    sn.omega = omega;
+    sn.delta = delta;
+    sn.nw = nw;
+    sn.inc_nin = inc_nin;
+    sn.floor = &s_floor;
     const u32 cmask = (u32)C - 1;
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     for (int i = threadIdx.x; i < C; i += blockDim.x) {
@@ -445,14 +416,14 @@ __global__ __launch_bounds__(256) void k_propose_hash(
         // same result, so the count is a power of two (a mask, not a division).
         u64 B = 1;
         while (B * (u64)(C / 2) < bound) B <<= 1;
-        u64 bs[PI];
-        i32 bm[PI];
+        sn.n = n;
+        sn.nin_n = nin_n;
+        sn.nw_n = nw_n;
+        sn.all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
+        TopList<PI> top;
         for (;;) {  // restarts with more passes if a pass overflows the table
-#pragma unroll
-            for (int r = 0; r < PI; ++r) {
-                bs[r] = 0;
-                bm[r] = -1;
-            }
+            top.clear();
+            if (threadIdx.x == 0) s_floor = 0;  // read after the first pass's barrier
             bool again = false;
             for (u64 pass = 0; pass < B && bound > 0; ++pass) {
                 for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
@@ -506,34 +477,21 @@ __global__ __launch_bounds__(256) void k_propose_hash(
                 __syncthreads();
                 const u32 nt = ntouched;
                 const int ov = overflow;
-                for (u32 t = threadIdx.x; t < nt; t += blockDim.x) {
-                    const u32 sl = touched[t];
-                    const i32 m = (i32)keys[sl];
-                    const BIN v = vals[sl];
-                    keys[sl] = kEmpty;
-                    vals[sl] = 0;
-                    if (ov) continue;
-                    const u64 eta = (u64)(v >> ib);
-                    const i64 inter = (i64)(v & imask);
-                    const bool full = bm[PI - 1] >= 0;
-                    if ((int)full & (int)(eta + cap < bs[PI - 1])) continue;
-                    const u64 sc = eta + pair_noise(seed, n, m, ndiv);
-                    if ((int)full & (int)!lex_gt(sc, m, bs[PI - 1], bm[PI - 1])) continue;
-                    const i64 nw_m = nw[m], nin_m = inc_nin[m];
-                    if ((int)(nw_n + nw_m > omega) | (int)((i64)nin_n + nin_m - inter > delta)) continue;
-                    u64 cs = sc;
-                    i32 cm = m;
-#pragma unroll
-                    for (int r = 0; r < PI; ++r) {
-                        const bool better = lex_better(cs, cm, bs[r], bm[r]);
-                        const u64 ts = bs[r];
-                        const i32 tm = bm[r];
-                        bs[r] = better ? cs : ts;
-                        bm[r] = better ? cm : tm;
-                        cs = better ? ts : cs;
-                        cm = better ? tm : cm;
+                u32 qh = 0, qn = 0;
+                for (u32 t0 = 0; t0 < nt; t0 += blockDim.x) {
+                    const u32 t = t0 + threadIdx.x;
+                    const int in = (int)(t < nt);
+                    const u32 sl = in ? touched[t] : 0u;
+                    const i32 m = in ? (i32)keys[sl] : 0;
+                    const BIN v = in ? vals[sl] : (BIN)0;
+                    if (in) {
+                        keys[sl] = kEmpty;
+                        vals[sl] = 0;
                     }
+                    const BIN vmin = sel_vmin<BIN, PI>(top, sn);
+                    sel_push(selq[wv], qh, qn, in & !ov & (int)(v >= vmin), m, v, top, sn);
                 }
+                sel_flush(selq[wv], qh, qn, top, sn);
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     ntouched = 0;
@@ -548,39 +506,7 @@ __global__ __launch_bounds__(256) void k_propose_hash(
             if (!again) break;
             B *= 2;
         }
-        for (int r = 0; r < PI; ++r) {
-            u64 hs = bs[0];
-            i32 hm = bm[0];
-            wave_lexmax(hs, hm);
-            if (lane == 0) {
-                red_s[wv] = hs;
-                red_m[wv] = hm;
-            }
-            __syncthreads();
-            u64 ws = red_s[0];
-            i32 wm = red_m[0];
-            for (int w = 1; w < nwv; ++w) {
-                const u64 s2 = red_s[w];
-                const i32 m2 = red_m[w];
-                const bool t = lex_gt(s2, m2, ws, wm);
-                ws = t ? s2 : ws;
-                wm = t ? m2 : wm;
-            }
-            __syncthreads();
-            if ((int)(wm >= 0) & (int)(bm[0] == wm)) {
-#pragma unroll
-                for (int q = 0; q + 1 < PI; ++q) {
-                    bs[q] = bs[q + 1];
-                    bm[q] = bm[q + 1];
-                }
-                bs[PI - 1] = 0;
-                bm[PI - 1] = -1;
-            }
-            if (threadIdx.x == 0) {
-                cand[(i64)n * PI + r] = wm;
-                score[(i64)n * PI + r] = wm >= 0 ? ws : 0;
-            }
-        }
+        sel_merge(top, red_s, red_m, cand + (i64)n * PI, score + (i64)n * PI);
     }
 }
 
@@ -956,8 +882,8 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
     // a CU.
     const int rmax = 65536 / (int)sizeof(BIN);
     const int R = (int)std::min<i64>(rmax, std::max<i64>(64, L.N));
-    const size_t lds = sizeof(BIN) * (size_t)R;
-    const size_t lds_all = lds + sizeof(SegTable<BIN>) + 256;
+    const size_t lds = sizeof(BIN) * (size_t)propose_bins_alloc(R);
+    const size_t lds_all = lds + sizeof(ProposeShared<BIN>) + 256;
     const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / lds_all)));
     const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu * 2);
     const int npass = (int)ceil_div(L.N, R);

@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "dev_util.h"
+#include "top_select.h"
 
 namespace hgp {
 
@@ -203,9 +204,9 @@ __global__ __launch_bounds__(256) void k_dense_gemm(int ntile, i32 W4, i32 wspli
             }
 }
 
-// Candidate selection from the dense rows, one block per node; the bin-scan
-// rules of the histogram kernel (block-wide pruning floor, all-valid fast
-// path, exact top PI, block merge).
+// Candidate selection from the dense rows, one block per node, with the
+// histogram kernel's selection (top_select.h): the same pruning bound, queue,
+// validity rules and block merge.
 template <int PI>
 __global__ __launch_bounds__(256) void k_dense_select(i32 N, i64 Npad, int ksplit, const u64* __restrict__ part,
                                                       const i32* __restrict__ inc_nin, const i32* __restrict__ nw,
@@ -214,112 +215,52 @@ __global__ __launch_bounds__(256) void k_dense_select(i32 N, i64 Npad, int kspli
                                                       i32* cand, u64* score) {
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
+    __shared__ SelQueue<u64> selq[4];
     __shared__ unsigned long long s_floor;
-    const u64 cap = stats[4];
-    DivU64 ndiv;
-    ndiv.m = stats[8];
-    ndiv.sh1 = (u32)stats[9];
-    ndiv.sh2 = (u32)(stats[9] >> 32);
-    ndiv.d = stats[10];
-    const u64 imask = (1ull << ib) - 1;
-    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    SelNode sn;
+    sn.seed = seed;
+    sn.cap = stats[4];
+    sn.ndiv.m = stats[8];
+    sn.ndiv.sh1 = (u32)stats[9];
+    sn.ndiv.sh2 = (u32)(stats[9] >> 32);
+    sn.ndiv.d = stats[10];
+    sn.ib = ib;
+    sn.omega = omega;
+    sn.delta = delta;
+    sn.nw = nw;
+    sn.inc_nin = inc_nin;
+    sn.floor = &s_floor;
+    const int wv = wave_id();
     for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
-        const i32 nin_n = inc_nin[n];
-        const i64 nw_n = nw[n];
-        const int all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
+        sn.n = n;
+        sn.nin_n = inc_nin[n];
+        sn.nw_n = nw[n];
+        sn.all_valid = (int)(sn.nw_n + (i64)stats[11] <= omega) & (int)((i64)sn.nin_n + (i64)stats[1] <= delta);
         if (threadIdx.x == 0) s_floor = 0;
         __syncthreads();
-        u64 bs[PI];
-        i32 bm[PI];
-#pragma unroll
-        for (int r = 0; r < PI; ++r) {
-            bs[r] = 0;
-            bm[r] = -1;
-        }
+        TopList<PI> top;
+        top.clear();
+        u32 qh = 0, qn = 0;
         const u64* rowp = part + (i64)n * Npad;
-        for (i32 s0 = threadIdx.x; s0 < N; s0 += kSelU * (i32)blockDim.x) {
-            u64 sc[kSelU];
-            i64 itr[kSelU];
-            int pick[kSelU];
-            const bool full = bm[PI - 1] >= 0;
-            const u64 b_s = bs[PI - 1];
-            const i32 b_m = bm[PI - 1];
-            const u64 fl = s_floor;
+        for (i32 s0 = 0; s0 < N; s0 += kSelU * (i32)blockDim.x) {
+            u64 vv[kSelU];
 #pragma unroll
             for (int u = 0; u < kSelU; ++u) {
-                const i32 m = s0 + u * (i32)blockDim.x;
+                const i32 m = s0 + u * (i32)blockDim.x + (i32)threadIdx.x;
                 const int in = (int)(m < N) & (int)(m != n);
                 u64 v = 0;
                 for (int k = 0; k < ksplit; ++k) v += in ? rowp[(i64)k * Npad * Npad + m] : 0ull;
-                const u64 eta = v >> ib;
-                itr[u] = (i64)(v & imask);
-                const int maybe = (int)(v != 0) & !((int)full & (int)(eta + cap < b_s)) & (int)(eta + cap >= fl);
-                sc[u] = maybe ? eta + pair_noise(seed, n, m, ndiv) : 0;
-                pick[u] = maybe & !((int)full & (int)!lex_gt(sc[u], m, b_s, b_m)) & (int)(sc[u] >= fl);
+                vv[u] = v;
             }
-            i64 nwm[kSelU], ninm[kSelU];
+            const u64 vmin = sel_vmin<u64, PI>(top, sn);
 #pragma unroll
-            for (int u = 0; u < kSelU; ++u) {
-                const int ld = pick[u] & !all_valid;
-                const i32 m = ld ? s0 + u * (i32)blockDim.x : 0;
-                nwm[u] = ld ? (i64)nw[m] : 0;
-                ninm[u] = ld ? (i64)inc_nin[m] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kSelU; ++u) {
-                const int ok = pick[u] & (int)(nw_n + nwm[u] <= omega) &
-                               (int)((i64)nin_n + ninm[u] - itr[u] <= delta);
-                if (ok) {  // ok is computed bitwise; the insertion itself is branch-free
-                    u64 cs = sc[u];
-                    i32 cm = s0 + u * (i32)blockDim.x;
-#pragma unroll
-                    for (int r = 0; r < PI; ++r) {
-                        const bool better = lex_better(cs, cm, bs[r], bm[r]);
-                        const u64 ts = bs[r];
-                        const i32 tm = bm[r];
-                        bs[r] = better ? cs : ts;
-                        bm[r] = better ? cm : tm;
-                        cs = better ? ts : cs;
-                        cm = better ? tm : cm;
-                    }
-                }
-            }
-            if ((int)(bm[PI - 1] >= 0) & (int)(bs[PI - 1] > fl)) atomicMax(&s_floor, (unsigned long long)bs[PI - 1]);
+            for (int u = 0; u < kSelU; ++u)
+                sel_push(selq[wv], qh, qn, (int)(vv[u] >= vmin), s0 + u * (i32)blockDim.x + (i32)threadIdx.x, vv[u],
+                         top, sn);
         }
+        sel_flush(selq[wv], qh, qn, top, sn);
         __syncthreads();
-        for (int r = 0; r < PI; ++r) {
-            u64 hs = bs[0];
-            i32 hm = bm[0];
-            wave_lexmax(hs, hm);
-            if (lane == 0) {
-                red_s[wv] = hs;
-                red_m[wv] = hm;
-            }
-            __syncthreads();
-            u64 ws = red_s[0];
-            i32 wm = red_m[0];
-            for (int w = 1; w < nwv; ++w) {
-                const u64 s2 = red_s[w];
-                const i32 m2 = red_m[w];
-                const bool t = lex_gt(s2, m2, ws, wm);
-                ws = t ? s2 : ws;
-                wm = t ? m2 : wm;
-            }
-            __syncthreads();
-            if ((int)(wm >= 0) & (int)(bm[0] == wm)) {
-#pragma unroll
-                for (int q = 0; q + 1 < PI; ++q) {
-                    bs[q] = bs[q + 1];
-                    bm[q] = bm[q + 1];
-                }
-                bs[PI - 1] = 0;
-                bm[PI - 1] = -1;
-            }
-            if (threadIdx.x == 0) {
-                cand[(i64)n * PI + r] = wm;
-                score[(i64)n * PI + r] = wm >= 0 ? ws : 0;
-            }
-        }
+        sel_merge(top, red_s, red_m, cand + (i64)n * PI, score + (i64)n * PI);
     }
 }
 
