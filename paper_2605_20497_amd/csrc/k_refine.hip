@@ -656,6 +656,7 @@ __global__ void k_positions(i32 M, const i32* __restrict__ H, const i32* __restr
 struct MoverRec {
     i32 q, ps, pd, slot;  // slot = (pin offset in e) << 1 | destination flag
 };
+constexpr int kInseqListMax = 256;  // largest h-edge of the event-list kernel
 
 __device__ __forceinline__ i32 lds_row(const i32* __restrict__ rp, const u32* __restrict__ rc, i32 L, i32 p,
                                        i32& ci) {
@@ -673,11 +674,13 @@ __device__ __forceinline__ i32 lds_row(const i32* __restrict__ rp, const u32* __
     return hit ? (i32)(v & 0xFFFFu) : 0;
 }
 
+// All pairs of movers: for h-edges larger than the event-list kernel below
+// takes (skip_le is the largest card it handles; those are skipped here).
 __global__ __launch_bounds__(64) void k_inseq_edges(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
-    const i32* __restrict__ len, unsigned char* code, int cap) {
+    const i32* __restrict__ len, unsigned char* code, int cap, i32 skip_le) {
     // shared memory: cap movers, then cap row parts and cap packed row counts
     extern __shared__ __align__(16) unsigned char smem_raw[];
     MoverRec* mv = (MoverRec*)smem_raw;
@@ -687,6 +690,7 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
         const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
+        if (b - a <= (i64)skip_le) continue;
         const i32 L = len[e];
         for (i32 r = lane; r < L; r += kWave) {
             rp[r] = part[a + r];
@@ -731,6 +735,149 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
             const i32 di = me.slot & 1;
             const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis + xis == 1)) << 2) |
                              ((u32)(di & (int)(cid + xid == 0)) << 3);
+            code[a + (me.slot >> 1)] = (unsigned char)bits;
+        }
+        __syncthreads();
+    }
+}
+
+// Same outcome bytes with per-part event lists instead of all pairs.  The
+// movers' source and destination parts go into a hash table in shared memory;
+// each mover pushes a leave event (q, -1) on its source part's list and an
+// enter event (q, +1) on its destination part's list.  A mover's count of a
+// part just before it moves is the part's row count plus the events of that
+// part's list with an earlier sequence position.  Lists are as long as the
+// number of movers touching a part, usually a few, so a mover reads a few
+// events where the all-pairs kernel compares it with every mover of e.
+// For h-edges of at most cap pins; T = 2^tbits >= 2 * cap table slots.
+struct InseqEv {
+    i32 q;
+    i32 link;  // ((next event + 1) << 1) | destination-pin flag of the mover
+};
+
+__device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inserted) {
+    const u32 tmask = (1u << tbits) - 1u;
+    u32 h = ((u32)p * 0x9E3779B1u) >> (32 - tbits);
+    inserted = 0;
+    for (u32 probe = 0; probe <= tmask; ++probe) {
+        const i32 k = tkey[h];
+        if (k == p) return (i32)h;
+        if (k == -1) {
+            const i32 prev = atomicCAS(&tkey[h], -1, p);
+            if (prev == -1) {
+                inserted = 1;
+                return (i32)h;
+            }
+            if (prev == p) return (i32)h;
+        }
+        h = (h + 1u) & tmask;
+    }
+    return -1;  // unreachable: the table has a slot for every part of 2 * cap movers
+}
+
+__global__ __launch_bounds__(64) void k_inseq_edges_lists(
+    i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
+    const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
+    const i32* __restrict__ len, unsigned char* code, int cap, int tbits) {
+    // shared memory: cap movers, cap row parts, cap packed row counts, then
+    // T keys, T list heads, T packed row counts of the table's parts, and
+    // 2 * cap events
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = 1 << tbits;
+    MoverRec* mv = (MoverRec*)smem_raw;
+    i32* rp = (i32*)(mv + cap);
+    u32* rc = (u32*)(rp + cap);
+    i32* tkey = (i32*)(rc + cap);
+    i32* thead = tkey + T;
+    u32* tcnt = (u32*)(thead + T);
+    InseqEv* ev = (InseqEv*)(tcnt + T);
+    const int lane = threadIdx.x;
+    const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+        const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
+        if (b - a > (i64)cap) continue;
+        const i32 L = len[e];
+        for (i32 r = lane; r < L; r += kWave) {
+            rp[r] = part[a + r];
+            rc[r] = (u32)cnt[a + r] | ((u32)cin[a + r] << 16);  // both <= |e| <= 4096
+        }
+        for (int t = lane; t < T; t += kWave) {
+            tkey[t] = -1;
+            thead[t] = -1;
+        }
+        int k = 0;
+        for (i64 base = a; base < b; base += kWave) {
+            const i64 j = base + lane;
+            const int inb = (int)(j < b);
+            const i32 m = pins[inb ? j : a];
+            const i32 q = posn[m];
+            const int is_mv = inb & (int)(q < M);
+            const u64 mask = __ballot(is_mv);
+            if (is_mv) {
+                MoverRec r;
+                r.q = q;
+                r.ps = rho[m];
+                r.pd = move_dst[m];
+                r.slot = (i32)((j - a) << 1) | (i32)(j >= d0);
+                mv[k + __popcll(mask & lt_mask)] = r;
+            }
+            k += __popcll(mask);
+        }
+        __syncthreads();
+        // Table slots of the movers' parts, their row counts, and the events.
+        for (int i = lane; i < k; i += kWave) {
+            MoverRec me = mv[i];
+            int ins_s, ins_d;
+            const i32 ts = part_slot(tkey, tbits, me.ps, ins_s);
+            const i32 td = part_slot(tkey, tbits, me.pd, ins_d);
+            if (ins_s) {
+                i32 ci;
+                const i32 c0 = lds_row(rp, rc, L, me.ps, ci);
+                tcnt[ts] = (u32)c0 | ((u32)ci << 16);
+            }
+            if (ins_d) {
+                i32 ci;
+                const i32 c0 = lds_row(rp, rc, L, me.pd, ci);
+                tcnt[td] = (u32)c0 | ((u32)ci << 16);
+            }
+            const i32 dj = me.slot & 1;
+            const i32 ns = atomicExch(&thead[ts], 2 * i);
+            const i32 nd = atomicExch(&thead[td], 2 * i + 1);
+            ev[2 * i].q = me.q;
+            ev[2 * i].link = ((ns + 1) << 1) | dj;
+            ev[2 * i + 1].q = me.q;
+            ev[2 * i + 1].link = ((nd + 1) << 1) | dj;
+            me.ps = ts;
+            me.pd = td;
+            mv[i] = me;
+        }
+        __syncthreads();
+        for (int i = lane; i < k; i += kWave) {
+            const MoverRec me = mv[i];
+            i32 x[2], xi[2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                i32 acc = 0, acci = 0;
+                i32 idx = thead[side ? me.pd : me.ps];
+                while (idx >= 0) {
+                    const InseqEv o = ev[idx];
+                    const i32 sg = (i32)(o.q < me.q) * ((idx & 1) ? 1 : -1);
+                    acc += sg;
+                    acci += sg * (o.link & 1);
+                    idx = (o.link >> 1) - 1;
+                }
+                x[side] = acc;
+                xi[side] = acci;
+            }
+            const u32 c0s = tcnt[me.ps], c0d = tcnt[me.pd];
+            const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
+            const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
+            const i32 cis = (i32)(c0s >> 16) + xi[0];
+            const i32 cid = (i32)(c0d >> 16) + xi[1];
+            const i32 di = me.slot & 1;
+            const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
+                             ((u32)(di & (int)(cid == 0)) << 3);
             code[a + (me.slot >> 1)] = (unsigned char)bits;
         }
         __syncthreads();
@@ -1151,10 +1298,20 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i32* ddd = wsp<i32>(c, WS_DDD, M);
     unsigned char* code = wsp<unsigned char>(c, WS_CODE, (size_t)(L.P > 0 ? L.P : 1));
     if (L.E > 0) {
+        // Event lists for h-edges of up to kInseqListMax pins, all pairs beyond.
         const int cap = std::max(1, c->max_card);
-        LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave,
-               (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho,
-               mdst, f.part, f.cnt, f.cin, f.len, code, cap);
+        const int capl = std::min(cap, kInseqListMax);
+        int tbits = 1;
+        while ((1 << tbits) < 2 * capl) ++tbits;
+        const size_t lds_l = (sizeof(MoverRec) + 2 * sizeof(i32) + 2 * sizeof(InseqEv)) * capl +
+                             (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
+        LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, lds_l, L.E,
+               (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl,
+               tbits);
+        if (cap > capl)
+            LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave,
+                   (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn,
+                   rho, mdst, f.part, f.cnt, f.cin, f.len, code, cap, (i32)capl);
     }
     LAUNCH(c, KF_INSEQ, k_inseq_movers, grid_for(M, 4, c->num_cu * 16), 256, 0, (i32)M, seqn, L.inc_off(), L.inc(),
            L.inc_pos(), c->hw(), code, gseq, dds, ddd);

@@ -242,3 +242,11 @@ def test_profile_family_mask():
     assert st["propose"][0] > 0
     assert all(v[0] == 0 for k, v in st.items() if k != "propose")
     g.close()
+
+
+def test_large_hedges_both_inseq_kernels():
+    # h-edges up to 420 pins: the in-sequence outcome comes from the event-list
+    # kernel for h-edges of at most 256 pins and from the all-pairs kernel above
+    hg = W.random_small(1200, 260, 420, 7, max_src=2, max_hw=3, max_nw=2, min_card=40)
+    assert int(np.diff(hg.he_off).max()) > 256
+    _compare_runs(hg, 64, 400, label="large-hedges")
