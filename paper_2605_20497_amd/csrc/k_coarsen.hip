@@ -119,10 +119,8 @@ constexpr int kProposeU = 8;
 constexpr int kProposeWaves = 4;
 constexpr int kScanVec = 2;  // 16-byte vectors of bins per thread per step of the bin scan
 // Batches whose segments average at least kLongSegment pins are instead swept
-// kProposeG h-edges at a time with kProposeGU loads per h-edge and lane.
-constexpr int kLongSegment = 64;
-constexpr int kProposeG = 4;
-constexpr int kProposeGU = 4;
+// by propose_group, several h-edges at a time.
+constexpr int kLongSegment = 32;
 
 template <typename BIN>
 struct SegTable {
@@ -153,6 +151,57 @@ __device__ __forceinline__ u32 vec_bin<u32>(const uint4& w, int i) {
 template <>
 __device__ __forceinline__ unsigned long long vec_bin<unsigned long long>(const uint4& w, int i) {
     return i == 0 ? ((unsigned long long)w.y << 32 | w.x) : ((unsigned long long)w.w << 32 | w.z);
+}
+
+// Grouped pin sweep of one wave batch (lane l holds h-edge l's metadata):
+// h-edges G at a time; each h-edge's sources and this pass's destinations form
+// one index space [0, cs + cd) (destination q at offset q + dsh from the
+// h-edge start), read GU * 64 entries per h-edge and step, so G * GU loads per
+// lane are in flight.  Destinations lie in the pass's id range (pass bounds);
+// sources are tested.
+template <int G, int GU, typename BIN, typename PIN>
+__device__ __forceinline__ void propose_group(int nb, int lane, i32 n, i32 lo, i32 hi, const PIN* __restrict__ pins,
+                                              i64 e0, i32 cs, i32 cd, i32 dsh, BIN add, BIN add_in, BIN* bins) {
+    for (int i0 = 0; i0 < nb; i0 += G) {
+        const PIN* rp[G];
+        i32 ns[G], nt[G], sh[G];
+        BIN sa[G], sai[G];
+        i32 maxt = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int src = min(i0 + g, kWave - 1);
+            const int on = (int)(i0 + g < nb);
+            rp[g] = pins + bcast(e0, src);  // wave-uniform row base
+            const i32 s1 = bcast(cs, src), d1 = bcast(cd, src);
+            ns[g] = s1;
+            nt[g] = on ? s1 + d1 : 0;
+            sh[g] = bcast(dsh, src);
+            sa[g] = bcast(add, src);
+            sai[g] = bcast(add_in, src);
+            maxt = max(maxt, nt[g]);
+        }
+        for (i32 q0 = 0; q0 < maxt; q0 += GU * kWave) {
+            i32 mm[G][GU];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const i32 q = q0 + u * kWave + lane;
+                    const i32 off = q + (q >= ns[g] ? sh[g] : 0);
+                    mm[g][u] = q < nt[g] ? (i32)rp[g][off] : n;
+                }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const i32 q = q0 + u * kWave + lane;
+                    const i32 m = mm[g][u];
+                    const int is_src = (int)(q < ns[g]);
+                    const int ok = (int)(m != n) & (!is_src | (int)((u32)(m - lo) < (u32)(hi - lo)));
+                    if (ok) atomicAdd(&bins[m - lo], is_src ? sa[g] : sai[g]);
+                }
+        }
+    }
 }
 
 template <typename BIN, int PI, typename PIN>
@@ -232,59 +281,16 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
                 const i32 T = __shfl(incl, kWave - 1, kWave);
                 const int nb = __popcll(__ballot(valid));
                 if (T >= kLongSegment * nb) {
-                    // Long segments: kProposeG h-edges at a time, kProposeGU
-                    // coalesced loads per h-edge and lane.
-                    for (int i0 = 0; i0 < nb; i0 += kProposeG) {
-                        i64 sb[kProposeG], db[kProposeG];
-                        i32 ss[kProposeG], dl[kProposeG];
-                        BIN sa[kProposeG], sai[kProposeG];
-                        i32 maxs = 0, maxd = 0;
-#pragma unroll
-                        for (int g = 0; g < kProposeG; ++g) {
-                            const int src = min(i0 + g, kWave - 1);
-                            const int on = (int)(i0 + g < nb);
-                            sb[g] = bcast(e0, src);
-                            db[g] = bcast(dlo, src);
-                            const i32 s1 = bcast(cs, src), d1 = bcast(cd, src);
-                            ss[g] = on ? s1 : 0;
-                            dl[g] = on ? d1 : 0;
-                            sa[g] = bcast(add, src);
-                            sai[g] = bcast(add_in, src);
-                            maxs = max(maxs, ss[g]);
-                            maxd = max(maxd, dl[g]);
-                        }
-                        for (i32 q0 = 0; q0 < maxs; q0 += kWave) {  // sources
-                            i32 mm[kProposeG];
-#pragma unroll
-                            for (int g = 0; g < kProposeG; ++g) {
-                                const i32 q = q0 + lane;
-                                mm[g] = q < ss[g] ? (i32)pins[sb[g] + q] : n;
-                            }
-#pragma unroll
-                            for (int g = 0; g < kProposeG; ++g) {
-                                const i32 m = mm[g];
-                                if ((int)(m != n) & (int)(m >= lo) & (int)(m < hi)) atomicAdd(&bins[m - lo], sa[g]);
-                            }
-                        }
-                        for (i32 q0 = 0; q0 < maxd; q0 += kProposeGU * kWave) {  // this pass's destinations
-                            i32 mm[kProposeG][kProposeGU];
-#pragma unroll
-                            for (int g = 0; g < kProposeG; ++g)
-#pragma unroll
-                                for (int u = 0; u < kProposeGU; ++u) {
-                                    const i32 q = q0 + u * kWave + lane;
-                                    mm[g][u] = q < dl[g] ? (i32)pins[db[g] + q] : n;
-                                }
-#pragma unroll
-                            for (int g = 0; g < kProposeG; ++g)
-#pragma unroll
-                                for (int u = 0; u < kProposeGU; ++u) {
-                                    const i32 m = mm[g][u];
-                                    if ((int)(m != n) & (int)(m >= lo) & (int)(m < hi))
-                                        atomicAdd(&bins[m - lo], sai[g]);
-                                }
-                        }
-                    }
+                    // Long segments: h-edges G at a time, GU coalesced loads per
+                    // h-edge and lane; more h-edges at once when they are short.
+                    const i32 avg = T / max(nb, 1);
+                    const i32 dsh = (i32)(dlo - e0) - cs;  // destination offset past the sources
+                    if (avg <= 64)
+                        propose_group<16, 1>(nb, lane, n, lo, hi, pins, e0, cs, cd, dsh, add, add_in, bins);
+                    else if (avg <= 128)
+                        propose_group<8, 2>(nb, lane, n, lo, hi, pins, e0, cs, cd, dsh, add, add_in, bins);
+                    else
+                        propose_group<4, 4>(nb, lane, n, lo, hi, pins, e0, cs, cd, dsh, add, add_in, bins);
                     continue;
                 }
                 sh.tab.start[wv][lane] = excl;

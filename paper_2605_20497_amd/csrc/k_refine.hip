@@ -247,6 +247,164 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
     }
 }
 
+// Same moves for at most kGainsFlagParts partitions, from a 16-bit row copy
+// whose top bit flags pins(p,e) = 1.  The saving of n is then summed while
+// sweeping (the row of p_s in e carries the flag), so no own-row table and no
+// per-h-edge count load; with a single pass the bins need no range test.
+constexpr i32 kGainsFlagParts = 32767;
+
+// Row sweep of one wave batch for k_gains16: rows G at a time, GU coalesced
+// loads per row and lane, so G * GU loads per lane are in flight.
+template <int G, int GU, bool ONE_PASS>
+__device__ __forceinline__ void gains_group(int nb, int lane, int pass, i32 ps, i32 lo, i32 hi,
+                                            const unsigned short* __restrict__ partf, i64 r0, i32 L, i32 w,
+                                            i64& saving, u32* bins) {
+    for (int i0 = 0; i0 < nb; i0 += G) {
+        const unsigned short* rp[G];
+        i32 sl[G];
+        u32 sw[G];
+        i32 maxl = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int src = min(i0 + g, kWave - 1);
+            rp[g] = partf + bcast(r0, src);  // wave-uniform row base
+            const i32 l = bcast(L, src);
+            sl[g] = i0 + g < nb ? l : 0;
+            sw[g] = (u32)bcast(w, src);
+            maxl = max(maxl, sl[g]);
+        }
+        for (i32 q0 = 0; q0 < maxl; q0 += GU * kWave) {
+            u32 pp[G][GU];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const i32 q = q0 + u * kWave + lane;
+                    pp[g][u] = q < sl[g] ? (u32)rp[g][q] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const u32 raw = pp[g][u];
+                    const i32 p = (i32)(raw & 0x7FFFu);
+                    const int in = (int)(raw != 0xFFFFFFFFu);
+                    // e's row of p_s: the saving counts e when p_s holds one pin of it
+                    if ((pass == 0) & in & (int)(p == ps)) saving += (raw >> 15) ? (i64)sw[g] : 0;
+                    const int range = ONE_PASS ? 1 : (int)((u32)(p - lo) < (u32)(hi - lo));
+                    if (in & (int)(p != ps) & range) atomicAdd(&bins[p - lo], sw[g]);
+                }
+        }
+    }
+}
+
+template <bool ONE_PASS>
+__global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
+    i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
+    const unsigned short* __restrict__ partf, const i32* __restrict__ len, const i32* __restrict__ hw,
+    const i32* __restrict__ nw, const i32* __restrict__ rho, const i64* __restrict__ psize, i64 omega,
+    i32* move_dst, i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R) {
+    extern __shared__ u32 bins[];  // R bins: one pass covers R consecutive partition ids
+    __shared__ i64 red[16];
+    __shared__ i64 red_g[16], red_g2[16];
+    __shared__ i32 red_p[16], red_p2[16];
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    const int npass = ONE_PASS ? 1 : (int)((nparts + R - 1) / R);
+    for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
+    __syncthreads();
+    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+        const i32 ps = rho[n];
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        const i64 deg = b - a;
+        const bool one_batch = deg <= (i64)nwv * kWave;
+        const i64 chunk = one_batch ? (deg + nwv - 1) / nwv : (i64)kWave;
+        i64 saving = 0, wi = 0;
+        i64 bg = 0, bg2 = 0;  // best move, and best move that keeps size(p) + size(n) <= Omega
+        i32 bp = -1, bp2 = -1;
+        i64 r0 = 0;
+        i32 L = 0, w = 0;
+        const i64 nw_n = nw[n];
+        for (int pass = 0; pass < npass; ++pass) {
+            const i32 lo = pass * R;
+            const i32 hi = min(nparts, lo + R);
+            for (i64 kb = a + (i64)wv * chunk; kb < b; kb += (i64)nwv * chunk) {
+                const int nb = (int)min((i64)chunk, b - kb);
+                if ((pass == 0) | !one_batch) {
+                    const i64 k = kb + lane;
+                    const int valid = (int)(lane < nb);
+                    const i32 e = inc[valid ? k : kb];
+                    r0 = he_off[e];
+                    const i32 Le = len[e], we = hw[e];
+                    L = valid ? Le : 0;
+                    w = valid ? we : 0;
+                    if (pass == 0) wi += w;
+                }
+                const i32 avg = wave_sum(L) / max(nb, 1);
+                if (avg <= 64)
+                    gains_group<16, 1, ONE_PASS>(nb, lane, pass, ps, lo, hi, partf, r0, L, w, saving, bins);
+                else if (avg <= 128)
+                    gains_group<8, 2, ONE_PASS>(nb, lane, pass, ps, lo, hi, partf, r0, L, w, saving, bins);
+                else if (avg <= 192)
+                    gains_group<6, 3, ONE_PASS>(nb, lane, pass, ps, lo, hi, partf, r0, L, w, saving, bins);
+                else
+                    gains_group<4, 4, ONE_PASS>(nb, lane, pass, ps, lo, hi, partf, r0, L, w, saving, bins);
+            }
+            if (pass == 0) {
+                saving = block_sum(saving, red);
+                wi = block_sum(wi, red);
+            } else {
+                __syncthreads();
+            }
+            // Only partitions with conn(n,p) > W_I(n) - saving(n) give a positive gain.
+            const i64 need = wi - saving;
+            const int used = hi - lo;
+            for (int sidx = threadIdx.x; sidx < used; sidx += blockDim.x) {
+                const u32 v = bins[sidx];
+                if (v == 0) continue;
+                bins[sidx] = 0;
+                if ((i64)v <= need) continue;
+                const i32 p = lo + sidx;
+                const i64 g = (i64)v - need;
+                const int fits = (int)(nw_n + psize[p] <= omega);
+                const bool t = lex_better(g, p, bg, bp);
+                bg = t ? g : bg;
+                bp = t ? p : bp;
+                const bool t2 = (fits & (int)lex_better(g, p, bg2, bp2)) != 0;
+                bg2 = t2 ? g : bg2;
+                bp2 = t2 ? p : bp2;
+            }
+            __syncthreads();
+        }
+        wave_lexmax_i64(bg, bp);
+        wave_lexmax_i64(bg2, bp2);
+        if (lane == 0) {
+            red_g[wv] = bg;
+            red_p[wv] = bp;
+            red_g2[wv] = bg2;
+            red_p2[wv] = bp2;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            const i64* rg = threadIdx.x == 0 ? red_g : red_g2;
+            const i32* rpp = threadIdx.x == 0 ? red_p : red_p2;
+            i64 G = rg[0];
+            i32 Pp = rpp[0];
+            for (int ww = 1; ww < nwv; ++ww) {
+                const i64 g2 = rg[ww];
+                const i32 p2 = rpp[ww];
+                const bool t = lex_better(g2, p2, G, Pp);
+                G = t ? g2 : G;
+                Pp = t ? p2 : Pp;
+            }
+            i32* md = threadIdx.x == 0 ? move_dst : move_dst_sa;
+            i64* mg = threadIdx.x == 0 ? move_gain : move_gain_sa;
+            md[n] = Pp;
+            mg[n] = Pp >= 0 ? G : 0;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_move_flags(i32 N, const i32* __restrict__ move_dst, i32* flag) {
     for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
         flag[n] = move_dst[n] >= 0 ? 1 : 0;
@@ -1076,12 +1234,13 @@ int bits_for(u64 v) {
 struct PhiBufs {
     i32 *part, *cnt, *cin, *len;
     i64 *psize, *pD;
-    unsigned short* part16;  // 16-bit copy of part when nparts <= 65,536, else null
+    unsigned short* part16;  // flagged 16-bit copy of part when nparts <= kGainsFlagParts, else null
 };
 
-__global__ void k_narrow16(i64 P, const i32* __restrict__ v, unsigned short* v16) {
+// 16-bit row copy for k_gains16: partition id, top bit set where pins(p,e) = 1.
+__global__ void k_narrow16(i64 P, const i32* __restrict__ v, const i32* __restrict__ cnt, unsigned short* v16) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
-        v16[i] = (unsigned short)v[i];
+        v16[i] = (unsigned short)((u32)v[i] | (cnt[i] == 1 ? 0x8000u : 0u));
 }
 
 PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
@@ -1092,7 +1251,7 @@ PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
     f.len = wsp<i32>(c, WS_PHI_LEN, (size_t)L.E + 1);
     f.psize = wsp<i64>(c, WS_PSIZE, nparts);
     f.pD = wsp<i64>(c, WS_PD, nparts);
-    f.part16 = nparts <= 65536 ? wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1) : nullptr;
+    f.part16 = nparts <= kGainsFlagParts ? wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1) : nullptr;
     return f;
 }
 
@@ -1106,9 +1265,10 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
     f.pD = wsp<i64>(c, WS_PD, nparts);
     build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len);
     f.part16 = nullptr;
-    if (nparts <= 65536 && L.P > 0) {
+    if (nparts <= kGainsFlagParts && L.P > 0) {
         f.part16 = wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1);
-        LAUNCH(c, KF_PHI, k_narrow16, grid_for(L.P, 256, c->num_cu * 8), 256, 0, L.P, (const i32*)f.part, f.part16);
+        LAUNCH(c, KF_PHI, k_narrow16, grid_for(L.P, 256, c->num_cu * 8), 256, 0, L.P, (const i32*)f.part,
+               (const i32*)f.cnt, f.part16);
     }
     HIPC(hipMemsetAsync(f.psize, 0, sizeof(i64) * nparts, c->stream));
     HIPC(hipMemsetAsync(f.pD, 0, sizeof(i64) * nparts, c->stream));
@@ -1147,10 +1307,14 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const size_t lds = sizeof(u32) * (size_t)R;
         const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 3 * 1024))));
         const int grid = (int)std::min<i64>(N, (i64)c->num_cu * per_cu * 2);
-        if (f.part16)  // half the bytes per row visit
-            LAUNCH(c, KF_GAINS, k_gains<unsigned short>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(),
-                   L.inc(), L.he_off(), (const unsigned short*)f.part16, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize,
-                   c->omega, mdst_any, mgain_any, mdst_sa, mgain_sa, R);
+        if (f.part16 && nparts <= R)  // half the bytes per row visit, one pass
+            LAUNCH(c, KF_GAINS, k_gains16<true>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
+                   L.he_off(), (const unsigned short*)f.part16, f.len, c->hw(), L.nw(), rho, f.psize, c->omega,
+                   mdst_any, mgain_any, mdst_sa, mgain_sa, R);
+        else if (f.part16)
+            LAUNCH(c, KF_GAINS, k_gains16<false>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
+                   L.he_off(), (const unsigned short*)f.part16, f.len, c->hw(), L.nw(), rho, f.psize, c->omega,
+                   mdst_any, mgain_any, mdst_sa, mgain_sa, R);
         else
             LAUNCH(c, KF_GAINS, k_gains<i32>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
                    L.he_off(), (const i32*)f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, mdst_any,
