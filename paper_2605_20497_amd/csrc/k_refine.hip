@@ -907,7 +907,8 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
 // part's list with an earlier sequence position.  Lists are as long as the
 // number of movers touching a part, usually a few, so a mover reads a few
 // events where the all-pairs kernel compares it with every mover of e.
-// For h-edges of at most cap pins; T = 2^tbits >= 2 * cap table slots.
+// For h-edges of at most cap pins; T = 2^tbits >= 2 * cap table slots.  The
+// table also carries e's row counts, so no search of the row is needed.
 struct InseqEv {
     i32 q;
     i32 link;  // ((next event + 1) << 1) | destination-pin flag of the mover
@@ -938,15 +939,14 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
     const i32* __restrict__ len, unsigned char* code, int cap, int tbits) {
-    // shared memory: cap movers, cap row parts, cap packed row counts, then
-    // T keys, T list heads, T packed row counts of the table's parts, and
-    // 2 * cap events
+    // shared memory: cap movers, then T keys, T list heads, T packed counts
+    // (pins | inbound pins << 16) of the table's parts, and 2 * cap events.
+    // The table holds e's row parts and the movers' destination parts: at
+    // most 2 * cap keys.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = 1 << tbits;
     MoverRec* mv = (MoverRec*)smem_raw;
-    i32* rp = (i32*)(mv + cap);
-    u32* rc = (u32*)(rp + cap);
-    i32* tkey = (i32*)(rc + cap);
+    i32* tkey = (i32*)(mv + cap);
     i32* thead = tkey + T;
     u32* tcnt = (u32*)(thead + T);
     InseqEv* ev = (InseqEv*)(tcnt + T);
@@ -956,13 +956,17 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
         const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
         if (b - a > (i64)cap) continue;
         const i32 L = len[e];
-        for (i32 r = lane; r < L; r += kWave) {
-            rp[r] = part[a + r];
-            rc[r] = (u32)cnt[a + r] | ((u32)cin[a + r] << 16);  // both <= |e| <= 4096
-        }
         for (int t = lane; t < T; t += kWave) {
             tkey[t] = -1;
             thead[t] = -1;
+        }
+        __syncthreads();
+        for (i32 r = lane; r < L; r += kWave) {  // the row parts are distinct
+            const i32 p = part[a + r];
+            const u32 cc = (u32)cnt[a + r] | ((u32)cin[a + r] << 16);  // both <= |e| <= 4096
+            int ins;
+            const i32 t = part_slot(tkey, tbits, p, ins);
+            tcnt[t] = cc;
         }
         int k = 0;
         for (i64 base = a; base < b; base += kWave) {
@@ -983,22 +987,15 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
             k += __popcll(mask);
         }
         __syncthreads();
-        // Table slots of the movers' parts, their row counts, and the events.
+        // Table slots of the movers' parts (a source part is in e's row; a
+        // destination part may be new, with no pins in e), and the events.
         for (int i = lane; i < k; i += kWave) {
             MoverRec me = mv[i];
             int ins_s, ins_d;
             const i32 ts = part_slot(tkey, tbits, me.ps, ins_s);
             const i32 td = part_slot(tkey, tbits, me.pd, ins_d);
-            if (ins_s) {
-                i32 ci;
-                const i32 c0 = lds_row(rp, rc, L, me.ps, ci);
-                tcnt[ts] = (u32)c0 | ((u32)ci << 16);
-            }
-            if (ins_d) {
-                i32 ci;
-                const i32 c0 = lds_row(rp, rc, L, me.pd, ci);
-                tcnt[td] = (u32)c0 | ((u32)ci << 16);
-            }
+            if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
+            if (ins_d) tcnt[td] = 0u;
             const i32 dj = me.slot & 1;
             const i32 ns = atomicExch(&thead[ts], 2 * i);
             const i32 nd = atomicExch(&thead[td], 2 * i + 1);
@@ -1467,8 +1464,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const int capl = std::min(cap, kInseqListMax);
         int tbits = 1;
         while ((1 << tbits) < 2 * capl) ++tbits;
-        const size_t lds_l = (sizeof(MoverRec) + 2 * sizeof(i32) + 2 * sizeof(InseqEv)) * capl +
-                             (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
+        const size_t lds_l = (sizeof(MoverRec) + 2 * sizeof(InseqEv)) * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
         LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, lds_l, L.E,
                (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl,
                tbits);
