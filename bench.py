@@ -7,9 +7,10 @@ HBM-resident tensors (on-device validation and incidence build), every
 coarsening level, and refinement of every level with Theta = 16 repetitions.
 
 Prints one JSON line: pins/s of the whole step (input pins / step time), the
-per-level pins/s, HIP-event times of the dominant kernel family with its
-roofline, and the serial oracle's rate on a bounded sample of the same
-workload family as the CPU baseline.
+per-level pins/s, the rooflines of the three largest kernels from HIP events
+over the timed steps (`roofline` is the one that takes the most time), the
+per-family breakdown, the batched job-stream leg, and the serial oracle's rate
+on a bounded sample of the same workload family as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -26,15 +27,23 @@ HBM_PEAK_GBS = 8000.0
 # The proposal kernel's histogram updates are 32-bit integer adds executed by
 # the LDS: at most one per bank per clock, 32 banks per CU, 256 CUs at 2.4 GHz.
 LDS_UPDATE_PEAK_GOPS = 256 * 32 * 2.4
+# Dense int8 MFMA peak of MI355X (no sparsity), in TOP/s.
+INT8_PEAK_TOPS = 5000.0
 
-# Measured HBM traffic of k_propose per launch on the bench workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by what the counters read
-# for a plain 256 MiB copy), valid only for the kernel sources they were taken
-# on (sha256 over the files below); otherwise traffic is reported as null.
-TRAFFIC_SOURCES = ["paper_2605_20497_amd/csrc/k_coarsen.hip", "paper_2605_20497_amd/csrc/dev_util.h",
-                   "paper_2605_20497_amd/csrc/hgp_internal.h"]
-TRAFFIC = {  # {sources_sha256: bytes per k_propose launch}
-    "ad259e73a71af4bd94eb9131f9627bbe1381be6e6ab47802a6d7a42249a700ea": 4027845045,
+# Measured HBM traffic per launch on the bench workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs (scaled by what the counters read for a plain
+# 256 MiB copy), valid only for the kernel sources they were taken on (sha256
+# over each kernel's files below); otherwise traffic is reported as null.
+_CSRC = "paper_2605_20497_amd/csrc/"
+TRAFFIC_SOURCES = {
+    "k_propose": [_CSRC + f for f in ("k_coarsen.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
+    "k_gains16": [_CSRC + f for f in ("k_refine.hip", "dev_util.h", "hgp_internal.h")],
+    "k_dense_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
+}
+TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
+    ("k_propose", "f6537ed8c5dda1c9e4c05243ee1ee74f3dc9818f0a4a84d0ddbeb35d89781205"): 8893054087,
+    ("k_gains16", "ef34a5b07bfed306dd6bee5ff39021c1019fecf56e3f0bf39e1a81ea50a204c9"): 3454187940,
+    ("k_dense_gemm", "a0811ddba2f56f46d6b18239e25d877793e7ca3346857c748c2e1d655fa4f5b8"): 1234917081,
 }
 
 
@@ -55,13 +64,17 @@ def _args():
     return ap.parse_args()
 
 
-def sources_sha256():
+def sources_sha256(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in TRAFFIC_SOURCES[kernel]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def traffic(kernel):
+    return TRAFFIC.get((kernel, sources_sha256(kernel)))
 
 
 def algorithmic_bytes(kernel, levels, pi):
@@ -163,11 +176,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # Timed steps record HIP events only around the dominant kernel (the
-    # roofline's launches); recording them around every launch would add
-    # about a sixth to the step.  One extra step after the timed region
+    # Timed steps record HIP events only around the three roofline kernels
+    # (proposal histogram, gains sweep, dense GEMM) and count the gains'
+    # row reads on the device; recording events around every launch would
+    # add about a sixth to the step.  One extra step after the timed region
     # records every family for the breakdown.
-    part = pkg.Partitioner(device=0, profile=True, profile_families=("propose",))
+    part = pkg.Partitioner(device=0, profile=True, profile_families=("propose", "gains", "dense_gemm"))
 
     def step():
         part.hgp_load_csr_device(hg.n_nodes, t_he_off, t_nsrc, t_pins, t_hw, t_nw)
@@ -213,32 +227,72 @@ def main():
     dom = max(fam, key=lambda k: fam[k][1])
     breakdown = {k: {"launches": v[0], "ms_per_step": round(v[1] * 1e-6, 3)}
                  for k, v in sorted(fam.items(), key=lambda kv: -kv[1][1])}
-    roof = None
-    prop = stats_timed.get("propose")  # HIP events over the timed steps
+    # Rooflines of the three largest kernels, from HIP events over the timed
+    # steps; `roofline` is the one that takes the most time.
+    card_lv = []
+    for lv in range(int(levels.shape[0])):
+        he_off = part.hgp_get_level_graph(lv, what=("he_off",))[0]
+        card_lv.append(np.diff(he_off).astype(np.int64))
+    work_timed = part.hgp_kernel_work()
+    roofs = {}
+    prop = stats_timed.get("propose")
+    dg = stats_timed.get("dense_gemm")
+    n_prop = int(round(prop[0] / args.steps)) if prop else 0
+    n_dense = int(round(dg[0] / args.steps)) if dg else 0
     if prop and prop[0] > 0:
-        # Per launch (one launch per coarsened level): histogram updates
-        # sum_e |e| (|e| - 1) of the level, and the compulsory HBM bytes.
-        launches = prop[0] / args.steps
+        # One launch per level on the histogram path (the first n_prop levels):
+        # histogram updates sum_e |e| (|e| - 1) and the compulsory HBM bytes.
         t_launch = prop[1] / prop[0] * 1e-9
-        per_lv = []
-        for lv in range(int(levels.shape[0])):
-            he_off = part.hgp_get_level_graph(lv, what=("he_off",))[0]
-            card = np.diff(he_off).astype(np.int64)
-            per_lv.append(int((card * (card - 1)).sum()))
-        # the last level is proposed on only when the loop stopped there
-        # because it merged nothing
-        updates = sum(per_lv[:int(round(launches))])
-        upd = updates / launches
+        upd = sum(int((c * (c - 1)).sum()) for c in card_lv[:n_prop]) / max(n_prop, 1)
         ach = upd / t_launch / 1e9
-        nbytes = algorithmic_bytes("propose", levels.tolist()[:int(round(launches))], part.pi) / launches
-        tr = TRAFFIC.get(sources_sha256())
-        roof = {"kernel": "k_propose", "bound": "alu", "achieved": round(ach, 2), "peak": LDS_UPDATE_PEAK_GOPS,
-                "unit": "Gop/s", "frac": round(ach / LDS_UPDATE_PEAK_GOPS, 5), "traffic": tr,
-                "op": "histogram update (32-bit LDS atomic add)", "ops_per_launch": int(upd),
-                "avg_launch_ms": round(t_launch * 1e3, 4),
-                "hbm_compulsory_bytes_per_launch": int(nbytes),
-                "hbm_compulsory_gbs": round(nbytes / t_launch / 1e9, 2),
-                "hbm_frac": round(nbytes / t_launch / 1e9 / HBM_PEAK_GBS, 5)}
+        nbytes = algorithmic_bytes("propose", levels.tolist()[:n_prop], part.pi) / max(n_prop, 1)
+        tr = traffic("k_propose")
+        roofs["k_propose"] = {
+            "kernel": "k_propose", "bound": "alu", "achieved": round(ach, 2), "peak": LDS_UPDATE_PEAK_GOPS,
+            "unit": "Gop/s", "frac": round(ach / LDS_UPDATE_PEAK_GOPS, 5), "traffic": tr,
+            "op": "histogram update (32-bit LDS atomic add)", "ops_per_launch": int(upd),
+            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(prop[1] * 1e-6 / args.steps, 3),
+            "hbm_compulsory_bytes_per_launch": int(nbytes),
+            "hbm_compulsory_gbs": round(nbytes / t_launch / 1e9, 2),
+            "hbm_frac": round(nbytes / t_launch / 1e9 / HBM_PEAK_GBS, 5)}
+    gn = stats_timed.get("gains")
+    if gn and gn[0] > 0 and work_timed.get("gains", 0) > 0:
+        # Phi row entries read (counted on the device): one bin update each,
+        # 2 bytes each from the 16-bit row copy.
+        t_launch = gn[1] / gn[0] * 1e-9
+        visits = work_timed["gains"] / gn[0]
+        ach = visits / t_launch / 1e9
+        roofs["k_gains16"] = {
+            "kernel": "k_gains16", "bound": "alu", "achieved": round(ach, 2), "peak": LDS_UPDATE_PEAK_GOPS,
+            "unit": "Gop/s", "frac": round(ach / LDS_UPDATE_PEAK_GOPS, 5), "traffic": traffic("k_gains16"),
+            "op": "row entry read + bin update (32-bit LDS atomic add)", "ops_per_launch": int(visits),
+            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(gn[1] * 1e-6 / args.steps, 3),
+            "row_bytes_gbs": round(2 * visits / t_launch / 1e9, 2)}
+    if dg and dg[0] > 0:
+        # int8 MACs of the dense proposal on its levels (the n_dense levels
+        # after the histogram ones): (planes + 1) products over the padded
+        # upper triangle of 128 x 128 tiles, K = E rounded up to 128.
+        hw = hg.hedge_w.astype(np.int64)
+        macs = 0
+        for lv in range(n_prop, n_prop + n_dense):
+            N, E = int(levels[lv, 0]), int(levels[lv, 1])
+            c = np.maximum(card_lv[lv], 1)
+            t = np.maximum(1, (hw[:E] << 16) // c)
+            tmax, planes = int(t.max()), 1
+            while planes <= 3 and (tmax >> (7 * planes)) != 0:
+                planes += 1
+            nt = (N + 127) // 128
+            epad = (((E + 31) // 32 + 3) // 4 * 4) * 32
+            macs += nt * (nt + 1) // 2 * 128 * 128 * epad * (planes + 1)
+        t_launch = dg[1] / dg[0] * 1e-9
+        ops = 2.0 * macs / max(n_dense, 1)
+        ach = ops / t_launch / 1e12
+        roofs["k_dense_gemm"] = {
+            "kernel": "k_dense_gemm", "bound": "mfma", "achieved": round(ach, 2), "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s", "frac": round(ach / INT8_PEAK_TOPS, 5), "traffic": traffic("k_dense_gemm"),
+            "op": "int8 MAC = 2 ops (v_mfma_i32_32x32x32_i8)", "ops_per_launch": int(ops),
+            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(dg[1] * 1e-6 / args.steps, 3)}
+    roof = max(roofs.values(), key=lambda r: r["ms_per_step"]) if roofs else None
 
     out = {
         "metric": "pins/s per coarsen+refine level & % HBM peak; batched vs plain jobs/s, p50/p99",
@@ -252,9 +306,10 @@ def main():
         "levels": per_level,
         "kernels": breakdown,
         "dominant_kernel": dom,
+        "rooflines": list(roofs.values()),
         "kernel_time_share": round(total_ns * 1e-9 / dt, 4) if dt > 0 else None,
         "kernels_note": "per-family times from one extra fully profiled step; the timed steps record "
-                        "events around the dominant kernel only",
+                        "events around the three roofline kernels only",
         "roofline": roof,
     }
     part.close()

@@ -204,6 +204,16 @@ hgp_status hgp_refine_rep(hgp_ctx* ctx, int32_t* rho, int32_t n_parts, int32_t r
 hgp_status hgp_kernel_stats(hgp_ctx* ctx, const char** names, int64_t* launches, int64_t* total_ns, int32_t* count);
 hgp_status hgp_reset_kernel_stats(hgp_ctx* ctx);
 
+/*
+ * Work units counted on the device while a family is profiled, in the same
+ * family order as hgp_kernel_stats (work[i] for 0 <= i < *count; NULL work
+ * queries *count).  Counted so far: "gains", the Phi row entries read by the
+ * 16-bit gains sweep (sum over nodes n and e in I(n) of lambda(e), per pass);
+ * every other family reads 0.  hgp_reset_kernel_stats clears them.  Waits for
+ * the context's stream.
+ */
+hgp_status hgp_kernel_work(hgp_ctx* ctx, int64_t* work, int32_t* count);
+
 /* Per-level phase times of the last hgp_coarsen / hgp_refine (HIP events on
  * the context's stream): out[2*l] = coarsen ns of level l, out[2*l+1] =
  * refine ns of level l. */

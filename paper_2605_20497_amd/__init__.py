@@ -90,6 +90,7 @@ def lib():
             "hgp_refine_rep": (C.c_int, [P, P, i32, i32, P, P, P, P, P, P, P, P]),
             "hgp_kernel_stats": (C.c_int, [P, C.POINTER(C.c_char_p), P, P, C.POINTER(i32)]),
             "hgp_reset_kernel_stats": (C.c_int, [P]),
+            "hgp_kernel_work": (C.c_int, [P, P, C.POINTER(i32)]),
             "hgp_level_times": (C.c_int, [P, P, i64]),
             "hgp_run_jobs": (C.c_int, [C.POINTER(hgp_options), C.POINTER(hgp_job), i64, i32, i64]),
         }
@@ -104,12 +105,13 @@ def lib():
 # Kernel families in the library's order (hgp_kernel_stats names).
 KERNEL_FAMILIES = ["validate", "transpose", "radix_sort", "scan", "level_stats", "propose", "match", "isolated",
                    "gamma", "contract_edges", "pack", "phi", "part_stats", "gains", "moves", "chains", "rank",
-                   "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense"]
+                   "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm"]
 
 EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
             "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
             "hgp_get_proposal", "hgp_get_level_graph", "hgp_get_partition", "hgp_get_phi", "hgp_evaluate",
-            "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_level_times", "hgp_run_jobs"]
+            "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_kernel_work", "hgp_level_times",
+            "hgp_run_jobs"]
 
 
 def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16, seed=0, device=0, flags=0):
@@ -338,6 +340,15 @@ class Partitioner:
 
     def hgp_reset_kernel_stats(self):
         self._chk(lib().hgp_reset_kernel_stats(self.h))
+
+    def hgp_kernel_work(self):
+        """Device-counted work units per kernel family while profiled
+        (gains: Phi row entries read); {family name: units}."""
+        cnt = C.c_int32()
+        self._chk(lib().hgp_kernel_work(self.h, None, C.byref(cnt)))
+        work = np.zeros(cnt.value, np.int64)
+        self._chk(lib().hgp_kernel_work(self.h, _p(work), C.byref(cnt)))
+        return {KERNEL_FAMILIES[i]: int(work[i]) for i in range(min(cnt.value, len(KERNEL_FAMILIES)))}
 
     def hgp_level_times(self):
         out = np.zeros(2 * self.nlevels, np.int64)

@@ -23,7 +23,7 @@ void hip_check(hipError_t e, const char* what) {
 static const char* const kKfNames[KF_COUNT] = {
     "validate", "transpose", "radix_sort", "scan", "level_stats", "propose", "match", "isolated",
     "gamma", "contract_edges", "pack", "phi", "part_stats", "gains", "moves", "chains",
-    "rank", "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense"};
+    "rank", "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm"};
 
 const char* kf_name(int kf) { return (kf >= 0 && kf < KF_COUNT) ? kKfNames[kf] : "?"; }
 
@@ -67,6 +67,16 @@ void prof_end(Ctx* c, int kf) {
     hipEvent_t e = prof_event(c);
     HIPC(hipEventRecord(e, c->stream));
     c->prof.open.push_back({kf, {c->prof.cur_begin, e}});
+}
+
+unsigned long long* prof_work(Ctx* c, int kf) {
+    if (!prof_on(c, kf)) return nullptr;
+    if (!c->prof.work) {
+        c->prof.b_work = c->alloc(sizeof(unsigned long long) * KF_COUNT);
+        c->prof.work = (unsigned long long*)c->prof.b_work.p;
+        HIPC(hipMemsetAsync(c->prof.work, 0, sizeof(unsigned long long) * KF_COUNT, c->stream));
+    }
+    return c->prof.work + kf;
 }
 
 Buf Ctx::alloc(size_t bytes) {
@@ -313,6 +323,7 @@ void hgp_destroy(hgp_ctx* h) {
         c->levels.clear();
         c->release(c->b_hw);
         for (auto& b : c->ws) c->release(b);
+        c->release(c->prof.b_work);
         (void)hipStreamSynchronize(c->stream);
         for (auto e : c->prof.pool) (void)hipEventDestroy(e);
         if (c->host_scalars) (void)hipHostFree(c->host_scalars);
@@ -658,6 +669,21 @@ hgp_status hgp_reset_kernel_stats(hgp_ctx* h) {
     API_BEGIN(h)
     prof_flush(c);
     for (int i = 0; i < KF_COUNT; ++i) c->prof.launches[i] = c->prof.ns[i] = 0;
+    if (c->prof.work) HIPC(hipMemsetAsync(c->prof.work, 0, sizeof(unsigned long long) * KF_COUNT, c->stream));
+    API_END
+}
+
+hgp_status hgp_kernel_work(hgp_ctx* h, int64_t* work, int32_t* count) {
+    API_BEGIN(h)
+    if (count) *count = KF_COUNT;
+    if (work) {
+        unsigned long long w[KF_COUNT] = {0};
+        if (c->prof.work) {
+            HIPC(hipMemcpyAsync(w, c->prof.work, sizeof(w), hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipStreamSynchronize(c->stream));
+        }
+        for (int i = 0; i < KF_COUNT; ++i) work[i] = (int64_t)w[i];
+    }
     API_END
 }
 

@@ -35,13 +35,17 @@ void hip_check(hipError_t e, const char* what);
 enum Kf {
     KF_VALIDATE, KF_TRANSPOSE, KF_SORT, KF_SCAN, KF_LEVEL_STATS, KF_PROPOSE, KF_MATCH, KF_ISOLATED,
     KF_GAMMA, KF_CONTRACT_EDGES, KF_PACK, KF_PHI, KF_PART_STATS, KF_GAINS, KF_MOVES, KF_CHAINS,
-    KF_RANK, KF_INSEQ, KF_EVENTS, KF_SELECT, KF_APPLY, KF_PROJECT, KF_EVAL, KF_MISC, KF_PROPOSE_DENSE, KF_COUNT
+    KF_RANK, KF_INSEQ, KF_EVENTS, KF_SELECT, KF_APPLY, KF_PROJECT, KF_EVAL, KF_MISC, KF_PROPOSE_DENSE, KF_DENSE_GEMM,
+    KF_COUNT
 };
 const char* kf_name(int kf);
 
 struct Ctx;
 void prof_begin(Ctx* c, int kf);
 void prof_end(Ctx* c, int kf);
+// Device counter of family kf's work units (e.g. row entries visited), or
+// null when the family is not profiled; kernels add to it only when non-null.
+unsigned long long* prof_work(Ctx* c, int kf);
 
 #define LAUNCH(ctx, kf, kern, grid, block, shmem, ...)                                  \
     do {                                                                                \
@@ -84,6 +88,8 @@ struct Prof {
     i64 ns[KF_COUNT] = {0};
     size_t used = 0;
     hipEvent_t cur_begin = nullptr;
+    unsigned long long* work = nullptr;  // device, KF_COUNT counters; allocated when first asked for
+    Buf b_work;
 };
 
 struct Ctx {

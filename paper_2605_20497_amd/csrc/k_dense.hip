@@ -314,13 +314,13 @@ void propose_dense(Ctx* c, const Level& L, int Pi, const unsigned long long* sta
     const dim3 grid(pairs, ksplit);
     switch (NP) {
         case 1:
-            LAUNCH(c, KF_PROPOSE_DENSE, k_dense_gemm<1>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
+            LAUNCH(c, KF_DENSE_GEMM, k_dense_gemm<1>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
             break;
         case 2:
-            LAUNCH(c, KF_PROPOSE_DENSE, k_dense_gemm<2>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
+            LAUNCH(c, KF_DENSE_GEMM, k_dense_gemm<2>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
             break;
         default:
-            LAUNCH(c, KF_PROPOSE_DENSE, k_dense_gemm<3>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
+            LAUNCH(c, KF_DENSE_GEMM, k_dense_gemm<3>, grid, 256, 0, ntile, W4, wsplit, A, D, dig, Epad, part, (i64)Npad, ib);
             break;
     }
     const int grid_s = (int)std::min<i64>(N, (i64)c->num_cu * 8);

@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
     i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
     const unsigned short* __restrict__ partf, const i32* __restrict__ len, const i32* __restrict__ hw,
     const i32* __restrict__ nw, const i32* __restrict__ rho, const i64* __restrict__ psize, i64 omega,
-    i32* move_dst, i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R) {
+    i32* move_dst, i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R, unsigned long long* work) {
     extern __shared__ u32 bins[];  // R bins: one pass covers R consecutive partition ids
     __shared__ i64 red[16];
     __shared__ i64 red_g[16], red_g2[16];
@@ -323,6 +323,7 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
         i32 bp = -1, bp2 = -1;
         i64 r0 = 0;
         i32 L = 0, w = 0;
+        u64 visits = 0;  // row entries this wave read (work counter when profiling)
         const i64 nw_n = nw[n];
         for (int pass = 0; pass < npass; ++pass) {
             const i32 lo = pass * R;
@@ -339,7 +340,9 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
                     w = valid ? we : 0;
                     if (pass == 0) wi += w;
                 }
-                const i32 avg = wave_sum(L) / max(nb, 1);
+                const i32 tot = wave_sum(L);
+                visits += (u64)tot;
+                const i32 avg = tot / max(nb, 1);
                 if (avg <= 64)
                     gains_group<16, 1, ONE_PASS>(nb, lane, pass, ps, lo, hi, partf, r0, L, w, saving, bins);
                 else if (avg <= 128)
@@ -401,6 +404,7 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
             md[n] = Pp;
             mg[n] = Pp >= 0 ? G : 0;
         }
+        if ((work != nullptr) & (lane == 0)) atomicAdd(work, (unsigned long long)visits);
         __syncthreads();
     }
 }
@@ -1307,11 +1311,11 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         if (f.part16 && nparts <= R)  // half the bytes per row visit, one pass
             LAUNCH(c, KF_GAINS, k_gains16<true>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
                    L.he_off(), (const unsigned short*)f.part16, f.len, c->hw(), L.nw(), rho, f.psize, c->omega,
-                   mdst_any, mgain_any, mdst_sa, mgain_sa, R);
+                   mdst_any, mgain_any, mdst_sa, mgain_sa, R, prof_work(c, KF_GAINS));
         else if (f.part16)
             LAUNCH(c, KF_GAINS, k_gains16<false>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
                    L.he_off(), (const unsigned short*)f.part16, f.len, c->hw(), L.nw(), rho, f.psize, c->omega,
-                   mdst_any, mgain_any, mdst_sa, mgain_sa, R);
+                   mdst_any, mgain_any, mdst_sa, mgain_sa, R, prof_work(c, KF_GAINS));
         else
             LAUNCH(c, KF_GAINS, k_gains<i32>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
                    L.he_off(), (const i32*)f.part, f.cnt, f.len, c->hw(), L.nw(), rho, f.psize, c->omega, mdst_any,

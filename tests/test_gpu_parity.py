@@ -250,3 +250,22 @@ def test_large_hedges_both_inseq_kernels():
     hg = W.random_small(1200, 260, 420, 7, max_src=2, max_hw=3, max_nw=2, min_card=40)
     assert int(np.diff(hg.he_off).max()) > 256
     _compare_runs(hg, 64, 400, label="large-hedges")
+
+
+def test_gains_work_counter():
+    # the profiled gains sweep counts the Phi row entries it reads:
+    # sum over n and e in I(n) of lambda(e) = sum over e of |e| lambda(e)
+    from paper_2605_20497_amd import Partitioner
+    hg = W.random_small(400, 380, 10, 33, max_src=2, max_hw=3, max_nw=2)
+    rho0 = np.random.default_rng(5).integers(0, 9, size=400).astype(np.int32)
+    g = Partitioner(profile=True, profile_families=("gains",))
+    g.load(hg)
+    g.hgp_set_limits(10 ** 6, 10 ** 6, 0)
+    g.hgp_reset_kernel_stats()
+    g.hgp_refine_rep(rho0, 9, 0)
+    work = g.hgp_kernel_work()
+    card = np.diff(hg.he_off)
+    lam = np.array([len(set(rho0[hg.pins[hg.he_off[e]:hg.he_off[e + 1]]].tolist())) for e in range(hg.n_hedges)])
+    assert work["gains"] == int((card * lam).sum())
+    assert all(v == 0 for k, v in work.items() if k != "gains")
+    g.close()
