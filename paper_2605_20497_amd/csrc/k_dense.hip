@@ -81,21 +81,26 @@ __device__ __forceinline__ u32 word_of(const uint4& q, int s) {
 
 // One workgroup per (upper-triangle tile pair, K split): 4 waves, each a
 // 64 x 64 block of the 128 x 128 tile as 2 x 2 MFMA blocks of 32 x 32, for NP
-// digit planes of eta and one plane of inter.  The h-edges are taken 128 at a
-// time (4 words per bit row): the workgroup stages the tile's 2 x 128 rows of
-// A and D bits and the digits of those h-edges in shared memory, double
-// buffered, so the next chunk's loads overlap the current chunk's products.
-// Lane l holds row (l mod 32) of its A-side block and column (l mod 32) of its
-// B-side block, for the 16 h-edges 16*(l / 32) .. +15 of each 32-edge step;
-// accumulator entry i is output (8*(i/4) + 4*(l/32) + i mod 4, l mod 32).  The
-// packed partial (eta << ib) | inter of each pair is written for both
+// digit planes of eta and one plane of inter.  Bit rows are loaded 128
+// h-edges at a time (4 words per row; thread t holds rows t and t + 256 of
+// the tile's A rows, D rows, A columns, D columns).  For each 32 h-edges the
+// threads expand their words once into bytes in shared memory (A columns as
+// 0x00 / 0xFF masks, ready to be ANDed with the digit bytes), double
+// buffered, and every wave reads its MFMA operands from there: the expansion
+// is done once per workgroup instead of once per wave that uses a row.
+// Lane l holds row (l mod 32) of its A-side block and column (l mod 32) of
+// its B-side block, for the 16 h-edges 16*(l / 32) .. +15 of each 32-edge
+// step; accumulator entry i is output (8*(i/4) + 4*(l/32) + i mod 4, l mod 32).
+// The packed partial (eta << ib) | inter of each pair is written for both
 // orientations into the split's own N x N slice.
+constexpr int kRowB = 48;  // bytes per expanded row: 32 h-edges + 16 spare (conflict-free 16-byte reads)
+
 template <int NP>
-__global__ __launch_bounds__(256) void k_dense_gemm(int ntile, i32 W4, i32 wsplit, const u32* __restrict__ A,
+__global__ __launch_bounds__(256, NP <= 2 ? 2 : 1) void k_dense_gemm(int ntile, i32 W4, i32 wsplit, const u32* __restrict__ A,
                                                     const u32* __restrict__ D, const signed char* __restrict__ dig,
                                                     i32 Epad, u64* part, i64 Npad, int ib) {
-    __shared__ uint4 sbits[2][4][kTile];   // [buffer][A rows, D rows, A cols, D cols][tile row]
-    __shared__ uint4 sdig[2][NP][8];       // [buffer][plane][16-byte group of the 128 h-edges]
+    __shared__ __align__(16) unsigned char sx[2][4][kTile][kRowB];  // [buffer][A rows, D rows, A cols, D cols]
+    __shared__ uint4 sdig[2][NP][8];  // [buffer][plane][16-byte group of the 128 h-edges]
     int ti = 0, rem = blockIdx.x;
     while (rem >= ntile - ti) {
         rem -= ntile - ti;
@@ -108,7 +113,10 @@ __global__ __launch_bounds__(256) void k_dense_gemm(int ntile, i32 W4, i32 wspli
     const int wv = t >> 6, l = t & 63, lr = l & 31, kh = l >> 5;
     const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;  // the wave's block within the tile
     const i64 R0 = (i64)ti * kTile, C0 = (i64)tj * kTile;
-    // staging: thread t moves rows t and t + 256 of the 512 (matrix, row) pairs
+    // thread t expands row t & 127 of matrix t >> 7 (A or D rows) and of
+    // matrix 2 + (t >> 7) (A or D columns); the A-column half is waves 0-1
+    const int mrow = t >> 7, rr = t & (kTile - 1);
+    const bool amask = mrow == 0;
     auto src = [&](int q, i32 w) -> const uint4* {
         const int which = q >> 7, row = q & (kTile - 1);
         const u32* M = (which & 1) ? D : A;
@@ -124,66 +132,75 @@ __global__ __launch_bounds__(256) void k_dense_gemm(int ntile, i32 W4, i32 wspli
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acc[p][a][b][i] = 0;
+    uint4 x0 = make_uint4(0u, 0u, 0u, 0u), x1 = make_uint4(0u, 0u, 0u, 0u);
     if (wbeg < wend) {
-        const uint4 x0 = *src(t, wbeg), x1 = *src(t + 256, wbeg);
-        sbits[0][t >> 7][t & (kTile - 1)] = x0;
-        sbits[0][(t + 256) >> 7][(t + 256) & (kTile - 1)] = x1;
+        x0 = *src(t, wbeg);
+        x1 = *src(t + 256, wbeg);
         if (t < NP * 8) sdig[0][t >> 3][t & 7] = *(const uint4*)&dig[(i64)(t >> 3) * Epad + (i64)wbeg * 32 + (t & 7) * 16];
     }
-    __syncthreads();
-    int cur = 0;
+    int dcur = 0, buf = 0;
     for (i32 w = wbeg; w < wend; w += 4) {
         const bool more = w + 4 < wend;
-        uint4 y0, y1, yd;
+        uint4 y0 = x0, y1 = x1, yd = make_uint4(0u, 0u, 0u, 0u);
         if (more) {
             y0 = *src(t, w + 4);
             y1 = *src(t + 256, w + 4);
             if (t < NP * 8) yd = *(const uint4*)&dig[(i64)(t >> 3) * Epad + (i64)(w + 4) * 32 + (t & 7) * 16];
         }
-        uint4 ar[2], dr[2], ac[2], dc[2];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            ar[b] = sbits[cur][0][wr + b * 32 + lr];
-            dr[b] = sbits[cur][1][wr + b * 32 + lr];
-            ac[b] = sbits[cur][2][wc + b * 32 + lr];
-            dc[b] = sbits[cur][3][wc + b * 32 + lr];
-        }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            v4i dg[NP];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const uint4 q = sdig[cur][p][2 * s + kh];
-                dg[p] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+            {  // expand word s of the thread's two rows
+                const u32 wa = word_of(x0, s), wb = word_of(x1, s);
+                const v4i e0 = spread16(wa & 0xFFFFu), e1 = spread16(wa >> 16);
+                v4i f0 = spread16(wb & 0xFFFFu), f1 = spread16(wb >> 16);
+                if (amask) {
+                    f0 = (f0 << 8) - f0;  // 0x00 / 0xFF bytes
+                    f1 = (f1 << 8) - f1;
+                }
+                *(v4i*)&sx[buf][mrow][rr][0] = e0;
+                *(v4i*)&sx[buf][mrow][rr][16] = e1;
+                *(v4i*)&sx[buf][2 + mrow][rr][0] = f0;
+                *(v4i*)&sx[buf][2 + mrow][rr][16] = f1;
             }
-            v4i fa[2], fd[2], fdc[2], fb[NP][2];
+            __syncthreads();
+            v4i fa[2], mk[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                fa[b] = spread16((word_of(ar[b], s) >> (16 * kh)) & 0xFFFFu);
-                fd[b] = spread16((word_of(dr[b], s) >> (16 * kh)) & 0xFFFFu);
-                fdc[b] = spread16((word_of(dc[b], s) >> (16 * kh)) & 0xFFFFu);
-                const v4i x = spread16((word_of(ac[b], s) >> (16 * kh)) & 0xFFFFu);
-                const v4i m = (x << 8) - x;  // 0x00 / 0xFF bytes
-#pragma unroll
-                for (int p = 0; p < NP; ++p) fb[p][b] = m & dg[p];
+                fa[b] = *(const v4i*)&sx[buf][0][wr + b * 32 + lr][kh * 16];
+                mk[b] = *(const v4i*)&sx[buf][2][wc + b * 32 + lr][kh * 16];
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int p = 0; p < NP; ++p) {  // eta planes: digit-masked columns, one plane at a time
+                const uint4 q = sdig[dcur][p][2 * s + kh];
+                const v4i dg = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+                const v4i fb0 = mk[0] & dg, fb1 = mk[1] & dg;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    acc[p][a][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb0, acc[p][a][0], 0, 0, 0);
+                    acc[p][a][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb1, acc[p][a][1], 0, 0, 0);
+                }
+            }
+            {  // inter
+                v4i fd[2], fdc[2];
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-#pragma unroll
-                    for (int p = 0; p < NP; ++p)
-                        acc[p][a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[p][b], acc[p][a][b], 0, 0, 0);
-                    acc[NP][a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fd[a], fdc[b], acc[NP][a][b], 0, 0, 0);
+                    fd[b] = *(const v4i*)&sx[buf][1][wr + b * 32 + lr][kh * 16];
+                    fdc[b] = *(const v4i*)&sx[buf][3][wc + b * 32 + lr][kh * 16];
                 }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[NP][a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fd[a], fdc[b], acc[NP][a][b], 0, 0, 0);
+            }
+            buf ^= 1;
         }
-        if (more) {
-            sbits[cur ^ 1][t >> 7][t & (kTile - 1)] = y0;
-            sbits[cur ^ 1][(t + 256) >> 7][(t + 256) & (kTile - 1)] = y1;
-            if (t < NP * 8) sdig[cur ^ 1][t >> 3][t & 7] = yd;
-        }
-        __syncthreads();
-        cur ^= 1;
+        // the next chunk's digits: read after the next expansion's barrier;
+        // the other buffer's last readers passed this chunk's barriers
+        if (more & (t < NP * 8)) sdig[dcur ^ 1][t >> 3][t & 7] = yd;
+        dcur ^= 1;
+        x0 = y0;
+        x1 = y1;
     }
     const i64 r0 = R0 + wr, c0 = C0 + wc;
     u64* out = part + (i64)blockIdx.y * Npad * Npad;
