@@ -819,6 +819,7 @@ struct MoverRec {
     i32 q, ps, pd, slot;  // slot = (pin offset in e) << 1 | destination flag
 };
 constexpr int kInseqListMax = 256;  // largest h-edge of the event-list kernel
+constexpr int kInseqU = 4;          // row entries / pins per lane loaded together
 
 __device__ __forceinline__ i32 lds_row(const i32* __restrict__ rp, const u32* __restrict__ rc, i32 L, i32 p,
                                        i32& ci) {
@@ -965,30 +966,59 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
             thead[t] = -1;
         }
         __syncthreads();
-        for (i32 r = lane; r < L; r += kWave) {  // the row parts are distinct
-            const i32 p = part[a + r];
-            const u32 cc = (u32)cnt[a + r] | ((u32)cin[a + r] << 16);  // both <= |e| <= 4096
-            int ins;
-            const i32 t = part_slot(tkey, tbits, p, ins);
-            tcnt[t] = cc;
+        // Row entries and pins kInseqU * 64 at a time: every round of
+        // dependent loads (pin -> position -> part and destination) is issued
+        // for the whole group before any is used.
+        for (i32 r0 = 0; r0 < L; r0 += kInseqU * kWave) {  // the row parts are distinct
+            i32 pp[kInseqU];
+            u32 cc[kInseqU];
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                const i32 r = r0 + u * kWave + lane;
+                const int in = (int)(r < L);
+                pp[u] = in ? part[a + r] : -1;
+                cc[u] = in ? ((u32)cnt[a + r] | ((u32)cin[a + r] << 16)) : 0u;  // both <= |e| <= 4096
+            }
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                if (pp[u] >= 0) {
+                    int ins;
+                    const i32 t = part_slot(tkey, tbits, pp[u], ins);
+                    tcnt[t] = cc[u];
+                }
+            }
         }
         int k = 0;
-        for (i64 base = a; base < b; base += kWave) {
-            const i64 j = base + lane;
-            const int inb = (int)(j < b);
-            const i32 m = pins[inb ? j : a];
-            const i32 q = posn[m];
-            const int is_mv = inb & (int)(q < M);
-            const u64 mask = __ballot(is_mv);
-            if (is_mv) {
-                MoverRec r;
-                r.q = q;
-                r.ps = rho[m];
-                r.pd = move_dst[m];
-                r.slot = (i32)((j - a) << 1) | (i32)(j >= d0);
-                mv[k + __popcll(mask & lt_mask)] = r;
+        for (i64 base = a; base < b; base += kInseqU * kWave) {
+            i32 mm[kInseqU], qq[kInseqU], ps[kInseqU], pd[kInseqU];
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                const i64 j = base + u * kWave + lane;
+                mm[u] = j < b ? pins[j] : -1;
             }
-            k += __popcll(mask);
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) qq[u] = mm[u] >= 0 ? posn[mm[u]] : M;
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                const int mvr = (int)(qq[u] < M);
+                ps[u] = mvr ? rho[mm[u]] : 0;
+                pd[u] = mvr ? move_dst[mm[u]] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                const i64 j = base + u * kWave + lane;
+                const int is_mv = (int)(qq[u] < M);
+                const u64 mask = __ballot(is_mv);
+                if (is_mv) {
+                    MoverRec r;
+                    r.q = qq[u];
+                    r.ps = ps[u];
+                    r.pd = pd[u];
+                    r.slot = (i32)((j - a) << 1) | (i32)(j >= d0);
+                    mv[k + __popcll(mask & lt_mask)] = r;
+                }
+                k += __popcll(mask);
+            }
         }
         __syncthreads();
         // Table slots of the movers' parts (a source part is in e's row; a

@@ -27,7 +27,8 @@ def _golden(name):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("name", ["rand-4k-e32", "rand-64k-e192", "netlist-500k", "layered-256k-e256"])
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name", ["rand-4k-e32", "rand-64k-e192", "netlist-500k", "layered-256k-e256", "conv-6.9m"])
 def test_full_size_against_oracle_digests(name):
     from paper_2605_20497_amd import Partitioner
     gold = _golden(name)
