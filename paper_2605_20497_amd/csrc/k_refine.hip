@@ -600,6 +600,47 @@ __global__ void k_round_end(unsigned long long* rs) {
     rs[1] = 0;
 }
 
+constexpr i64 kChainCompactMax = 1 << 16;  // largest move count of k_chain_compact1
+
+// First step of a chain round for at most kChainCompactMax moves, in one
+// workgroup: fold the previous round's links into the totals (the
+// k_round_end step; a round that linked nothing ends the rounds), then the
+// moves without a predecessor, their exclusive scan and compaction, and the
+// reset of the acceptance accumulators.  Replaces three launches per round.
+__global__ __launch_bounds__(1024) void k_chain_compact1(i32 M, int round, unsigned long long* rs,
+                                                         const i32* __restrict__ pred, i32* pls, i32* cl, u64* accG,
+                                                         i32* accN) {
+    __shared__ i32 red[16];
+    __shared__ int active;
+    if (threadIdx.x == 0) {
+        unsigned long long a = rs[0];
+        if (a && round > 0) {
+            if (rs[1] == 0) a = 0;
+            rs[2] += rs[1];
+            rs[1] = 0;
+            rs[0] = a;
+        }
+        active = (int)(a != 0);
+    }
+    __syncthreads();
+    if (!active) return;
+    i32 carry = 0;
+    for (i64 base = 0; base < M; base += blockDim.x) {
+        const i64 i = base + threadIdx.x;
+        const i32 v = i < M ? (pred[i] < 0 ? 1 : 0) : 0;
+        i32 tot;
+        const i32 ex = block_excl_scan(v, red, &tot);
+        if (i < M) {
+            pls[i] = carry + ex;
+            if (v) cl[carry + ex] = (i32)i;
+            accG[i] = 0;
+            accN[i] = -1;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) pls[M] = carry;
+}
+
 // All chain rounds in one workgroup, for move counts so small that per-round
 // launches and host checks would dominate (beyond a few hundred moves the
 // windowed proposals, one wave per move, need the whole GPU).  Same steps,
@@ -1406,23 +1447,32 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     if (M <= kChainSingleMax)
         LAUNCH(c, KF_CHAINS, k_chain_rounds, 1, 1024, 0, (i32)M, rs, pred, succ, pl, pls, cl, accG, accN, spd, segb,
                sege, sg, snw, snin, snode, prop, propG);
+    // Up to kChainCompactMax moves, a round's first three steps and the
+    // previous round's end run as one single-workgroup launch.
+    const bool one = M <= kChainCompactMax;
     for (int round = 0; round < kChainRounds && M > kChainSingleMax; ++round) {
-        LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
-        scan_excl_i32(c, pl, pls, M);
-        LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
+        if (one) {
+            LAUNCH(c, KF_CHAINS, k_chain_compact1, 1, 1024, 0, (i32)M, round, rs, pred, pls, cl, accG, accN);
+        } else {
+            LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
+            scan_excl_i32(c, pl, pls, M);
+            LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
+        }
         LAUNCH(c, KF_CHAINS, k_chain_propose, wblocks, 256, 0, (i32)M, rs, succ, spd, segb, sege, pls, cl, sg, snw,
                snin, snode, prop, propG);
         LAUNCH(c, KF_CHAINS, k_chain_accept_a, nbM, 256, 0, (i32)M, rs, prop, propG, accG);
         LAUNCH(c, KF_CHAINS, k_chain_accept_b, nbM, 256, 0, (i32)M, rs, prop, propG, accG, snode, accN);
         LAUNCH(c, KF_CHAINS, k_chain_link, nbM, 256, 0, (i32)M, rs, prop, propG, accG, accN, snode, pred, succ);
-        LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);
+        if (!one) LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);
         // Later rounds of a finished chain build are no-ops; stop issuing them.
         if (round == 1 || round == 3 || round == 7) {
-            i64 active = 0;
-            read_back(c, rs, &active, 1, 8);
-            if (!active) break;
+            i64 st[2] = {0, 0};
+            read_back(c, rs, st, 2, 8);
+            // with `one` this round's links are folded by the next round's first launch
+            if (!st[0] || (one && st[1] == 0)) break;
         }
     }
+    if (one && M > kChainSingleMax) LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);  // fold the last round
 
     // Chains: cycles, heads, ranks.
     const int K = bits_for((u64)M) + 1;
