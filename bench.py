@@ -7,7 +7,7 @@ HBM-resident tensors (on-device validation and incidence build), every
 coarsening level, and refinement of every level with Theta = 16 repetitions.
 
 Prints one JSON line: pins/s of the whole step (input pins / step time), the
-per-level pins/s, the rooflines of the three largest kernels from HIP events
+per-level pins/s, the rooflines of the largest kernels from HIP events
 over the timed steps (`roofline` is the one that takes the most time), the
 per-family breakdown, the batched job-stream leg, and the serial oracle's rate
 on a bounded sample of the same workload family as the CPU baseline.
@@ -39,6 +39,7 @@ TRAFFIC_SOURCES = {
     "k_propose": [_CSRC + f for f in ("k_coarsen.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
     "k_gains16": [_CSRC + f for f in ("k_refine.hip", "dev_util.h", "hgp_internal.h")],
     "k_dense_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
+    "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     ("k_propose", "f6537ed8c5dda1c9e4c05243ee1ee74f3dc9818f0a4a84d0ddbeb35d89781205"): 8893054087,
@@ -176,12 +177,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # Timed steps record HIP events only around the three roofline kernels
-    # (proposal histogram, gains sweep, dense GEMM) and count the gains'
-    # row reads on the device; recording events around every launch would
+    # Timed steps record HIP events only around the roofline kernels
+    # (proposal histogram, gains sweep, the two dense GEMMs) and count the
+    # gains' row reads on the device; recording events around every launch would
     # add about a sixth to the step.  One extra step after the timed region
     # records every family for the breakdown.
-    part = pkg.Partitioner(device=0, profile=True, profile_families=("propose", "gains", "dense_gemm"))
+    part = pkg.Partitioner(device=0, profile=True, profile_families=("propose", "gains", "dense_gemm", "gains_gemm"))
 
     def step():
         part.hgp_load_csr_device(hg.n_nodes, t_he_off, t_nsrc, t_pins, t_hw, t_nw)
@@ -227,8 +228,8 @@ def main():
     dom = max(fam, key=lambda k: fam[k][1])
     breakdown = {k: {"launches": v[0], "ms_per_step": round(v[1] * 1e-6, 3)}
                  for k, v in sorted(fam.items(), key=lambda kv: -kv[1][1])}
-    # Rooflines of the three largest kernels, from HIP events over the timed
-    # steps; `roofline` is the one that takes the most time.
+    # Rooflines of the largest kernels, from HIP events over the timed steps;
+    # `roofline` is the one that takes the most time.
     card_lv = []
     for lv in range(int(levels.shape[0])):
         he_off = part.hgp_get_level_graph(lv, what=("he_off",))[0]
@@ -238,7 +239,6 @@ def main():
     prop = stats_timed.get("propose")
     dg = stats_timed.get("dense_gemm")
     n_prop = int(round(prop[0] / args.steps)) if prop else 0
-    n_dense = int(round(dg[0] / args.steps)) if dg else 0
     if prop and prop[0] > 0:
         # One launch per level on the histogram path (the first n_prop levels):
         # histogram updates sum_e |e| (|e| - 1) and the compulsory HBM bytes.
@@ -269,29 +269,32 @@ def main():
             "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(gn[1] * 1e-6 / args.steps, 3),
             "row_bytes_gbs": round(2 * visits / t_launch / 1e9, 2)}
     if dg and dg[0] > 0:
-        # int8 MACs of the dense proposal on its levels (the n_dense levels
-        # after the histogram ones): (planes + 1) products over the padded
-        # upper triangle of 128 x 128 tiles, K = E rounded up to 128.
-        hw = hg.hedge_w.astype(np.int64)
-        macs = 0
-        for lv in range(n_prop, n_prop + n_dense):
-            N, E = int(levels[lv, 0]), int(levels[lv, 1])
-            c = np.maximum(card_lv[lv], 1)
-            t = np.maximum(1, (hw[:E] << 16) // c)
-            tmax, planes = int(t.max()), 1
-            while planes <= 3 and (tmax >> (7 * planes)) != 0:
-                planes += 1
-            nt = (N + 127) // 128
-            epad = (((E + 31) // 32 + 3) // 4 * 4) * 32
-            macs += nt * (nt + 1) // 2 * 128 * 128 * epad * (planes + 1)
+        # int8 MACs issued by the dense proposal's products (counted by the
+        # library from the padded sizes: planes + 1 products over the upper
+        # triangle of 128 x 128 tiles, K = E rounded up to 128)
+        macs = work_timed.get("dense_gemm", 0)
         t_launch = dg[1] / dg[0] * 1e-9
-        ops = 2.0 * macs / max(n_dense, 1)
+        ops = 2.0 * macs / dg[0]
         ach = ops / t_launch / 1e12
         roofs["k_dense_gemm"] = {
             "kernel": "k_dense_gemm", "bound": "mfma", "achieved": round(ach, 2), "peak": INT8_PEAK_TOPS,
             "unit": "TOP/s", "frac": round(ach / INT8_PEAK_TOPS, 5), "traffic": traffic("k_dense_gemm"),
             "op": "int8 MAC = 2 ops (v_mfma_i32_32x32x32_i8)", "ops_per_launch": int(ops),
             "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(dg[1] * 1e-6 / args.steps, 3)}
+    gg = stats_timed.get("gains_gemm")
+    if gg and gg[0] > 0:
+        # int8 MACs issued by the dense in-isolation moves (counted by the
+        # library: weight planes x padded nodes x padded partitions x E
+        # rounded up to 128)
+        macs = work_timed.get("gains_gemm", 0)
+        t_launch = gg[1] / gg[0] * 1e-9
+        ops = 2.0 * macs / gg[0]
+        ach = ops / t_launch / 1e12
+        roofs["k_conn_gemm"] = {
+            "kernel": "k_conn_gemm", "bound": "mfma", "achieved": round(ach, 2), "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s", "frac": round(ach / INT8_PEAK_TOPS, 5), "traffic": traffic("k_conn_gemm"),
+            "op": "int8 MAC = 2 ops (v_mfma_i32_32x32x32_i8)", "ops_per_launch": int(ops),
+            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(gg[1] * 1e-6 / args.steps, 3)}
     roof = max(roofs.values(), key=lambda r: r["ms_per_step"]) if roofs else None
 
     out = {
@@ -309,7 +312,7 @@ def main():
         "rooflines": list(roofs.values()),
         "kernel_time_share": round(total_ns * 1e-9 / dt, 4) if dt > 0 else None,
         "kernels_note": "per-family times from one extra fully profiled step; the timed steps record "
-                        "events around the three roofline kernels only",
+                        "events around the roofline kernels only",
         "roofline": roof,
     }
     part.close()

@@ -67,7 +67,10 @@ typedef struct hgp_options {
                               passes while every neighbourhood fits a few hashed passes.
                               bit 1: use the dense (MFMA product) proposal wherever it fits;
                               bit 2: never use it; by default it is chosen per level by an
-                              estimate of both proposals' time.  Results are identical. */
+                              estimate of both proposals' time.
+                              bit 3: compute the in-isolation moves of refinement as a dense
+                              (MFMA) product wherever it fits; bit 4: never; by default per
+                              level by an estimate.  Results are identical in every case. */
     uint32_t profile_families; /* with profile = 1: bit i times only kernel family i (the order of
                                 * hgp_kernel_stats' names); 0 = every family */
     int32_t reserved[5];
@@ -205,12 +208,13 @@ hgp_status hgp_kernel_stats(hgp_ctx* ctx, const char** names, int64_t* launches,
 hgp_status hgp_reset_kernel_stats(hgp_ctx* ctx);
 
 /*
- * Work units counted on the device while a family is profiled, in the same
- * family order as hgp_kernel_stats (work[i] for 0 <= i < *count; NULL work
- * queries *count).  Counted so far: "gains", the Phi row entries read by the
- * 16-bit gains sweep (sum over nodes n and e in I(n) of lambda(e), per pass);
- * every other family reads 0.  hgp_reset_kernel_stats clears them.  Waits for
- * the context's stream.
+ * Work units counted while a family is profiled, in the same family order as
+ * hgp_kernel_stats (work[i] for 0 <= i < *count; NULL work queries *count):
+ * "gains", the Phi row entries read by the 16-bit gains sweep (sum over nodes
+ * n and e in I(n) of lambda(e), per pass; counted on the device);
+ * "dense_gemm" and "gains_gemm", the int8 multiply-adds issued by the two
+ * dense products (padded sizes); every other family reads 0.
+ * hgp_reset_kernel_stats clears them.  Waits for the context's stream.
  */
 hgp_status hgp_kernel_work(hgp_ctx* ctx, int64_t* work, int32_t* count);
 

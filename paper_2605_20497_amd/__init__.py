@@ -105,7 +105,8 @@ def lib():
 # Kernel families in the library's order (hgp_kernel_stats names).
 KERNEL_FAMILIES = ["validate", "transpose", "radix_sort", "scan", "level_stats", "propose", "match", "isolated",
                    "gamma", "contract_edges", "pack", "phi", "part_stats", "gains", "moves", "chains", "rank",
-                   "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm"]
+                   "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm",
+                   "gains_gemm"]
 
 EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
             "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
@@ -181,14 +182,16 @@ class Partitioner:
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
                  use_torch: bool = True, stream=None, sparse_proposal: bool = False, profile_families=(),
-                 dense_proposal=None):
+                 dense_proposal=None, dense_gains=None):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
         opt.device, opt.pi, opt.theta, opt.seed, opt.profile = device, pi, theta, seed, int(profile)
         # flags: bit 0 hashed proposal everywhere; bit 1 dense (MFMA) proposal wherever it
-        # fits; bit 2 never dense; neither of bits 1-2 = chosen per level by cost
-        opt.flags = (1 if sparse_proposal else 0) | {None: 0, True: 2, False: 4}[dense_proposal]
+        # fits; bit 2 never dense; neither of bits 1-2 = chosen per level by cost; bits 3-4
+        # the same choice for the in-isolation moves of refinement
+        opt.flags = ((1 if sparse_proposal else 0) | {None: 0, True: 2, False: 4}[dense_proposal]
+                     | {None: 0, True: 8, False: 16}[dense_gains])
         # kernel families to time (names as in hgp_kernel_stats); empty = all
         opt.profile_families = sum(1 << KERNEL_FAMILIES.index(f) for f in profile_families)
         self._keep = []

@@ -23,7 +23,8 @@ void hip_check(hipError_t e, const char* what) {
 static const char* const kKfNames[KF_COUNT] = {
     "validate", "transpose", "radix_sort", "scan", "level_stats", "propose", "match", "isolated",
     "gamma", "contract_edges", "pack", "phi", "part_stats", "gains", "moves", "chains",
-    "rank", "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm"};
+    "rank", "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm",
+    "gains_gemm"};
 
 const char* kf_name(int kf) { return (kf >= 0 && kf < KF_COUNT) ? kKfNames[kf] : "?"; }
 
@@ -67,6 +68,10 @@ void prof_end(Ctx* c, int kf) {
     hipEvent_t e = prof_event(c);
     HIPC(hipEventRecord(e, c->stream));
     c->prof.open.push_back({kf, {c->prof.cur_begin, e}});
+}
+
+void prof_add_work(Ctx* c, int kf, i64 units) {
+    if (prof_on(c, kf)) c->prof.host_work[kf] += units;
 }
 
 unsigned long long* prof_work(Ctx* c, int kf) {
@@ -381,8 +386,8 @@ hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int
     else fill_i32(c, L0.nw(), 1, n_nodes);
     i64* dres = (i64*)c->ws_get(0 + 150, 8 * sizeof(i64));
     validate_graph(c, n_nodes, n_hedges, L0.he_off(), L0.he_nsrc(), L0.pins(), c->hw(), L0.nw(), P, dres);
-    i64 r[4];
-    read_back(c, dres, r, 4, 8);
+    i64 r[5];
+    read_back(c, dres, r, 5, 8);
     if (r[0] != 0) {
         const hgp_status st = (r[0] == 128) ? HGP_E_UNSUPPORTED : HGP_E_INVALID;
         for (auto& X : c->levels) c->free_level(X);
@@ -397,6 +402,7 @@ hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int
     c->total_hw = r[1];
     c->total_nw = r[2];
     c->max_card = (i32)std::max<i64>(1, r[3]);
+    c->max_hw = std::max<i64>(1, r[4]);
     build_incidence(c, L0);
     c->sync();
     c->loaded = true;
@@ -668,7 +674,7 @@ hgp_status hgp_kernel_stats(hgp_ctx* h, const char** names, int64_t* launches, i
 hgp_status hgp_reset_kernel_stats(hgp_ctx* h) {
     API_BEGIN(h)
     prof_flush(c);
-    for (int i = 0; i < KF_COUNT; ++i) c->prof.launches[i] = c->prof.ns[i] = 0;
+    for (int i = 0; i < KF_COUNT; ++i) c->prof.launches[i] = c->prof.ns[i] = c->prof.host_work[i] = 0;
     if (c->prof.work) HIPC(hipMemsetAsync(c->prof.work, 0, sizeof(unsigned long long) * KF_COUNT, c->stream));
     API_END
 }
@@ -682,7 +688,7 @@ hgp_status hgp_kernel_work(hgp_ctx* h, int64_t* work, int32_t* count) {
             HIPC(hipMemcpyAsync(w, c->prof.work, sizeof(w), hipMemcpyDeviceToHost, c->stream));
             HIPC(hipStreamSynchronize(c->stream));
         }
-        for (int i = 0; i < KF_COUNT; ++i) work[i] = (int64_t)w[i];
+        for (int i = 0; i < KF_COUNT; ++i) work[i] = (int64_t)w[i] + c->prof.host_work[i];
     }
     API_END
 }

@@ -36,7 +36,7 @@ enum Kf {
     KF_VALIDATE, KF_TRANSPOSE, KF_SORT, KF_SCAN, KF_LEVEL_STATS, KF_PROPOSE, KF_MATCH, KF_ISOLATED,
     KF_GAMMA, KF_CONTRACT_EDGES, KF_PACK, KF_PHI, KF_PART_STATS, KF_GAINS, KF_MOVES, KF_CHAINS,
     KF_RANK, KF_INSEQ, KF_EVENTS, KF_SELECT, KF_APPLY, KF_PROJECT, KF_EVAL, KF_MISC, KF_PROPOSE_DENSE, KF_DENSE_GEMM,
-    KF_COUNT
+    KF_GAINS_GEMM, KF_COUNT
 };
 const char* kf_name(int kf);
 
@@ -46,6 +46,9 @@ void prof_end(Ctx* c, int kf);
 // Device counter of family kf's work units (e.g. row entries visited), or
 // null when the family is not profiled; kernels add to it only when non-null.
 unsigned long long* prof_work(Ctx* c, int kf);
+// Adds work units known on the host (e.g. the MACs of a dense product) to
+// family kf's counter when the family is profiled.
+void prof_add_work(Ctx* c, int kf, i64 units);
 
 #define LAUNCH(ctx, kf, kern, grid, block, shmem, ...)                                  \
     do {                                                                                \
@@ -90,6 +93,7 @@ struct Prof {
     hipEvent_t cur_begin = nullptr;
     unsigned long long* work = nullptr;  // device, KF_COUNT counters; allocated when first asked for
     Buf b_work;
+    i64 host_work[KF_COUNT] = {0};
 };
 
 struct Ctx {
@@ -106,6 +110,7 @@ struct Ctx {
     i32 k = 0;
     i64 total_nw = 0, total_hw = 0;
     i32 max_card = 1;  // largest input h-edge; bounds every level
+    i64 max_hw = 1;    // largest h-edge weight
     bool force_hash_propose = false;  // testing: use the sparse proposal at every level
 
     Buf b_hw;  // h-edge weights, shared by every level (h-edges keep their id)
@@ -173,7 +178,10 @@ void build_incidence(Ctx* c, Level& L);
 // Coarse pins of every h-edge through gamma, deduplicated, src' = gamma(src) \ dst'.
 void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out);
 // Phi rows at the h-edge offsets: part / cnt / cnt_in, row length in len[E].
-void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len);
+// Phi rows of every h-edge at its pin offset; with `single`, one byte per pin
+// slot that is 1 when pins(rho(m), e) = 1 for the slot's pin m.
+void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len,
+               unsigned char* single = nullptr);
 
 // ---------------------------------------------------------------------------
 // Coarsening launchers (k_coarsen.hip).
@@ -184,6 +192,12 @@ bool dense_proposal_fits(i32 N, i32 E, u64 max_t);
 bool prefer_dense_proposal(const Ctx* c, i32 N, i32 E, u64 max_t, u64 sum_card_sq);
 void propose_dense(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, u64 max_t, i32* cand,
                    u64* score);  // builds levels[lv+1] or leaves levels unchanged if no merge
+// Dense (MFMA) in-isolation moves for small levels; see k_dense.hip.  `single`
+// holds one byte per pin slot (pins(rho(m), e) = 1), `part` / `len` the Phi rows.
+bool use_dense_gains(const Ctx* c, const Level& L, i32 nparts);
+void gains_dense(Ctx* c, const Level& L, const i32* rho, i32 nparts, const i32* part, const i32* len,
+                 const unsigned char* single, const i64* psize, i32* mdst_any, i64* mgain_any, i32* mdst_sa,
+                 i64* mgain_sa);
 
 // ---------------------------------------------------------------------------
 // Refinement launchers (k_refine.hip).

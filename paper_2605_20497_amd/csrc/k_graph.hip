@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_validate_edges(i32 N, i32 E, const i64*
                                                         i64 P, unsigned long long* out) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
-    unsigned long long err = 0, wsum = 0, cmax = 0;
+    unsigned long long err = 0, wsum = 0, cmax = 0, wmax = 0;
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
         const i64 a = he_off[e], b = he_off[e + 1];
         if (a < 0 || b > P || b < a) { err |= VE_OFFSETS; continue; }
@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_validate_edges(i32 N, i32 E, const i64*
         const i32 w = hw ? hw[e] : 1;
         if (w < 1) err |= VE_WEIGHT;
         if (lane == 0) wsum += (unsigned long long)(w > 0 ? w : 0);
+        wmax = wmax > (unsigned long long)(w > 0 ? w : 0) ? wmax : (unsigned long long)(w > 0 ? w : 0);
         const i32 ns = he_nsrc[e];
         if (ns < 0 || ns > card) { err |= VE_NSRC; continue; }
         const i64 d0 = a + ns;
@@ -68,10 +69,12 @@ __global__ __launch_bounds__(256) void k_validate_edges(i32 N, i32 E, const i64*
     err = wave_or(err);
     wsum = wave_sum(wsum);
     cmax = wave_max(cmax);
+    wmax = wave_max(wmax);
     if (lane == 0) {
         if (err) atomicOr(&out[0], err);
         atomicAdd(&out[1], wsum);
         atomicMax(&out[3], cmax);
+        atomicMax(&out[4], wmax);
     }
 }
 
@@ -207,9 +210,14 @@ __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict
 // pins(p,e) and pins_in(p,e) of one h-edge per block: sort (rho(pin), is_dst)
 // in shared memory and run-length count.  Rows are written at the h-edge's pin
 // offset, ascending p; len[e] = lambda(e).
+// With `single` non-null, also writes one byte per pin slot: 1 when the
+// pin's partition holds no other pin of the h-edge (pins(rho(m), e) = 1).
+// Shared memory then holds two more arrays (the unsorted keys and the row of
+// each sorted position).
 __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
                                              const i32* __restrict__ pins, const i32* __restrict__ rho,
-                                             i32* part, i32* cnt, i32* cnt_in, i32* len) {
+                                             i32* part, i32* cnt, i32* cnt_in, i32* len, unsigned char* single,
+                                             int npad_max) {
     extern __shared__ u32 sm[];
     __shared__ i32 red[16];
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
@@ -219,8 +227,12 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
         u32* keys = sm;
         i32* c_all = (i32*)(sm + npad);
         i32* c_in = c_all + npad;
+        u32* orig = sm + 3 * npad_max;                // unsorted keys (with `single`)
+        i32* rowat = (i32*)(sm + 4 * npad_max);       // row of each sorted position
         for (int i = threadIdx.x; i < npad; i += blockDim.x) {
-            keys[i] = i < card ? (((u32)rho[pins[a + i]] << 1) | (i >= ns ? 1u : 0u)) : 0xFFFFFFFFu;
+            const u32 k = i < card ? (((u32)rho[pins[a + i]] << 1) | (i >= ns ? 1u : 0u)) : 0xFFFFFFFFu;
+            keys[i] = k;
+            if (single) orig[i] = k;
             c_all[i] = 0;
             c_in[i] = 0;
         }
@@ -239,6 +251,7 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
                 if (head) part[a + r] = (i32)(kc >> 1);
                 atomicAdd(&c_all[r], 1);
                 if (kc & 1u) atomicAdd(&c_in[r], 1);
+                if (single) rowat[i] = r;
             }
             rows += tot;
         }
@@ -246,6 +259,19 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
         for (int r = threadIdx.x; r < rows; r += blockDim.x) {
             cnt[a + r] = c_all[r];
             cnt_in[a + r] = c_in[r];
+        }
+        if (single) {
+            for (int i = threadIdx.x; i < card; i += blockDim.x) {
+                const u32 k = orig[i];
+                int lo = 0, hi = card;  // first sorted position with key >= k (the key is present)
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int lt = (int)(keys[mid] < k);
+                    lo = lt ? mid + 1 : lo;
+                    hi = lt ? hi : mid;
+                }
+                single[a + i] = (unsigned char)(c_all[rowat[lo]] == 1 ? 1 : 0);
+            }
         }
         if (threadIdx.x == 0) len[e] = rows;
         __syncthreads();
@@ -262,7 +288,7 @@ int bits_for(u64 v) {
 
 void validate_graph(Ctx* c, i32 N, i32 E, const i64* he_off, const i32* he_nsrc, const i32* pins, const i32* hw,
                     const i32* nw, i64 P, i64* d_out) {
-    HIPC(hipMemsetAsync(d_out, 0, 4 * sizeof(i64), c->stream));
+    HIPC(hipMemsetAsync(d_out, 0, 5 * sizeof(i64), c->stream));
     if (E > 0)
         LAUNCH(c, KF_VALIDATE, k_validate_edges, grid_for(E, 4, c->num_cu * 16), 256, 0, N, E, he_off, he_nsrc,
                pins, hw, P, (unsigned long long*)d_out);
@@ -322,11 +348,12 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
                (const i64*)out.he_off(), (const i32*)tmp, out.pins());
 }
 
-void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len) {
+void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len,
+               unsigned char* single) {
     if (L.E == 0) return;
     const int npad = next_pow2(c->max_card);
-    LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * 3 * npad, L.E, L.he_off(),
-           L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len);
+    LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * (single ? 5 : 3) * npad, L.E,
+           L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, npad);
 }
 
 }  // namespace hgp

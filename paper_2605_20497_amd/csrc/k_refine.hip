@@ -20,7 +20,8 @@ enum {
     WS_LRS = 112, WS_CSTART = 113, WS_SEQN = 114, WS_SEQS = 115, WS_SEQD = 116, WS_POSN = 117, WS_GSEQ = 118,
     WS_EVK = 119, WS_EVK2 = 120, WS_EVI = 121, WS_EVI2 = 122, WS_EVDS = 123, WS_EVDD = 124, WS_ES = 125,
     WS_ED = 126, WS_SEX = 127, WS_DEX = 128, WS_SEGST = 129, WS_DVQ = 130, WS_CEX = 131, WS_VEX = 132,
-    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137, WS_CODE = 138, WS_PHI_PART16 = 139
+    WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137, WS_CODE = 138, WS_PHI_PART16 = 139,
+    WS_SINGLE = 140
 };
 
 // rstats: [0] active chain rounds flag, [1] links this round, [2] total links,
@@ -1327,7 +1328,7 @@ PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
     return f;
 }
 
-PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
+PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsigned char* single = nullptr) {
     PhiBufs f;
     f.part = wsp<i32>(c, WS_PHI_PART, (size_t)L.P + 1);
     f.cnt = wsp<i32>(c, WS_PHI_CNT, (size_t)L.P + 1);
@@ -1335,7 +1336,7 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts) {
     f.len = wsp<i32>(c, WS_PHI_LEN, (size_t)L.E + 1);
     f.psize = wsp<i64>(c, WS_PSIZE, nparts);
     f.pD = wsp<i64>(c, WS_PD, nparts);
-    build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len);
+    build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len, single);
     f.part16 = nullptr;
     if (nparts <= kGainsFlagParts && L.P > 0) {
         f.part16 = wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1);
@@ -1362,7 +1363,11 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     const int nbN = grid_for(N, 256, c->num_cu * 8);
     // With `reuse`, rho is unchanged since the previous repetition (it applied
     // nothing): its pins rows, sizes, D and both move variants still hold.
-    PhiBufs f = reuse ? phi_bufs(c, L, nparts) : phi_and_parts(c, L, rho, nparts);
+    // Small levels take the moves from a dense MFMA product, which needs one
+    // byte per pin slot from the Phi kernel (pins(rho(m), e) = 1).
+    const bool dense_gains = !reuse && use_dense_gains(c, L, nparts);
+    unsigned char* single = dense_gains ? wsp<unsigned char>(c, WS_SINGLE, (size_t)(L.P > 0 ? L.P : 1)) : nullptr;
+    PhiBufs f = reuse ? phi_bufs(c, L, nparts) : phi_and_parts(c, L, rho, nparts, single);
     unsigned long long* rs = wsp<unsigned long long>(c, WS_RSTATS, 8);
     HIPC(hipMemsetAsync(rs, 0, 8 * sizeof(u64), c->stream));
     LAUNCH(c, KF_PART_STATS, k_initial_violations, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, f.psize,
@@ -1374,7 +1379,9 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i32* mdst_sa = wsp<i32>(c, WS_MDST_SA, N);
     i64* mgain_sa = wsp<i64>(c, WS_MGAIN_SA, N);
     const bool size_aware = rep >= theta / 2;
-    if (!reuse) {
+    if (dense_gains) {
+        gains_dense(c, L, rho, nparts, f.part, f.len, single, f.psize, mdst_any, mgain_any, mdst_sa, mgain_sa);
+    } else if (!reuse) {
         const int R = (int)std::min<i64>(16384, std::max<i64>(64, nparts));
         const size_t lds = sizeof(u32) * (size_t)R;
         const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 3 * 1024))));

@@ -11,18 +11,19 @@ from paper_2605_20497_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _gpu(Pi=4, theta=16, seed=0, profile=False, sparse=False, dense=None):
+def _gpu(Pi=4, theta=16, seed=0, profile=False, sparse=False, dense=None, dense_gains=None):
     from paper_2605_20497_amd import Partitioner
     return Partitioner(pi=Pi, theta=theta, seed=seed, profile=profile, sparse_proposal=sparse,
-                       dense_proposal=dense)
+                       dense_proposal=dense, dense_gains=dense_gains)
 
 
-def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label="", sparse=False, dense=None):
+def _compare_runs(hg, omega, delta, k=0, Pi=4, theta=16, seed=0, label="", sparse=False, dense=None,
+                  dense_gains=None):
     print("case", label, "N", hg.n_nodes, "E", hg.n_hedges, "P", hg.n_pins, "omega", omega, "delta", delta,
-          "k", k, "sparse", sparse, "dense", dense, flush=True)
+          "k", k, "sparse", sparse, "dense", dense, "dense_gains", dense_gains, flush=True)
     og = oracle.Graph(hg)
     res = og.partition(omega, delta, k=k, Pi=Pi, theta=theta, seed=seed)
-    g = _gpu(Pi, theta, seed, sparse=sparse, dense=dense)
+    g = _gpu(Pi, theta, seed, sparse=sparse, dense=dense, dense_gains=dense_gains)
     g.load(hg)
     g.hgp_set_limits(omega, delta, k)
     nl = g.hgp_coarsen()
@@ -268,4 +269,39 @@ def test_gains_work_counter():
     lam = np.array([len(set(rho0[hg.pins[hg.he_off[e]:hg.he_off[e + 1]]].tolist())) for e in range(hg.n_hedges)])
     assert work["gains"] == int((card * lam).sum())
     assert all(v == 0 for k, v in work.items() if k != "gains")
+    g.close()
+
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=lambda c: "n%d-e%d-s%d" % (c[0], c[1], c[3]))
+def test_small_random_dense_gains(case):
+    # every level's in-isolation moves through the MFMA product (weights up to 4)
+    n, e, card, seed, msrc, mhw, mnw, omega, delta = case
+    hg = W.random_small(n, e, card, seed, max_src=msrc, max_hw=mhw, max_nw=mnw)
+    _compare_runs(hg, omega, delta, label="dense-gains-%d" % seed, dense_gains=True)
+
+
+def test_dense_gains_snn_netlist_large_weights():
+    hg = W.random_snn(4096, 95, 6)
+    _compare_runs(hg, 128, 1024, label="snn-4k-dense-gains", dense_gains=True)
+    hg = W.netlist(6000, 6600, 2, 300, 2.827, 256, 0.9, 8, seed=9, k=8, delta=1 << 15)
+    _compare_runs(hg, hg.omega, hg.delta, k=8, label="netlist-6k-k8-dense-gains", dense_gains=True)
+    # h-edge weights up to 300,000: three 7-bit digit planes
+    hg = W.random_small(700, 800, 40, 21, max_src=2, max_hw=300000, max_nw=3)
+    _compare_runs(hg, 48, 400, label="heavy-weights-dense-gains", dense_gains=True)
+
+
+def test_dense_gains_rep_step():
+    # one repetition with an arbitrary partition: moves equal the oracle's
+    hg = W.random_small(400, 380, 10, 33, max_src=2, max_hw=3, max_nw=2)
+    og = oracle.Graph(hg)
+    rho0 = np.random.default_rng(2).integers(0, 9, size=400).astype(np.int32)
+    ev = og.evaluate(rho0, 9)
+    omega, delta = int(ev["max_size"]) + 2, int(ev["max_inbound"]) + 1
+    g = _gpu(dense_gains=True)
+    g.load(hg)
+    g.hgp_set_limits(omega, delta, 0)
+    for rep in (0, 11):
+        odst, ogain = og.moves(rho0, 9, rep, 16, omega)
+        grho, gd = g.hgp_refine_rep(rho0, 9, rep)
+        assert np.array_equal(gd["move_dst"], odst) and np.array_equal(gd["move_gain"], ogain)
     g.close()
