@@ -116,27 +116,28 @@ __device__ __forceinline__ DivU64 noise_div(const unsigned long long* stats) {
 // walks that space with stride 64, kProposeU loads in flight at a time, so a
 // wave keeps many loads outstanding whatever the h-edge sizes.
 constexpr int kProposeU = 8;
-constexpr int kProposeWaves = 4;
+constexpr int kProposeWaves = 4;       // waves per block with a 64 KiB histogram
+constexpr int kProposeWavesBig = 8;    // waves per block with a 128 KiB histogram (one block per CU)
 constexpr int kScanVec = 2;  // 16-byte vectors of bins per thread per step of the bin scan
 // Batches whose segments average at least kLongSegment pins are instead swept
 // by propose_group, several h-edges at a time.
 constexpr int kLongSegment = 32;
 
-template <typename BIN>
+template <typename BIN, int WAVES>
 struct SegTable {
-    i32 start[kProposeWaves][kWave];    // first flat index of the lane's segment
-    i32 src_end[kProposeWaves][kWave];  // flat index where its destinations begin
-    i64 sbase[kProposeWaves][kWave];    // pin position = base + flat index
-    i64 dbase[kProposeWaves][kWave];
-    BIN add[kProposeWaves][kWave];      // per source pin
-    BIN add_in[kProposeWaves][kWave];   // per destination pin
+    i32 start[WAVES][kWave];    // first flat index of the lane's segment
+    i32 src_end[WAVES][kWave];  // flat index where its destinations begin
+    i64 sbase[WAVES][kWave];    // pin position = base + flat index
+    i64 dbase[WAVES][kWave];
+    BIN add[WAVES][kWave];      // per source pin
+    BIN add_in[WAVES][kWave];   // per destination pin
 };
 
 // The sweep's offset tables and the scan's queues are never live together.
-template <typename BIN>
+template <typename BIN, int WAVES>
 union ProposeShared {
-    SegTable<BIN> tab;
-    SelQueue<BIN> q[kProposeWaves];
+    SegTable<BIN, WAVES> tab;
+    SelQueue<BIN> q[WAVES];
 };
 
 // Histogram allocation in bins: R rounded up to whole scan vectors of a block.
@@ -204,8 +205,8 @@ __device__ __forceinline__ void propose_group(int nb, int lane, i32 n, i32 lo, i
     }
 }
 
-template <typename BIN, int PI, typename PIN>
-__global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
+template <typename BIN, int PI, typename PIN, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_propose(
     i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
     const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const PIN* __restrict__ pins,
     const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(kProposeWaves * kWave) void k_propose(
     uint4* bins4 = (uint4*)smem_raw;
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
-    __shared__ ProposeShared<BIN> sh;
+    __shared__ ProposeShared<BIN, WAVES> sh;
     __shared__ unsigned long long s_floor;
     SelNode sn;
     sn.seed = seed;
@@ -884,12 +885,17 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
         return;
     }
     // Bins per pass: all neighbour ids at once when they fit 64 KiB of LDS,
-    // otherwise 64 KiB worth per pass; smaller histograms let more blocks share
-    // a CU.
-    const int rmax = 65536 / (int)sizeof(BIN);
+    // otherwise 128 KiB worth per pass in one 8-wave block per CU (half the
+    // passes: each pass re-reads the sources and the pass bounds); smaller
+    // histograms let more blocks share a CU.
+    const int r64 = 65536 / (int)sizeof(BIN);
+    const bool big = L.N > r64;
+    const int rmax = big ? 2 * r64 : r64;
+    const int waves = big ? kProposeWavesBig : kProposeWaves;
     const int R = (int)std::min<i64>(rmax, std::max<i64>(64, L.N));
     const size_t lds = sizeof(BIN) * (size_t)propose_bins_alloc(R);
-    const size_t lds_all = lds + sizeof(ProposeShared<BIN>) + 256;
+    const size_t lds_all =
+        lds + (big ? sizeof(ProposeShared<BIN, kProposeWavesBig>) : sizeof(ProposeShared<BIN, kProposeWaves>)) + 256;
     const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / lds_all)));
     const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu * 2);
     const int npass = (int)ceil_div(L.N, R);
@@ -902,22 +908,27 @@ void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* st
     // Ids of at most 65,536 nodes are read from the level's 16-bit pin
     // mirror: half the bytes per pin visit.
     const unsigned short* pins16 = (const unsigned short*)L.b_pins16.p;
+#define HGP_PROPW(PIV, PINT, PINS, WV)                                                                             \
+    LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV, PINT, WV>), grid, WV * kWave, lds, L.N, L.inc_off(), L.inc_nin(),  \
+           L.inc(), L.he_off(), L.he_nsrc(), PINS, c->hw(), L.nw(), c->omega, c->delta, c->opt.seed, stats, ib,  \
+           cand, score, R, bnd)
 #define HGP_PROP(PIV)                                                                                              \
     case PIV:                                                                                                      \
-        if (pins16)                                                                                                \
-            LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV, unsigned short>), grid, kProposeWaves * kWave, lds, L.N,    \
-                   L.inc_off(), L.inc_nin(), L.inc(), L.he_off(), L.he_nsrc(), pins16, c->hw(), L.nw(), c->omega,  \
-                   c->delta, c->opt.seed, stats, ib, cand, score, R, bnd);                                         \
+        if (pins16 && waves == kProposeWavesBig)                                                                   \
+            HGP_PROPW(PIV, unsigned short, pins16, kProposeWavesBig);                                              \
+        else if (pins16)                                                                                           \
+            HGP_PROPW(PIV, unsigned short, pins16, kProposeWaves);                                                 \
+        else if (waves == kProposeWavesBig)                                                                        \
+            HGP_PROPW(PIV, i32, L.pins(), kProposeWavesBig);                                                       \
         else                                                                                                       \
-            LAUNCH(c, KF_PROPOSE, (k_propose<BIN, PIV, i32>), grid, kProposeWaves * kWave, lds, L.N, L.inc_off(),  \
-                   L.inc_nin(), L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta,   \
-                   c->opt.seed, stats, ib, cand, score, R, bnd);                                                   \
+            HGP_PROPW(PIV, i32, L.pins(), kProposeWaves);                                                          \
         break;
     switch (Pi) {
         HGP_PROP(1) HGP_PROP(2) HGP_PROP(3) HGP_PROP(4) HGP_PROP(5) HGP_PROP(6) HGP_PROP(7) HGP_PROP(8)
         default: fail(HGP_E_INVALID, "pi must be in 1..8");
     }
 #undef HGP_PROP
+#undef HGP_PROPW
 }
 
 }  // namespace

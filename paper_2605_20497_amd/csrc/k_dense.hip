@@ -524,14 +524,14 @@ bool dense_proposal_fits(i32 N, i32 E, u64 max_t) {
 }
 
 // Estimated times of the two proposals: MFMA products over the padded
-// upper triangle at a third of the int8 peak, against the histogram's
+// upper triangle at 40 % of the int8 peak, against the histogram's
 // Sigma |e|^2 updates at the rate it sustains on such levels.
 bool prefer_dense_proposal(const Ctx* c, i32 N, i32 E, u64 max_t, u64 sum_card_sq) {
     if (!dense_proposal_fits(N, E, max_t)) return false;
     const double Npad = (double)((N + kTile - 1) / kTile * kTile);
     const double Epad = (double)(((E + 31) / 32 + 3) / 4 * 4 * 32);
     const double macs = Npad * (Npad + kTile) / 2.0 * Epad * (dense_planes(max_t) + 1);
-    const double dense_s = macs / (2.5e15 * c->num_cu / 256.0 / 3.0) + 60e-6;
+    const double dense_s = macs / (2.5e15 * c->num_cu / 256.0 / 2.5) + 60e-6;
     const double sparse_s = (double)sum_card_sq / 4.0e11;
     return dense_s < sparse_s;
 }
