@@ -42,9 +42,10 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "f6537ed8c5dda1c9e4c05243ee1ee74f3dc9818f0a4a84d0ddbeb35d89781205"): 8893054087,
-    ("k_gains16", "ef34a5b07bfed306dd6bee5ff39021c1019fecf56e3f0bf39e1a81ea50a204c9"): 3454187940,
-    ("k_dense_gemm", "a0811ddba2f56f46d6b18239e25d877793e7ca3346857c748c2e1d655fa4f5b8"): 1234917081,
+    ("k_propose", "74e79012d2e9080dda9a636c76b5b683f47784f9fcaa9421eec00c893980a5da"): 6519275500,
+    ("k_gains16", "e503050b969e036b94c7716cb1f27040f3f3db8c5100efd6852a7901b3a70fc3"): 5202884067,
+    ("k_dense_gemm", "8cad496683c6f0030c5b7d99fca3df59d6b4752e8c09a1be334953f1c7f1efd3"): 2569985707,
+    ("k_conn_gemm", "8cad496683c6f0030c5b7d99fca3df59d6b4752e8c09a1be334953f1c7f1efd3"): 783987381,
 }
 
 
