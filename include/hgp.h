@@ -73,8 +73,17 @@ typedef struct hgp_options {
                               level by an estimate.  Results are identical in every case. */
     uint32_t profile_families; /* with profile = 1: bit i times only kernel family i (the order of
                                 * hgp_kernel_stats' names); 0 = every family */
-    int32_t reserved[5];
+    int32_t delta_mode;    /* which h-edges Delta counts for a partition (constraint variants of
+                            * Sec. II-B, whose reformulation the paper notes): HGP_DELTA_INBOUND
+                            * (default: those with a destination pin in the part), _OUTBOUND (a
+                            * source pin) or _INCIDENT (any pin; also undirected inputs).  The
+                            * library applies it at load by relabelling pin roles: outbound
+                            * swaps sources and destinations, incident makes every pin a
+                            * destination.  Connectivity does not depend on roles. */
+    int32_t reserved[4];
 } hgp_options;
+
+enum { HGP_DELTA_INBOUND = 0, HGP_DELTA_OUTBOUND = 1, HGP_DELTA_INCIDENT = 2 };
 
 /* Fills `opt` with the defaults above. */
 void hgp_default_options(hgp_options* opt);

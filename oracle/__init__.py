@@ -92,11 +92,39 @@ def noise(seed: int, a: int, b: int, cap: int) -> int:
     return int(lib().hgpo_noise(seed, a, b, cap))
 
 
+def relabel(he_off, he_nsrc, pins, mode):
+    """Constraint variants of the Delta cap (Sec. II-B counts the distinct
+    inbound h-edges of a partition; the paper notes that outbound or incident
+    counting are reformulations).  Delta only ever counts the h-edges whose
+    destination pins touch a part, so relabelling pin roles selects the
+    variant: mode 1 (outbound) makes each h-edge's sources its destinations
+    and vice versa; mode 2 (incident, also undirected inputs) makes every pin
+    a destination.  Blocks stay sorted.  Plain per-h-edge Python."""
+    he_off = np.asarray(he_off, np.int64)
+    he_nsrc = np.asarray(he_nsrc, np.int32)
+    pins = np.asarray(pins, np.int32)
+    if mode == 0:
+        return he_off, he_nsrc, pins
+    out = np.empty_like(pins)
+    nsrc = np.empty_like(he_nsrc)
+    for e in range(he_nsrc.shape[0]):
+        a, b = int(he_off[e]), int(he_off[e + 1])
+        src, dst = pins[a:a + int(he_nsrc[e])], pins[a + int(he_nsrc[e]):b]
+        if mode == 1:
+            out[a:b] = np.concatenate([dst, src])
+            nsrc[e] = dst.shape[0]
+        else:
+            out[a:b] = np.sort(np.concatenate([src, dst]))
+            nsrc[e] = 0
+    return he_off, nsrc, out
+
+
 class Graph:
-    """Oracle-side hypergraph.  Built from the generator's CSR arrays."""
+    """Oracle-side hypergraph.  Built from the generator's CSR arrays;
+    delta_mode selects the Delta variant (see relabel)."""
 
     def __init__(self, hg=None, *, n_nodes=None, he_off=None, he_nsrc=None, pins=None,
-                 hedge_w=None, node_w=None, _handle=None, _owner=None):
+                 hedge_w=None, node_w=None, delta_mode=0, _handle=None, _owner=None):
         self._owner = _owner
         if _handle is not None:
             self.h = _handle
@@ -105,6 +133,7 @@ class Graph:
             if hg is not None:
                 n_nodes, he_off, he_nsrc, pins = hg.n_nodes, hg.he_off, hg.he_nsrc, hg.pins
                 hedge_w, node_w = hg.hedge_w, hg.node_w
+            he_off, he_nsrc, pins = relabel(he_off, he_nsrc, pins, delta_mode)
             he_off = np.ascontiguousarray(he_off, np.int64)
             he_nsrc = np.ascontiguousarray(he_nsrc, np.int32)
             pins = np.ascontiguousarray(pins, np.int32)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libhgp.so")
 
 HGP_OK, HGP_E_INVALID, HGP_E_INFEASIBLE, HGP_E_NOMEM, HGP_E_DEVICE, HGP_E_STATE, HGP_E_UNSUPPORTED = range(7)
 HGP_MEM_HOST, HGP_MEM_DEVICE = 0, 1
+HGP_DELTA_INBOUND, HGP_DELTA_OUTBOUND, HGP_DELTA_INCIDENT = 0, 1, 2
 INT64_MAX = (1 << 63) - 1
 
 _STATUS = {0: "OK", 1: "INVALID", 2: "INFEASIBLE", 3: "NOMEM", 4: "DEVICE", 5: "STATE", 6: "UNSUPPORTED"}
@@ -30,7 +31,7 @@ class hgp_options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", C.c_void_p), ("pi", C.c_int32), ("theta", C.c_int32), ("seed", C.c_uint64),
                 ("profile", C.c_int32), ("flags", C.c_int32), ("profile_families", C.c_uint32),
-                ("reserved", C.c_int32 * 5)]
+                ("delta_mode", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class hgp_eval(C.Structure):
@@ -115,7 +116,8 @@ EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error"
             "hgp_run_jobs"]
 
 
-def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16, seed=0, device=0, flags=0):
+def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16, seed=0, device=0, flags=0,
+                 delta_mode=0):
     """Runs a list of hypergraphs (workloads.Hypergraph, with their omega,
     delta and k) as jobs on `workers` concurrent contexts; `arrivals` are the
     seconds after the start at which each may be admitted (sorted; default
@@ -142,6 +144,7 @@ def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16,
     opt = hgp_options()
     lib().hgp_default_options(C.byref(opt))
     opt.device, opt.pi, opt.theta, opt.seed, opt.flags = device, pi, theta, seed, flags
+    opt.delta_mode = int(delta_mode)
     st = lib().hgp_run_jobs(C.byref(opt), jobs, n, int(workers), int(hbm_budget))
     if st != 0:
         raise HgpError(st, "hgp_run_jobs failed")
@@ -182,7 +185,7 @@ class Partitioner:
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
                  use_torch: bool = True, stream=None, sparse_proposal: bool = False, profile_families=(),
-                 dense_proposal=None, dense_gains=None):
+                 dense_proposal=None, dense_gains=None, delta_mode=0):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
@@ -192,6 +195,8 @@ class Partitioner:
         # the same choice for the in-isolation moves of refinement
         opt.flags = ((1 if sparse_proposal else 0) | {None: 0, True: 2, False: 4}[dense_proposal]
                      | {None: 0, True: 8, False: 16}[dense_gains])
+        # what Delta counts: 0 inbound h-edges (the paper's), 1 outbound, 2 incident
+        opt.delta_mode = int(delta_mode)
         # kernel families to time (names as in hgp_kernel_stats); empty = all
         opt.profile_families = sum(1 << KERNEL_FAMILIES.index(f) for f in profile_families)
         self._keep = []

@@ -290,7 +290,7 @@ hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt) {
     Ctx* c = &h->c;
     hgp_default_options(&c->opt);
     if (opt) c->opt = *opt;
-    if (c->opt.pi < 1 || c->opt.pi > 8 || c->opt.theta < 0) {
+    if (c->opt.pi < 1 || c->opt.pi > 8 || c->opt.theta < 0 || c->opt.delta_mode < 0 || c->opt.delta_mode > 2) {
         delete h;
         return HGP_E_INVALID;
     }
@@ -403,6 +403,10 @@ hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int
     c->total_nw = r[2];
     c->max_card = (i32)std::max<i64>(1, r[3]);
     c->max_hw = std::max<i64>(1, r[4]);
+    // Constraint variants: Delta counts the h-edges whose destination pins
+    // touch a part, so relabelling the roles of the validated input selects
+    // what it counts (sources: swap the blocks; any pin: one merged block).
+    if (c->opt.delta_mode != HGP_DELTA_INBOUND) retarget_pins(c, L0, c->opt.delta_mode);
     build_incidence(c, L0);
     c->sync();
     c->loaded = true;

@@ -178,6 +178,10 @@ void build_incidence(Ctx* c, Level& L);
 // Coarse pins of every h-edge through gamma, deduplicated, src' = gamma(src) \ dst'.
 void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out);
 // Phi rows at the h-edge offsets: part / cnt / cnt_in, row length in len[E].
+// Relabels pin roles in place for a constraint variant (delta_mode 1: each
+// h-edge's sources and destinations swap blocks; 2: one sorted block of
+// destinations, no sources).
+void retarget_pins(Ctx* c, Level& L, int mode);
 // Phi rows of every h-edge at its pin offset; with `single`, one byte per pin
 // slot that is 1 when pins(rho(m), e) = 1 for the slot's pin m.
 void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len,

@@ -348,6 +348,49 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
                (const i64*)out.he_off(), (const i32*)tmp, out.pins());
 }
 
+// Pin roles of one h-edge per block, staged in shared memory (|e| <= 4,096):
+// mode 1 writes the destination block first and makes it the sources; mode 2
+// merges the two sorted blocks into one (each pin's place is its index in its
+// own block plus the count of smaller pins in the other; the blocks are
+// disjoint) with no sources.
+__global__ __launch_bounds__(256) void k_retarget(i32 E, const i64* __restrict__ he_off, i32* he_nsrc, i32* pins,
+                                                  int mode) {
+    __shared__ i32 sp[kMaxCard];
+    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e], nd = card - ns;
+        for (int i = threadIdx.x; i < card; i += blockDim.x) sp[i] = pins[a + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < card; i += blockDim.x) {
+            const i32 v = sp[i];
+            const int src = (int)(i < ns);
+            int pos;
+            if (mode == 1) {
+                pos = src ? nd + i : i - ns;
+            } else {
+                const int lo0 = src ? ns : 0, hi0 = src ? card : ns;  // the other block
+                int lo = lo0, hi = hi0;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int lt = (int)(sp[mid] < v);
+                    lo = lt ? mid + 1 : lo;
+                    hi = lt ? hi : mid;
+                }
+                pos = (src ? i : i - ns) + (lo - lo0);
+            }
+            pins[a + pos] = v;
+        }
+        if (threadIdx.x == 0) he_nsrc[e] = mode == 1 ? nd : 0;
+        __syncthreads();
+    }
+}
+
+void retarget_pins(Ctx* c, Level& L, int mode) {
+    if (L.E == 0) return;
+    LAUNCH(c, KF_VALIDATE, k_retarget, grid_for(L.E, 1, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(),
+           L.pins(), mode);
+}
+
 void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len,
                unsigned char* single) {
     if (L.E == 0) return;

@@ -305,3 +305,29 @@ def test_dense_gains_rep_step():
         grho, gd = g.hgp_refine_rep(rho0, 9, rep)
         assert np.array_equal(gd["move_dst"], odst) and np.array_equal(gd["move_gain"], ogain)
     g.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_delta_variants_full_pipeline(mode):
+    # outbound (1) and incident (2) Delta: the library relabels pin roles on
+    # the device at load; the oracle relabels the same input on the host
+    from paper_2605_20497_amd import Partitioner
+    for hg, omega, delta in ((W.random_small(300, 260, 14, 8, max_src=2, max_hw=2), 24, 40),
+                             (W.random_snn(2048, 23, 4), 64, 300)):
+        print("case delta_mode", mode, "N", hg.n_nodes, "P", hg.n_pins, flush=True)
+        og = oracle.Graph(hg, delta_mode=mode)
+        res = og.partition(omega, delta, Pi=4, theta=16, seed=0)
+        g = Partitioner(delta_mode=mode)
+        g.load(hg)
+        g.hgp_set_limits(omega, delta, 0)
+        assert g.hgp_coarsen() == res.nlevels
+        g.hgp_refine()
+        rho, _ = g.hgp_get_partition()
+        assert np.array_equal(rho, res.rho(0))
+        ev = g.hgp_evaluate()
+        assert ev["conn"] == res.conn and ev["violations"] == 0
+        # evaluation of an arbitrary partition under the variant
+        r2 = np.random.default_rng(mode).integers(0, 7, size=hg.n_nodes).astype(np.int32)
+        e2, o2 = g.hgp_evaluate(r2, 7), og.evaluate(r2, 7)
+        assert (e2["conn"], e2["max_inbound"]) == (o2["conn"], o2["max_inbound"])
+        g.close()

@@ -1,0 +1,69 @@
+"""Constraint variants of the Delta cap (Sec. II-B: a partition's distinct
+inbound h-edges; the paper notes outbound and incident counting, and
+undirected inputs, as reformulations).  The oracle selects a variant by
+relabelling pin roles (oracle.relabel); these tests pin that relabelling
+against the variants' definitions computed directly from the original
+h-graph by brute force."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_20497_amd import workloads as W
+
+
+def _brute_D(hg, rho, nparts, mode):
+    # D(p) = number of h-edges with a destination (mode 0), source (1) or any
+    # (2) pin in p, straight from the definition
+    D = np.zeros(nparts, np.int64)
+    for e in range(hg.n_hedges):
+        a, b = int(hg.he_off[e]), int(hg.he_off[e + 1])
+        ns = int(hg.he_nsrc[e])
+        sel = {0: hg.pins[a + ns:b], 1: hg.pins[a:a + ns], 2: hg.pins[a:b]}[mode]
+        for p in set(rho[sel].tolist()):
+            D[p] += 1
+    return D
+
+
+def _brute_conn(hg, rho):
+    return sum(int(hg.hedge_w[e]) * (len(set(rho[hg.pins[hg.he_off[e]:hg.he_off[e + 1]]].tolist())) - 1)
+               for e in range(hg.n_hedges))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_relabel_shapes(seed):
+    hg = W.random_small(90, 120, 9, seed, max_src=3)
+    off, ns1, p1 = oracle.relabel(hg.he_off, hg.he_nsrc, hg.pins, 1)
+    off2, ns2, p2 = oracle.relabel(off, ns1, p1, 1)
+    assert np.array_equal(ns2, hg.he_nsrc) and np.array_equal(p2, hg.pins)  # swapping twice is the identity
+    _, ns3, p3 = oracle.relabel(hg.he_off, hg.he_nsrc, hg.pins, 2)
+    assert (ns3 == 0).all()
+    for e in range(hg.n_hedges):
+        a, b = hg.he_off[e], hg.he_off[e + 1]
+        assert np.array_equal(p3[a:b], np.sort(hg.pins[a:b]))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_variant_evaluation_matches_definition(mode):
+    hg = W.random_small(150, 200, 12, 4, max_src=3, max_hw=3)
+    og = oracle.Graph(hg, delta_mode=mode)
+    rng = np.random.default_rng(mode)
+    for P in (1, 6, 40):
+        rho = rng.integers(0, P, size=hg.n_nodes).astype(np.int32)
+        ev = og.evaluate(rho, P)
+        D = _brute_D(hg, rho, P, mode)
+        assert np.array_equal(ev["part_inbound"], D)
+        assert ev["max_inbound"] == D.max()
+        assert ev["conn"] == _brute_conn(hg, rho)  # connectivity does not depend on pin roles
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_variant_partition_respects_its_cap(mode):
+    hg = W.random_small(300, 260, 14, 8, max_src=2, max_hw=2)
+    og = oracle.Graph(hg, delta_mode=mode)
+    res = og.partition(24, 40, Pi=4, theta=8, seed=0)
+    rho = res.rho(0)
+    P = int(rho.max()) + 1
+    D = _brute_D(hg, rho, P, mode)
+    assert D.max() <= 40
+    assert np.bincount(rho, weights=hg.node_w, minlength=P).max() <= 24
+    assert res.conn == _brute_conn(hg, rho)
