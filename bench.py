@@ -63,6 +63,9 @@ def _args():
     ap.add_argument("--batch-jobs", type=int, default=64)
     ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--batch-max-nodes", type=int, default=32768)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the step: Pi and Theta sweeps and the chain-free ablation on --sweep-workload")
+    ap.add_argument("--sweep-workload", default="rand-64k-e192")
     return ap.parse_args()
 
 
@@ -148,12 +151,59 @@ def batched_leg(args):
             "bit_exact_vs_plain": bool(ok)}
 
 
+def sweep(args):
+    """Parameter sweeps of the method on one workload: Pi (candidates and
+    matching rounds) at Theta = 16, Theta (repetitions per level) at Pi = 4,
+    and the ablation without chain rounds (moves sequenced by gain alone).
+    Per setting: the partition's connectivity and violations, the hierarchy
+    depth and the wall time of one partitioning (after one untimed run)."""
+    import torch
+
+    import paper_2605_20497_amd as pkg
+    from paper_2605_20497_amd import workloads as W
+
+    hg = W.CONFIGS[args.sweep_workload]()
+    torch.cuda.set_device(0)
+
+    def run(pi, theta, flags=0):
+        g = pkg.Partitioner(device=0, pi=pi, theta=theta)
+        if flags:
+            g.close()
+            g = pkg.Partitioner(device=0, pi=pi, theta=theta, no_chains=True)
+        out = None
+        for rep in range(2):
+            g.load(hg)
+            g.hgp_set_limits(hg.omega, hg.delta, hg.k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nl = g.hgp_coarsen()
+            g.hgp_refine()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ev = g.hgp_evaluate()
+            out = {"pi": pi, "theta": theta, "chains": not flags, "conn": int(ev["conn"]),
+                   "violations": int(ev["violations"]), "parts": int(ev["n_parts"]), "levels": int(nl),
+                   "ms": round(dt * 1e3, 2)}
+        g.close()
+        print(json.dumps(out), file=sys.stderr, flush=True)
+        return out
+
+    rows = [run(pi, 16) for pi in (1, 2, 3, 4, 6, 8)]
+    rows += [run(4, th) for th in (0, 1, 2, 4, 8, 32, 64)]
+    rows.append(run(4, 16, flags=1))
+    print(json.dumps({"sweep": args.sweep_workload, "nodes": hg.n_nodes, "pins": hg.n_pins,
+                      "omega": hg.omega, "delta": hg.delta, "rows": rows}))
+
+
 def main():
     args = _args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(sharding across GPUs is described in DESIGN.md)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        sweep(args)
+        return
     import numpy as np
     import torch
 

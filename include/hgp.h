@@ -70,7 +70,9 @@ typedef struct hgp_options {
                               estimate of both proposals' time.
                               bit 3: compute the in-isolation moves of refinement as a dense
                               (MFMA) product wherever it fits; bit 4: never; by default per
-                              level by an estimate.  Results are identical in every case. */
+                              level by an estimate.  Results are identical in every case.
+                              bit 5: ablation without chain rounds (Sec. VII): every move is a
+                              chain of its own, sequenced by gain alone (changes results). */
     uint32_t profile_families; /* with profile = 1: bit i times only kernel family i (the order of
                                 * hgp_kernel_stats' names); 0 = every family */
     int32_t delta_mode;    /* which h-edges Delta counts for a partition (constraint variants of

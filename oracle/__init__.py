@@ -284,11 +284,12 @@ class Graph:
             raise OracleError(err.value.decode())
         return rho
 
-    def partition(self, omega, delta, k=0, Pi=4, theta=16, seed=0, early_exit=True) -> "Result":
+    def partition(self, omega, delta, k=0, Pi=4, theta=16, seed=0, early_exit=True, chains=True) -> "Result":
+        # chains=False: the ablation without chain rounds (moves sequenced by gain alone)
         h = C.c_void_p()
         err = C.create_string_buffer(256)
         rc = lib().hgpo_partition(self.h, int(omega), int(delta), int(k), Pi, theta, C.c_uint64(seed),
-                                  int(bool(early_exit)), C.byref(h), err, 256)
+                                  int(bool(early_exit)) | (0 if chains else 2), C.byref(h), err, 256)
         if rc != 0:
             raise OracleError(err.value.decode())
         return Result(h.value, Pi)

@@ -506,7 +506,8 @@ std::vector<Move> propose_moves(const Graph& g, const i32* rho, i32 nparts, int 
 
 // One refinement repetition: moves, sequence of chains (Sec. VI-C), in-sequence
 // gains, validity of every prefix (Sec. VI-D) and the applied prefix.
-RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 omega, i64 delta) {
+RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 omega, i64 delta,
+                  int chain_rounds = 16) {
     RepOut out;
     auto rows = phi_rows(g, rho);
     std::vector<i64> psize(nparts, 0), D(nparts, 0);
@@ -532,8 +533,10 @@ RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 
     // grades the first 256 predecessor-less moves leaving its destination and
     // proposes the lexicographic max of (grade, node id); a successor accepts
     // the max of (grade, proposer id).  Grade = 10^7 x the paper's grade.
+    // chain_rounds = 0 is the ablation without chaining (Sec. VII): every move
+    // is a chain of its own, so the sequence orders moves by gain alone.
     std::vector<i64> pred(M, -1), succ(M, -1);
-    const int kWindow = 256, kRounds = 16;
+    const int kWindow = 256, kRounds = chain_rounds;
     for (int round = 0; round < kRounds; ++round) {
         std::vector<i64> prop(M, -1), propG(M, 0);
         for (i64 i = 0; i < M; ++i) {
@@ -658,6 +661,8 @@ RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 
 // ---------------------------------------------------------------------------
 // Multilevel driver (Sec. III) and the k-way adapter (Sec. VII-A).
 // ---------------------------------------------------------------------------
+// early_exit: bit 0 = Reading R25's early exit of repetitions; bit 1 = the
+// ablation without chain rounds.
 struct Params { i64 omega, delta; i32 k, Pi, Theta; u64 seed; int early_exit; };
 
 struct LevelLog {
@@ -783,11 +788,12 @@ void run_partition(Result& R, const Graph& g0, const Params& prm) {
         }
         i64 applied = 0;
         for (int rep = 0; rep < prm.Theta; ++rep) {
-            RepOut o = refine_rep(g, rho.data(), R.nparts, rep, prm.Theta, prm.omega, prm.delta);
+            RepOut o = refine_rep(g, rho.data(), R.nparts, rep, prm.Theta, prm.omega, prm.delta,
+                                  (prm.early_exit & 2) ? 0 : 16);
             applied += o.kstar;
             // Reading R25: a repetition that applies nothing leaves rho and the
             // sizes unchanged, so the rest of its half would repeat it exactly.
-            if (prm.early_exit && o.kstar == 0) {
+            if ((prm.early_exit & 1) && o.kstar == 0) {
                 if (rep < prm.Theta / 2) rep = prm.Theta / 2 - 1;
                 else break;
             }

@@ -185,7 +185,7 @@ class Partitioner:
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
                  use_torch: bool = True, stream=None, sparse_proposal: bool = False, profile_families=(),
-                 dense_proposal=None, dense_gains=None, delta_mode=0):
+                 dense_proposal=None, dense_gains=None, delta_mode=0, no_chains=False):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
@@ -194,7 +194,7 @@ class Partitioner:
         # fits; bit 2 never dense; neither of bits 1-2 = chosen per level by cost; bits 3-4
         # the same choice for the in-isolation moves of refinement
         opt.flags = ((1 if sparse_proposal else 0) | {None: 0, True: 2, False: 4}[dense_proposal]
-                     | {None: 0, True: 8, False: 16}[dense_gains])
+                     | {None: 0, True: 8, False: 16}[dense_gains] | (32 if no_chains else 0))
         # what Delta counts: 0 inbound h-edges (the paper's), 1 outbound, 2 incident
         opt.delta_mode = int(delta_mode)
         # kernel families to time (names as in hgp_kernel_stats); empty = all

@@ -1451,13 +1451,15 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     fill_i32(c, succ, -1, M);
     LAUNCH(c, KF_CHAINS, k_set_flag, 1, 1, 0, rs);
     const int wblocks = grid_for(M, 4, c->num_cu * 16);
-    if (M <= kChainSingleMax)
+    // flags bit 5: the ablation without chain rounds (every move its own chain)
+    const int rounds = (c->opt.flags & 32) ? 0 : kChainRounds;
+    if (M <= kChainSingleMax && rounds > 0)
         LAUNCH(c, KF_CHAINS, k_chain_rounds, 1, 1024, 0, (i32)M, rs, pred, succ, pl, pls, cl, accG, accN, spd, segb,
                sege, sg, snw, snin, snode, prop, propG);
     // Up to kChainCompactMax moves, a round's first three steps and the
     // previous round's end run as one single-workgroup launch.
     const bool one = M <= kChainCompactMax;
-    for (int round = 0; round < kChainRounds && M > kChainSingleMax; ++round) {
+    for (int round = 0; round < rounds && M > kChainSingleMax; ++round) {
         if (one) {
             LAUNCH(c, KF_CHAINS, k_chain_compact1, 1, 1024, 0, (i32)M, round, rs, pred, pls, cl, accG, accN);
         } else {
@@ -1479,7 +1481,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
             if (!st[0] || (one && st[1] == 0)) break;
         }
     }
-    if (one && M > kChainSingleMax) LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);  // fold the last round
+    if (one && M > kChainSingleMax && rounds > 0) LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);  // fold the last round
 
     // Chains: cycles, heads, ranks.
     const int K = bits_for((u64)M) + 1;

@@ -331,3 +331,19 @@ def test_delta_variants_full_pipeline(mode):
         e2, o2 = g.hgp_evaluate(r2, 7), og.evaluate(r2, 7)
         assert (e2["conn"], e2["max_inbound"]) == (o2["conn"], o2["max_inbound"])
         g.close()
+
+
+def test_no_chains_ablation():
+    from paper_2605_20497_amd import Partitioner
+    for hg, omega, delta in ((W.random_snn(1024, 15, 3), 64, 256), (W.random_snn(4096, 95, 6), 128, 1024)):
+        print("case no-chains N", hg.n_nodes, flush=True)
+        res = oracle.Graph(hg).partition(omega, delta, Pi=4, theta=16, seed=0, chains=False)
+        g = Partitioner(no_chains=True)
+        g.load(hg)
+        g.hgp_set_limits(omega, delta, 0)
+        assert g.hgp_coarsen() == res.nlevels
+        g.hgp_refine()
+        rho, _ = g.hgp_get_partition()
+        assert np.array_equal(rho, res.rho(0))
+        assert g.hgp_evaluate()["conn"] == res.conn
+        g.close()

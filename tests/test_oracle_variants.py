@@ -67,3 +67,18 @@ def test_variant_partition_respects_its_cap(mode):
     assert D.max() <= 40
     assert np.bincount(rho, weights=hg.node_w, minlength=P).max() <= 24
     assert res.conn == _brute_conn(hg, rho)
+
+
+def test_no_chains_ablation_oracle():
+    # the ablation without chain rounds (Sec. VII): still a valid partition
+    # whose connectivity is what the definition gives; on this input the
+    # chains change the outcome, so the switch is effective
+    hg = W.random_snn(1024, 15, 3)
+    og = oracle.Graph(hg)
+    a = og.partition(64, 256, Pi=4, theta=16, seed=0, chains=False)
+    b = og.partition(64, 256, Pi=4, theta=16, seed=0)
+    ra = a.rho(0)
+    P = int(ra.max()) + 1
+    ev = og.evaluate(ra, P, 64, 256)
+    assert ev["violations"] == 0 and ev["conn"] == a.conn == _brute_conn(hg, ra)
+    assert not np.array_equal(ra, b.rho(0)) or a.conn != b.conn
