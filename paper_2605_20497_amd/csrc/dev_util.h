@@ -242,6 +242,46 @@ __device__ __forceinline__ void block_bitonic_sort_u32(u32* s, int npad) {
     }
 }
 
+// Bitonic sort, ascending, of 64 * KPL keys held in one wave: lane l holds
+// positions KPL*l .. KPL*l + KPL - 1 in v[0 .. KPL).  Partners KPL or more
+// positions apart are in other lanes (same register, exchanged by shuffles);
+// closer ones are in the same lane.  Fully unrolled: no barriers, no shared
+// memory.
+template <int KPL>
+__device__ __forceinline__ void wave_bitonic_sort(u32 (&v)[KPL]) {
+    constexpr int N = 64 * KPL;
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= KPL) {
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    const int i = lane * KPL + r;
+                    const u32 o = (u32)__shfl_xor((int)v[r], j / KPL, kWave);
+                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                    const u32 mn = v[r] < o ? v[r] : o, mx = v[r] < o ? o : v[r];
+                    v[r] = keep_min ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    const int rp = r ^ j;
+                    if (rp > r) {
+                        const int i = lane * KPL + r;
+                        const bool up = (i & k) == 0;
+                        const u32 a = v[r], b = v[rp];
+                        const bool sw = (a > b) == up;
+                        v[r] = sw ? b : a;
+                        v[rp] = sw ? a : b;
+                    }
+                }
+            }
+        }
+    }
+}
+
 __host__ __device__ __forceinline__ int next_pow2(int x) {
     int p = 1;
     while (p < x) p <<= 1;

@@ -152,12 +152,13 @@ __global__ void k_inc_offsets(i32 N, i64 P, const u32* __restrict__ skeys, i64* 
 __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __restrict__ he_off,
                                                         const i32* __restrict__ he_nsrc,
                                                         const i32* __restrict__ pins, const i32* __restrict__ gamma,
-                                                        i32* tmp, i32* card_out, i32* nsrc_out) {
+                                                        i32* tmp, i32* card_out, i32* nsrc_out, int skip_le) {
     extern __shared__ u32 keys[];
     __shared__ i32 red[16];
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
+        if (card <= skip_le) continue;  // taken by the wave kernel
         const int npad = next_pow2(card);
         for (int i = threadIdx.x; i < npad; i += blockDim.x)
             keys[i] = i < card ? (((u32)gamma[pins[a + i]] << 1) | (i < ns ? 1u : 0u)) : 0xFFFFFFFFu;
@@ -217,12 +218,13 @@ __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict
 __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
                                              const i32* __restrict__ pins, const i32* __restrict__ rho,
                                              i32* part, i32* cnt, i32* cnt_in, i32* len, unsigned char* single,
-                                             int npad_max) {
+                                             int npad_max, int skip_le) {
     extern __shared__ u32 sm[];
     __shared__ i32 red[16];
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
+        if (card <= skip_le) continue;  // taken by the wave kernel
         const int npad = next_pow2(card);
         u32* keys = sm;
         i32* c_all = (i32*)(sm + npad);
@@ -275,6 +277,172 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
         }
         if (threadIdx.x == 0) len[e] = rows;
         __syncthreads();
+    }
+}
+
+// ---- one wave per h-edge of at most 256 pins --------------------------------
+// The h-edge's keys are sorted in registers (wave_bitonic_sort, KPL keys per
+// lane, blocked), runs are found by comparing each key with its predecessor,
+// and outputs are placed by wave scans: no block barriers and no shared
+// memory for the sort.  Results are those of the block kernels above.
+constexpr int kWaveEdgeMax = 256;
+
+// In-lane inclusive prefix of flags and the wave-exclusive offset of the lane.
+template <int KPL>
+__device__ __forceinline__ i32 lane_offsets(const int (&f)[KPL], i32 (&pre)[KPL], i32& total) {
+    i32 c = 0;
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        c += f[r];
+        pre[r] = c;
+    }
+    const i32 incl = wave_incl_scan(c);
+    total = __shfl(incl, kWave - 1, kWave);
+    return incl - c;
+}
+
+template <int KPL>
+__device__ __forceinline__ void contract_edge_wave(i64 a, int card, int ns, const i32* __restrict__ pins,
+                                                   const i32* __restrict__ gamma, i32* tmp, i32& ncard, i32& nsrc) {
+    const int lane = lane_id();
+    u32 v[KPL];
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        const int pos = lane * KPL + r;
+        v[r] = pos < card ? (((u32)gamma[pins[a + pos]] << 1) | (pos < ns ? 1u : 0u)) : 0xFFFFFFFFu;
+    }
+    wave_bitonic_sort<KPL>(v);
+    const u32 last = (u32)__shfl_up((int)v[KPL - 1], 1, kWave);
+    int fs[KPL], fd[KPL];
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        const int pos = lane * KPL + r;
+        const u32 prev = r > 0 ? v[r - 1] : last;
+        const int head = (int)(pos < card) & ((int)(pos == 0) | (int)((v[r] >> 1) != (prev >> 1)));
+        fs[r] = head & (int)((v[r] & 1u) != 0);  // a cluster with a destination pin is a destination
+        fd[r] = head & (int)((v[r] & 1u) == 0);
+    }
+    i32 ps[KPL], pd[KPL], ts, td;
+    const i32 os = lane_offsets<KPL>(fs, ps, ts);
+    const i32 od = lane_offsets<KPL>(fd, pd, td);
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        if (fs[r]) tmp[a + os + ps[r] - 1] = (i32)(v[r] >> 1);
+        if (fd[r]) tmp[a + ts + od + pd[r] - 1] = (i32)(v[r] >> 1);
+    }
+    ncard = ts + td;
+    nsrc = ts;
+}
+
+__global__ __launch_bounds__(256) void k_contract_edges_wave(i32 E, const i64* __restrict__ he_off,
+                                                             const i32* __restrict__ he_nsrc,
+                                                             const i32* __restrict__ pins,
+                                                             const i32* __restrict__ gamma, i32* tmp, i32* card_out,
+                                                             i32* nsrc_out) {
+    const int wpb = blockDim.x / kWave;
+    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
+        if (card > kWaveEdgeMax) continue;  // taken by the block kernel
+        i32 nc, nsv;
+        if (card <= 64) contract_edge_wave<1>(a, card, ns, pins, gamma, tmp, nc, nsv);
+        else if (card <= 128) contract_edge_wave<2>(a, card, ns, pins, gamma, tmp, nc, nsv);
+        else contract_edge_wave<4>(a, card, ns, pins, gamma, tmp, nc, nsv);
+        if (lane_id() == 0) {
+            card_out[e] = nc;
+            nsrc_out[e] = nsv;
+        }
+    }
+}
+
+// Phi rows of one h-edge in one wave.  Shared memory per wave: the sorted
+// keys and the row of each sorted position (for `single`), the row counts.
+struct PhiWaveShared {
+    u32 keys[kWaveEdgeMax];
+    i32 rowat[kWaveEdgeMax];
+    i32 c_all[kWaveEdgeMax];
+    i32 c_in[kWaveEdgeMax];
+};
+
+template <int KPL>
+__device__ __forceinline__ void phi_edge_wave(PhiWaveShared& sh, i64 a, int card, int ns, const i32* __restrict__ pins,
+                                              const i32* __restrict__ rho, i32* part, i32* cnt, i32* cnt_in,
+                                              unsigned char* single, i32& rows) {
+    const int lane = lane_id();
+    u32 v[KPL], orig[KPL];
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        const int pos = lane * KPL + r;
+        v[r] = pos < card ? (((u32)rho[pins[a + pos]] << 1) | (pos >= ns ? 1u : 0u)) : 0xFFFFFFFFu;
+        orig[r] = v[r];
+        sh.c_all[pos] = 0;
+        sh.c_in[pos] = 0;
+    }
+    wave_bitonic_sort<KPL>(v);
+    const u32 last = (u32)__shfl_up((int)v[KPL - 1], 1, kWave);
+    int hd[KPL];
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        const int pos = lane * KPL + r;
+        const u32 prev = r > 0 ? v[r - 1] : last;
+        hd[r] = (int)(pos < card) & ((int)(pos == 0) | (int)((v[r] >> 1) != (prev >> 1)));
+    }
+    i32 pre[KPL];
+    const i32 off = lane_offsets<KPL>(hd, pre, rows);
+    wave_sync();  // counters cleared
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        const int pos = lane * KPL + r;
+        if (pos < card) {
+            const i32 row = off + pre[r] - 1;
+            if (hd[r]) part[a + row] = (i32)(v[r] >> 1);
+            atomicAdd(&sh.c_all[row], 1);
+            if (v[r] & 1u) atomicAdd(&sh.c_in[row], 1);
+            sh.keys[pos] = v[r];
+            sh.rowat[pos] = row;
+        }
+    }
+    wave_sync();
+    for (int r = lane; r < rows; r += kWave) {
+        cnt[a + r] = sh.c_all[r];
+        cnt_in[a + r] = sh.c_in[r];
+    }
+    if (single) {
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+            const int pos = lane * KPL + r;
+            if (pos < card) {
+                const u32 k = orig[r];
+                int lo = 0, hi = card;  // first sorted position with key >= k (the key is present)
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int lt = (int)(sh.keys[mid] < k);
+                    lo = lt ? mid + 1 : lo;
+                    hi = lt ? hi : mid;
+                }
+                single[a + pos] = (unsigned char)(sh.c_all[sh.rowat[lo]] == 1 ? 1 : 0);
+            }
+        }
+    }
+    wave_sync();  // shared memory is reused by the wave's next h-edge
+}
+
+__global__ __launch_bounds__(256) void k_phi_wave(i32 E, const i64* __restrict__ he_off,
+                                                  const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+                                                  const i32* __restrict__ rho, i32* part, i32* cnt, i32* cnt_in,
+                                                  i32* len, unsigned char* single) {
+    __shared__ PhiWaveShared sh[4];
+    const int wpb = blockDim.x / kWave;
+    PhiWaveShared& my = sh[wave_id()];
+    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
+        if (card > kWaveEdgeMax) continue;  // taken by the block kernel
+        i32 rows;
+        if (card <= 64) phi_edge_wave<1>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, rows);
+        else if (card <= 128) phi_edge_wave<2>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, rows);
+        else phi_edge_wave<4>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, rows);
+        if (lane_id() == 0) len[e] = rows;
     }
 }
 
@@ -335,8 +503,12 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
     if (E > 0) {
         // the input's largest h-edge bounds every level (|e'| <= |e|)
         const int npad = next_pow2(c->max_card);
-        LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges, grid_for(E, 1, c->num_cu * 16), 256,
-               sizeof(u32) * npad, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc());
+        LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges_wave, grid_for(E, 4, c->num_cu * 16), 256, 0, E, L.he_off(),
+               L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc());
+        if (c->max_card > kWaveEdgeMax)
+            LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges, grid_for(E, 1, c->num_cu * 16), 256,
+                   sizeof(u32) * npad, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(),
+                   kWaveEdgeMax);
     }
     scan_excl_i32_to_i64(c, card, out.he_off(), E);
     i64 P2 = 0;
@@ -395,8 +567,11 @@ void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32*
                unsigned char* single) {
     if (L.E == 0) return;
     const int npad = next_pow2(c->max_card);
-    LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * (single ? 5 : 3) * npad, L.E,
-           L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, npad);
+    LAUNCH(c, KF_PHI, k_phi_wave, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(), L.pins(),
+           rho, part, cnt, cnt_in, len, single);
+    if (c->max_card > kWaveEdgeMax)
+        LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * (single ? 5 : 3) * npad, L.E,
+               L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, npad, kWaveEdgeMax);
 }
 
 }  // namespace hgp
