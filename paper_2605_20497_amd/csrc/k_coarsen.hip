@@ -15,26 +15,37 @@ enum {
     WS_STATS = 30, WS_T = 31, WS_S = 32, WS_PARENT = 33, WS_J0 = 34, WS_J1 = 35, WS_D0 = 36, WS_D1 = 37,
     WS_ACC_A = 38, WS_ACC_BV = 39, WS_ACC_BC = 40, WS_SS0 = 41, WS_SS10 = 42, WS_ISO_FLAG = 43, WS_ISO_POS = 44,
     WS_ISO_KEYS = 45, WS_ISO_KEYS2 = 46, WS_ISO_VALS = 47, WS_ISO_VALS2 = 48, WS_REP = 49, WS_CID = 50,
-    WS_BND = 51
+    WS_BND = 51, WS_TE = 52, WS_CM1 = 53
 };
 
 // stats: [0] max_n sum_{e in I(n)} t(e); [1] max |in(n)|; [2] sum of t(e) over
 // h-edges with >= 2 pins; [3] their count; [4] noise cap; [5] max depth;
 // [6] merged pairs; [7] scratch.
+// Per node, from the per-h-edge t(e) and |e| - 1 written by k_edge_tsum.
 __global__ __launch_bounds__(256) void k_node_tsum(i32 N, const i64* __restrict__ inc_off,
                                                    const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
-                                                   const i64* __restrict__ he_off, const i32* __restrict__ hw,
+                                                   const u64* __restrict__ te, const i32* __restrict__ cm1,
                                                    const i32* __restrict__ nw, unsigned long long* stats) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
     unsigned long long mx = 0, mn = 0, mw = 0, mb = 0;
     for (i64 n = (i64)blockIdx.x * wpb + wave_id(); n < N; n += (i64)gridDim.x * wpb) {
         u64 s = 0, nb = 0;
-        for (i64 k = inc_off[n] + lane; k < inc_off[n + 1]; k += kWave) {
-            const i32 e = inc[k];
-            const i64 card = he_off[e + 1] - he_off[e];
-            s += norm_weight(hw[e], card);
-            nb += (u64)(card - 1);
+        const i64 k0 = inc_off[n], k1 = inc_off[n + 1];
+        for (i64 kb = k0; kb < k1; kb += 4 * kWave) {
+            i32 ee[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const i64 k = kb + u * kWave + lane;
+                ee[u] = k < k1 ? inc[k] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (ee[u] >= 0) {
+                    s += te[ee[u]];
+                    nb += (u64)cm1[ee[u]];
+                }
+            }
         }
         s = wave_sum(s);
         nb = wave_sum(nb);
@@ -54,12 +65,14 @@ __global__ __launch_bounds__(256) void k_node_tsum(i32 N, const i64* __restrict_
 }
 
 __global__ __launch_bounds__(256) void k_edge_tsum(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ hw,
-                                                   unsigned long long* stats) {
+                                                   unsigned long long* stats, u64* te, i32* cm1) {
     __shared__ unsigned long long red[16];
     unsigned long long s = 0, c = 0, sq = 0, tmax = 0;
     for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (i64)gridDim.x * blockDim.x) {
         const i64 card = he_off[e + 1] - he_off[e];
         const u64 t = norm_weight(hw[e], card > 0 ? card : 1);
+        te[e] = t;
+        cm1[e] = (i32)(card - 1);
         if (card >= 2) {
             s += t;
             c += 1;
@@ -940,11 +953,13 @@ void coarsen_level(Ctx* c, int lv) {
     const int nb = grid_for(N, 256, c->num_cu * 8);
     unsigned long long* stats = wsp<unsigned long long>(c, WS_STATS, 16);
     HIPC(hipMemsetAsync(stats, 0, 16 * sizeof(u64), c->stream));
-    LAUNCH(c, KF_LEVEL_STATS, k_node_tsum, grid_for(N, 4, c->num_cu * 16), 256, 0, N, L.inc_off(), L.inc_nin(),
-           L.inc(), L.he_off(), c->hw(), L.nw(), stats);
+    u64* te = wsp<u64>(c, WS_TE, (size_t)(L.E > 0 ? L.E : 1));
+    i32* cm1 = wsp<i32>(c, WS_CM1, (size_t)(L.E > 0 ? L.E : 1));
     if (L.E > 0)
         LAUNCH(c, KF_LEVEL_STATS, k_edge_tsum, grid_for(L.E, 256, c->num_cu * 4), 256, 0, L.E, L.he_off(), c->hw(),
-               stats);
+               stats, te, cm1);
+    LAUNCH(c, KF_LEVEL_STATS, k_node_tsum, grid_for(N, 4, c->num_cu * 16), 256, 0, N, L.inc_off(), L.inc_nin(),
+           L.inc(), (const u64*)te, (const i32*)cm1, L.nw(), stats);
     LAUNCH(c, KF_LEVEL_STATS, k_noise_cap, 1, 1, 0, stats);
     i64 st[16];
     read_back(c, stats, st, 16, 8);
