@@ -42,10 +42,10 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "74e79012d2e9080dda9a636c76b5b683f47784f9fcaa9421eec00c893980a5da"): 6519275500,
-    ("k_gains16", "e503050b969e036b94c7716cb1f27040f3f3db8c5100efd6852a7901b3a70fc3"): 5202884067,
-    ("k_dense_gemm", "8cad496683c6f0030c5b7d99fca3df59d6b4752e8c09a1be334953f1c7f1efd3"): 2569985707,
-    ("k_conn_gemm", "8cad496683c6f0030c5b7d99fca3df59d6b4752e8c09a1be334953f1c7f1efd3"): 783987381,
+    ("k_propose", "257e5d7724dbc9955df7210acd5ff98e6f355226ed8a0fb0a9070296867692af"): 6517537645,
+    ("k_gains16", "29367d2bf4230b3d4849440a91240e501423b4ba2e55cc481f54669a7d8e7e61"): 5214535996,
+    ("k_dense_gemm", "2440a8cc21458bdd17362fcddadebc2f2da4da9212c309e760ba05c83d6a9d0f"): 2568522303,
+    ("k_conn_gemm", "2440a8cc21458bdd17362fcddadebc2f2da4da9212c309e760ba05c83d6a9d0f"): 783950245,
 }
 
 
