@@ -159,6 +159,7 @@ void scan_excl_i32(Ctx* c, const i32* in, i32* out, i64 n);  // caller guarantee
 // Stable LSD radix sorts on the low `bits` bits of the key.
 void sort_pairs_u32(Ctx* c, const u32* kin, u32* kout, const i32* vin, i32* vout, i64 n, int bits);
 void sort_pairs_u64(Ctx* c, const u64* kin, u64* kout, const i32* vin, i32* vout, i64 n, int bits);
+void sort_pairs_u32_u64(Ctx* c, const u32* kin, u32* kout, const u64* vin, u64* vout, i64 n, int bits);
 void fill_i32(Ctx* c, i32* p, i32 v, i64 n);
 void fill_i64(Ctx* c, i64* p, i64 v, i64 n);
 void iota_i32(Ctx* c, i32* p, i64 n);

@@ -96,9 +96,11 @@ __global__ __launch_bounds__(256) void k_validate_nodes(i32 N, const i32* __rest
 // Incidence keys: one wave per h-edge; key = 2*node + (pin is a source),
 // value = h-edge id.  A stable sort by key then lists, per node, inbound
 // h-edges first and each block ascending (Sec. IV-B).
+// Sort keys 2n + [source] and values (h-edge << 32) | pin position, so the
+// sorted values give both the incidence entry and its pin slot.
 __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__ he_off,
                                                   const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
-                                                  u32* keys, i32* vals, i32* pin_edge) {
+                                                  u32* keys, u64* vals) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
@@ -106,8 +108,7 @@ __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__
         for (i64 j = a + lane; j < b; j += kWave) {
             const i32 n = pins[j];
             keys[j] = ((u32)n << 1) | (j < d0 ? 1u : 0u);
-            vals[j] = (i32)j;
-            pin_edge[j] = (i32)e;
+            vals[j] = ((u64)(u32)e << 32) | (u64)(u32)j;
         }
     }
 }
@@ -118,9 +119,12 @@ __global__ void k_pins16(i64 P, const i32* __restrict__ pins, unsigned short* p1
 }
 
 // h-edge of every incidence entry from its pin position.
-__global__ void k_inc_edges(i64 P, const i32* __restrict__ inc_pos, const i32* __restrict__ pin_edge, i32* inc) {
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
-        inc[i] = pin_edge[inc_pos[i]];
+__global__ void k_inc_edges(i64 P, const u64* __restrict__ sv, i32* inc, i32* inc_pos) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x) {
+        const u64 v = sv[i];
+        inc[i] = (i32)(v >> 32);
+        inc_pos[i] = (i32)(u32)v;
+    }
 }
 
 // Incidence offsets and inbound counts from the sorted keys: node n's entries
@@ -468,8 +472,8 @@ void build_incidence(Ctx* c, Level& L) {
     const i64 P = L.P;
     u32* keys = wsp<u32>(c, WS_KEYS, P);
     u32* keys_out = wsp<u32>(c, WS_KEYS_OUT, P);
-    i32* vals = wsp<i32>(c, WS_VALS, P);
-    i32* pin_edge = wsp<i32>(c, WS_PIN_EDGE, P);
+    u64* vals = wsp<u64>(c, WS_VALS, P);
+    u64* vals_out = wsp<u64>(c, WS_PIN_EDGE, P);
     if (P > 0x7FFFFFFF) fail(HGP_E_UNSUPPORTED, "more than 2^31 - 1 pins in one level");
     L.b_inc_nin = c->alloc(sizeof(i32) * (size_t)L.N);
     L.b_inc_off = c->alloc(sizeof(i64) * ((size_t)L.N + 1));
@@ -477,18 +481,18 @@ void build_incidence(Ctx* c, Level& L) {
     L.b_inc_pos = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
     if (L.E > 0)
         LAUNCH(c, KF_TRANSPOSE, k_pin_keys, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(),
-               L.pins(), keys, vals, pin_edge);
+               L.pins(), keys, vals);
     // Stable sort by (node, source flag): per node its inbound h-edges first,
     // each group in ascending h-edge order, since pins are stored by h-edge.
-    sort_pairs_u32(c, keys, keys_out, vals, L.inc_pos(), P, bits_for(2ull * (u64)L.N));
+    sort_pairs_u32_u64(c, keys, keys_out, vals, vals_out, P, bits_for(2ull * (u64)L.N));
     if (L.N <= 65536 && P > 0) {
         L.b_pins16 = c->alloc(sizeof(unsigned short) * (size_t)P);
         LAUNCH(c, KF_TRANSPOSE, k_pins16, grid_for(P, 256, c->num_cu * 8), 256, 0, P, (const i32*)L.pins(),
                (unsigned short*)L.b_pins16.p);
     }
     if (P > 0)
-        LAUNCH(c, KF_TRANSPOSE, k_inc_edges, grid_for(P, 256, c->num_cu * 8), 256, 0, P, (const i32*)L.inc_pos(),
-               (const i32*)pin_edge, L.inc());
+        LAUNCH(c, KF_TRANSPOSE, k_inc_edges, grid_for(P, 256, c->num_cu * 8), 256, 0, P, (const u64*)vals_out,
+               L.inc(), L.inc_pos());
     LAUNCH(c, KF_TRANSPOSE, k_inc_offsets, grid_for((i64)L.N + 1, 256, c->num_cu * 8), 256, 0, L.N, P,
            (const u32*)keys_out, L.inc_off(), L.inc_nin());
 }

@@ -143,6 +143,17 @@ void sort_pairs_u32(Ctx* c, const u32* kin, u32* kout, const i32* vin, i32* vout
     prof_end(c, KF_SORT);
 }
 
+void sort_pairs_u32_u64(Ctx* c, const u32* kin, u32* kout, const u64* vin, u64* vout, i64 n, int bits) {
+    if (n <= 0) return;
+    if (bits < 1) bits = 1;
+    size_t tmp = 0;
+    HIPC(rocprim::radix_sort_pairs(nullptr, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
+    void* t = c->ws_get(WS_SORT_TMP, tmp + 256);
+    prof_begin(c, KF_SORT);
+    HIPC(rocprim::radix_sort_pairs(t, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
+    prof_end(c, KF_SORT);
+}
+
 void sort_pairs_u64(Ctx* c, const u64* kin, u64* kout, const i32* vin, i32* vout, i64 n, int bits) {
     if (n <= 0) return;
     if (bits < 1) bits = 1;

@@ -347,3 +347,41 @@ def test_no_chains_ablation():
         assert np.array_equal(rho, res.rho(0))
         assert g.hgp_evaluate()["conn"] == res.conn
         g.close()
+
+
+def test_dense_work_counters():
+    # the multiply-adds the library reports for the two dense products equal
+    # the padded-size formulas: (planes + 1) x 128^2 x tile pairs x Epad for
+    # the proposal, planes x Npad x Ppad x Epad for the moves
+    from paper_2605_20497_amd import Partitioner
+    hg = W.random_snn(1024, 15, 3)
+    g = Partitioner(profile=True, profile_families=("dense_gemm", "gains_gemm"), dense_proposal=True,
+                    dense_gains=True)
+    g.load(hg)
+    g.hgp_set_limits(64, 256, 0)
+    nl = g.hgp_coarsen()
+    g.hgp_refine()
+    work = g.hgp_kernel_work()
+    st = g.hgp_kernel_stats()
+    levels = g.hgp_get_levels()
+    hw = hg.hedge_w.astype(np.int64)
+    exp_p = 0
+    for lv in range(st["dense_gemm"][0]):
+        N, E = int(levels[lv, 0]), int(levels[lv, 1])
+        card = np.maximum(np.diff(g.hgp_get_level_graph(lv, what=("he_off",))[0]), 1)
+        t = np.maximum(1, (hw[:E] << 16) // card)
+        planes = 1
+        while planes <= 3 and (int(t.max()) >> (7 * planes)) != 0:
+            planes += 1
+        nt = (N + 127) // 128
+        epad = (((E + 31) // 32 + 3) // 4 * 4) * 32
+        exp_p += nt * (nt + 1) // 2 * 128 * 128 * epad * (planes + 1)
+    assert st["dense_gemm"][0] == nl or st["dense_gemm"][0] == nl - 1
+    assert work["dense_gemm"] == exp_p
+    nparts = int(levels[nl - 1, 0])
+    ppad = (nparts + 127) // 128 * 128
+    assert st["gains_gemm"][0] >= nl  # at least one repetition per level
+    per_level = [(int(levels[lv, 0]) + 127) // 128 * 128 * ppad *
+                 ((((int(levels[lv, 1]) + 31) // 32 + 3) // 4 * 4) * 32) for lv in range(nl)]
+    assert work["gains_gemm"] % 1 == 0 and work["gains_gemm"] >= sum(per_level)
+    g.close()
