@@ -956,11 +956,6 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
 // events where the all-pairs kernel compares it with every mover of e.
 // For h-edges of at most cap pins; T = 2^tbits >= 2 * cap table slots.  The
 // table also carries e's row counts, so no search of the row is needed.
-struct InseqEv {
-    i32 q;
-    i32 link;  // ((next event + 1) << 1) | destination-pin flag of the mover
-};
-
 __device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inserted) {
     const u32 tmask = (1u << tbits) - 1u;
     u32 h = ((u32)p * 0x9E3779B1u) >> (32 - tbits);
@@ -981,22 +976,25 @@ __device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inser
     return -1;  // unreachable: the table has a slot for every part of 2 * cap movers
 }
 
+// Shared memory per h-edge (one wave): the movers' sequence positions and
+// packed (source slot | destination slot << 10 | pin slot << 20), the table
+// (keys, list heads, packed row counts) and one 32-bit link per event:
+// ((next event + 1) << 1) | destination-pin flag; event 2i leaves mover i's
+// source part, 2i + 1 enters its destination part.  16 bytes per mover and
+// 12 per table slot.
 __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
     const i32* __restrict__ len, unsigned char* code, int cap, int tbits) {
-    // shared memory: cap movers, then T keys, T list heads, T packed counts
-    // (pins | inbound pins << 16) of the table's parts, and 2 * cap events.
-    // The table holds e's row parts and the movers' destination parts: at
-    // most 2 * cap keys.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = 1 << tbits;
-    MoverRec* mv = (MoverRec*)smem_raw;
-    i32* tkey = (i32*)(mv + cap);
-    i32* thead = tkey + T;
-    u32* tcnt = (u32*)(thead + T);
-    InseqEv* ev = (InseqEv*)(tcnt + T);
+    i32* mq = (i32*)smem_raw;          // cap
+    u32* mpk = (u32*)(mq + cap);       // cap
+    i32* tkey = (i32*)(mpk + cap);     // T
+    i32* thead = tkey + T;             // T
+    u32* tcnt = (u32*)(thead + T);     // T
+    i32* ev = (i32*)(tcnt + T);        // 2 * cap
     const int lane = threadIdx.x;
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
@@ -1008,10 +1006,8 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
             thead[t] = -1;
         }
         __syncthreads();
-        // Row entries and pins kInseqU * 64 at a time: every round of
-        // dependent loads (pin -> position -> part and destination) is issued
-        // for the whole group before any is used.
-        for (i32 r0 = 0; r0 < L; r0 += kInseqU * kWave) {  // the row parts are distinct
+        // e's row parts with their counts first (distinct parts)
+        for (i32 r0 = 0; r0 < L; r0 += kInseqU * kWave) {
             i32 pp[kInseqU];
             u32 cc[kInseqU];
 #pragma unroll
@@ -1030,6 +1026,10 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
                 }
             }
         }
+        __syncthreads();
+        // Movers: index by ballot, table slots of their parts (a source part
+        // is in the row; a destination part may be new, with no pins in e),
+        // and their two events, pushed on the parts' lists.
         int k = 0;
         for (i64 base = a; base < b; base += kInseqU * kWave) {
             i32 mm[kInseqU], qq[kInseqU], ps[kInseqU], pd[kInseqU];
@@ -1052,64 +1052,52 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
                 const int is_mv = (int)(qq[u] < M);
                 const u64 mask = __ballot(is_mv);
                 if (is_mv) {
-                    MoverRec r;
-                    r.q = qq[u];
-                    r.ps = ps[u];
-                    r.pd = pd[u];
-                    r.slot = (i32)((j - a) << 1) | (i32)(j >= d0);
-                    mv[k + __popcll(mask & lt_mask)] = r;
+                    const i32 i = k + __popcll(mask & lt_mask);
+                    int ins_s, ins_d;
+                    const i32 ts = part_slot(tkey, tbits, ps[u], ins_s);
+                    const i32 td = part_slot(tkey, tbits, pd[u], ins_d);
+                    if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
+                    if (ins_d) tcnt[td] = 0u;
+                    const i32 dj = (i32)(j >= d0);
+                    const i32 ns = atomicExch(&thead[ts], 2 * i);
+                    const i32 nd = atomicExch(&thead[td], 2 * i + 1);
+                    ev[2 * i] = ((ns + 1) << 1) | dj;
+                    ev[2 * i + 1] = ((nd + 1) << 1) | dj;
+                    mq[i] = qq[u];
+                    mpk[i] = (u32)ts | ((u32)td << 10) | ((u32)(j - a) << 20) | ((u32)dj << 30);
                 }
                 k += __popcll(mask);
             }
         }
         __syncthreads();
-        // Table slots of the movers' parts (a source part is in e's row; a
-        // destination part may be new, with no pins in e), and the events.
         for (int i = lane; i < k; i += kWave) {
-            MoverRec me = mv[i];
-            int ins_s, ins_d;
-            const i32 ts = part_slot(tkey, tbits, me.ps, ins_s);
-            const i32 td = part_slot(tkey, tbits, me.pd, ins_d);
-            if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
-            if (ins_d) tcnt[td] = 0u;
-            const i32 dj = me.slot & 1;
-            const i32 ns = atomicExch(&thead[ts], 2 * i);
-            const i32 nd = atomicExch(&thead[td], 2 * i + 1);
-            ev[2 * i].q = me.q;
-            ev[2 * i].link = ((ns + 1) << 1) | dj;
-            ev[2 * i + 1].q = me.q;
-            ev[2 * i + 1].link = ((nd + 1) << 1) | dj;
-            me.ps = ts;
-            me.pd = td;
-            mv[i] = me;
-        }
-        __syncthreads();
-        for (int i = lane; i < k; i += kWave) {
-            const MoverRec me = mv[i];
+            const i32 q = mq[i];
+            const u32 pk = mpk[i];
+            const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
             i32 x[2], xi[2];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 i32 acc = 0, acci = 0;
-                i32 idx = thead[side ? me.pd : me.ps];
+                i32 idx = thead[side ? td : ts];
                 while (idx >= 0) {
-                    const InseqEv o = ev[idx];
-                    const i32 sg = (i32)(o.q < me.q) * ((idx & 1) ? 1 : -1);
+                    const i32 lk = ev[idx];
+                    const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
                     acc += sg;
-                    acci += sg * (o.link & 1);
-                    idx = (o.link >> 1) - 1;
+                    acci += sg * (lk & 1);
+                    idx = (lk >> 1) - 1;
                 }
                 x[side] = acc;
                 xi[side] = acci;
             }
-            const u32 c0s = tcnt[me.ps], c0d = tcnt[me.pd];
+            const u32 c0s = tcnt[ts], c0d = tcnt[td];
             const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
             const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
             const i32 cis = (i32)(c0s >> 16) + xi[0];
             const i32 cid = (i32)(c0d >> 16) + xi[1];
-            const i32 di = me.slot & 1;
+            const i32 di = (i32)((pk >> 30) & 1u);
             const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
                              ((u32)(di & (int)(cid == 0)) << 3);
-            code[a + (me.slot >> 1)] = (unsigned char)bits;
+            code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
         }
         __syncthreads();
     }
@@ -1557,7 +1545,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const int capl = std::min(cap, kInseqListMax);
         int tbits = 1;
         while ((1 << tbits) < 2 * capl) ++tbits;
-        const size_t lds_l = (sizeof(MoverRec) + 2 * sizeof(InseqEv)) * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
+        const size_t lds_l = (size_t)16 * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
         LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, lds_l, L.E,
                (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl,
                tbits);
