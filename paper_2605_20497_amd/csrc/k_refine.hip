@@ -642,6 +642,53 @@ __global__ __launch_bounds__(1024) void k_chain_compact1(i32 M, int round, unsig
     if (threadIdx.x == 0) pls[M] = carry;
 }
 
+// The rest of a chain round after the proposals, in one workgroup (up to
+// kChainCompactMax moves): acceptance (both phases), links and their count
+// folded into the totals (a round that links nothing ends the rounds), and,
+// when another round follows, its moves without a predecessor, their scan and
+// compaction and the reset of the accumulators.  Replaces four launches per
+// round.
+__global__ __launch_bounds__(1024) void k_chain_tail1(i32 M, int next, unsigned long long* rs, i32* pred, i32* succ,
+                                                      i32* pls, i32* cl, u64* accG, i32* accN,
+                                                      const i32* __restrict__ snode, const i32* __restrict__ prop,
+                                                      const i64* __restrict__ propG) {
+    __shared__ i32 red[16];
+    __shared__ unsigned long long red_l[16];
+    __shared__ int active;
+    if (threadIdx.x == 0) active = (int)(rs[0] != 0);
+    __syncthreads();
+    if (!active) return;
+    for (i64 i = threadIdx.x; i < M; i += blockDim.x) accept_a_elem(i, prop, propG, accG);
+    __syncthreads();
+    for (i64 i = threadIdx.x; i < M; i += blockDim.x) accept_b_elem(i, prop, propG, accG, snode, accN);
+    __syncthreads();
+    unsigned long long lk = 0;
+    for (i64 i = threadIdx.x; i < M; i += blockDim.x)
+        lk += (unsigned long long)link_elem(i, prop, propG, accG, accN, snode, pred, succ);
+    lk = block_sum(lk, red_l);  // ends with a barrier
+    if (threadIdx.x == 0) {
+        rs[2] += lk;
+        rs[1] = 0;
+        if (lk == 0) rs[0] = 0;
+    }
+    if ((lk == 0) | !next) return;
+    i32 carry = 0;
+    for (i64 base = 0; base < M; base += blockDim.x) {
+        const i64 i = base + threadIdx.x;
+        const i32 v = i < M ? (pred[i] < 0 ? 1 : 0) : 0;
+        i32 tot;
+        const i32 ex = block_excl_scan(v, red, &tot);
+        if (i < M) {
+            pls[i] = carry + ex;
+            if (v) cl[carry + ex] = (i32)i;
+            accG[i] = 0;
+            accN[i] = -1;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) pls[M] = carry;
+}
+
 // All chain rounds in one workgroup, for move counts so small that per-round
 // launches and host checks would dominate (beyond a few hundred moves the
 // windowed proposals, one wave per move, need the whole GPU).  Same steps,
@@ -1444,32 +1491,41 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     if (M <= kChainSingleMax && rounds > 0)
         LAUNCH(c, KF_CHAINS, k_chain_rounds, 1, 1024, 0, (i32)M, rs, pred, succ, pl, pls, cl, accG, accN, spd, segb,
                sege, sg, snw, snin, snode, prop, propG);
-    // Up to kChainCompactMax moves, a round's first three steps and the
-    // previous round's end run as one single-workgroup launch.
+    // Up to kChainCompactMax moves, everything but the windowed proposals of
+    // a round runs in single-workgroup launches: two launches per round.
     const bool one = M <= kChainCompactMax;
-    for (int round = 0; round < rounds && M > kChainSingleMax; ++round) {
-        if (one) {
-            LAUNCH(c, KF_CHAINS, k_chain_compact1, 1, 1024, 0, (i32)M, round, rs, pred, pls, cl, accG, accN);
-        } else {
-            LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
-            scan_excl_i32(c, pl, pls, M);
-            LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
+    if (one && M > kChainSingleMax && rounds > 0)
+        LAUNCH(c, KF_CHAINS, k_chain_compact1, 1, 1024, 0, (i32)M, 0, rs, pred, pls, cl, accG, accN);
+    for (int round = 0; round < rounds && M > kChainSingleMax && one; ++round) {
+        // proposals on the whole device, the rest of the round (and the next
+        // round's compaction) in one workgroup
+        LAUNCH(c, KF_CHAINS, k_chain_propose, wblocks, 256, 0, (i32)M, rs, succ, spd, segb, sege, pls, cl, sg, snw,
+               snin, snode, prop, propG);
+        LAUNCH(c, KF_CHAINS, k_chain_tail1, 1, 1024, 0, (i32)M, (int)(round + 1 < rounds), rs, pred, succ, pls, cl,
+               accG, accN, snode, prop, propG);
+        if (round == 1 || round == 3 || round == 7) {
+            i64 active = 0;
+            read_back(c, rs, &active, 1, 8);
+            if (!active) break;
         }
+    }
+    for (int round = 0; round < rounds && M > kChainSingleMax && !one; ++round) {
+        LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
+        scan_excl_i32(c, pl, pls, M);
+        LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
         LAUNCH(c, KF_CHAINS, k_chain_propose, wblocks, 256, 0, (i32)M, rs, succ, spd, segb, sege, pls, cl, sg, snw,
                snin, snode, prop, propG);
         LAUNCH(c, KF_CHAINS, k_chain_accept_a, nbM, 256, 0, (i32)M, rs, prop, propG, accG);
         LAUNCH(c, KF_CHAINS, k_chain_accept_b, nbM, 256, 0, (i32)M, rs, prop, propG, accG, snode, accN);
         LAUNCH(c, KF_CHAINS, k_chain_link, nbM, 256, 0, (i32)M, rs, prop, propG, accG, accN, snode, pred, succ);
-        if (!one) LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);
+        LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);
         // Later rounds of a finished chain build are no-ops; stop issuing them.
         if (round == 1 || round == 3 || round == 7) {
-            i64 st[2] = {0, 0};
-            read_back(c, rs, st, 2, 8);
-            // with `one` this round's links are folded by the next round's first launch
-            if (!st[0] || (one && st[1] == 0)) break;
+            i64 active = 0;
+            read_back(c, rs, &active, 1, 8);
+            if (!active) break;
         }
     }
-    if (one && M > kChainSingleMax && rounds > 0) LAUNCH(c, KF_CHAINS, k_round_end, 1, 1, 0, rs);  // fold the last round
 
     // Chains: cycles, heads, ranks.
     const int K = bits_for((u64)M) + 1;
