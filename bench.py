@@ -42,10 +42,10 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "257e5d7724dbc9955df7210acd5ff98e6f355226ed8a0fb0a9070296867692af"): 6517537645,
-    ("k_gains16", "29367d2bf4230b3d4849440a91240e501423b4ba2e55cc481f54669a7d8e7e61"): 5214535996,
-    ("k_dense_gemm", "2440a8cc21458bdd17362fcddadebc2f2da4da9212c309e760ba05c83d6a9d0f"): 2568522303,
-    ("k_conn_gemm", "2440a8cc21458bdd17362fcddadebc2f2da4da9212c309e760ba05c83d6a9d0f"): 783950245,
+    ("k_propose", "0e3c169363ba74aab164c106247ed503589c1509929fbe8922f1566f5c8296ac"): 6517665132,
+    ("k_gains16", "9192abfcaf825eca499f68826bc1c8bb215c6713f946c73b7ea02067de5d6563"): 5213681330,
+    ("k_dense_gemm", "e7f47ba45335a69ed464630338d37b2d4b8a88f3796e26d9e04804f1a65593ad"): 2563305081,
+    ("k_conn_gemm", "e7f47ba45335a69ed464630338d37b2d4b8a88f3796e26d9e04804f1a65593ad"): 783948814,
 }
 
 
