@@ -170,51 +170,85 @@ __device__ __forceinline__ unsigned long long vec_bin<unsigned long long>(const 
 // Grouped pin sweep of one wave batch (lane l holds h-edge l's metadata):
 // h-edges G at a time; each h-edge's sources and this pass's destinations form
 // one index space [0, cs + cd) (destination q at offset q + dsh from the
-// h-edge start), read GU * 64 entries per h-edge and step, so G * GU loads per
+// h-edge start), read GU * 64 entries per h-edge and chunk, so G * GU loads per
 // lane are in flight.  Destinations lie in the pass's id range (pass bounds);
-// sources are tested.
+// sources are tested.  The sweep is software pipelined: the loads of the next
+// chunk are issued before the updates of the current one, in two register sets
+// used alternately.
+template <int G, int GU, typename BIN>
+struct GroupChunk {
+    i32 m[G][GU];    // pin id, n when the entry is past the h-edge's segment
+    BIN ad[G][GU];   // histogram increment of the entry
+    u32 src;         // bit g * GU + u: the entry is a source
+};
+
+// Issues the loads of chunk (i0, q0); returns the group's longest segment.
+template <int G, int GU, typename BIN, typename PIN>
+__device__ __forceinline__ i32 group_load(int i0, i32 q0, int nb, int lane, i32 n, const PIN* __restrict__ pins,
+                                          i64 e0, i32 cs, i32 cd, i32 dsh, BIN add, BIN add_in,
+                                          GroupChunk<G, GU, BIN>& c) {
+    i32 maxt = 0;
+    u32 srcm = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int sl = min(i0 + g, kWave - 1);
+        const PIN* rp = pins + bcast(e0, sl);  // wave-uniform row base
+        const i32 ns = bcast(cs, sl);
+        const i32 nt = i0 + g < nb ? ns + bcast(cd, sl) : 0;
+        const i32 sh = bcast(dsh, sl);
+        const BIN sa = bcast(add, sl), sai = bcast(add_in, sl);
+        maxt = max(maxt, nt);
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const i32 q = q0 + u * kWave + lane;
+            const int is_src = (int)(q < ns);
+            c.m[g][u] = q < nt ? (i32)rp[q + (is_src ? 0 : sh)] : n;
+            c.ad[g][u] = is_src ? sa : sai;
+            srcm |= (u32)is_src << (g * GU + u);
+        }
+    }
+    c.src = srcm;
+    return maxt;
+}
+
+template <int G, int GU, typename BIN>
+__device__ __forceinline__ void group_apply(const GroupChunk<G, GU, BIN>& c, i32 n, i32 lo, i32 hi, BIN* bins) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const i32 m = c.m[g][u];
+            const int is_src = (int)((c.src >> (g * GU + u)) & 1u);
+            const int ok = (int)(m != n) & (!is_src | (int)((u32)(m - lo) < (u32)(hi - lo)));
+            if (ok) atomicAdd(&bins[m - lo], c.ad[g][u]);
+        }
+}
+
 template <int G, int GU, typename BIN, typename PIN>
 __device__ __forceinline__ void propose_group(int nb, int lane, i32 n, i32 lo, i32 hi, const PIN* __restrict__ pins,
                                               i64 e0, i32 cs, i32 cd, i32 dsh, BIN add, BIN add_in, BIN* bins) {
-    for (int i0 = 0; i0 < nb; i0 += G) {
-        const PIN* rp[G];
-        i32 ns[G], nt[G], sh[G];
-        BIN sa[G], sai[G];
-        i32 maxt = 0;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int src = min(i0 + g, kWave - 1);
-            const int on = (int)(i0 + g < nb);
-            rp[g] = pins + bcast(e0, src);  // wave-uniform row base
-            const i32 s1 = bcast(cs, src), d1 = bcast(cd, src);
-            ns[g] = s1;
-            nt[g] = on ? s1 + d1 : 0;
-            sh[g] = bcast(dsh, src);
-            sa[g] = bcast(add, src);
-            sai[g] = bcast(add_in, src);
-            maxt = max(maxt, nt[g]);
+    if (nb <= 0) return;
+    GroupChunk<G, GU, BIN> c0, c1;
+    int i0 = 0;
+    i32 q0 = 0;
+    // chunk order: GU * 64 entries of the group at a time, then the next group
+    auto next = [&](i32 mt) {
+        q0 += GU * kWave;
+        if (q0 >= mt) {
+            i0 += G;
+            q0 = 0;
         }
-        for (i32 q0 = 0; q0 < maxt; q0 += GU * kWave) {
-            i32 mm[G][GU];
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int u = 0; u < GU; ++u) {
-                    const i32 q = q0 + u * kWave + lane;
-                    const i32 off = q + (q >= ns[g] ? sh[g] : 0);
-                    mm[g][u] = q < nt[g] ? (i32)rp[g][off] : n;
-                }
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int u = 0; u < GU; ++u) {
-                    const i32 q = q0 + u * kWave + lane;
-                    const i32 m = mm[g][u];
-                    const int is_src = (int)(q < ns[g]);
-                    const int ok = (int)(m != n) & (!is_src | (int)((u32)(m - lo) < (u32)(hi - lo)));
-                    if (ok) atomicAdd(&bins[m - lo], is_src ? sa[g] : sai[g]);
-                }
-        }
+    };
+    i32 mt = group_load<G, GU>(i0, q0, nb, lane, n, pins, e0, cs, cd, dsh, add, add_in, c0);
+    while (true) {
+        next(mt);
+        if (i0 < nb) mt = group_load<G, GU>(i0, q0, nb, lane, n, pins, e0, cs, cd, dsh, add, add_in, c1);
+        group_apply(c0, n, lo, hi, bins);
+        if (i0 >= nb) break;
+        next(mt);
+        if (i0 < nb) mt = group_load<G, GU>(i0, q0, nb, lane, n, pins, e0, cs, cd, dsh, add, add_in, c0);
+        group_apply(c1, n, lo, hi, bins);
+        if (i0 >= nb) break;
     }
 }
 

@@ -65,6 +65,14 @@ __global__ void k_dense_digits(i32 E, i32 Epad, int NP, const i64* __restrict__ 
     }
 }
 
+// 0 / 1 bytes -> 0x00 / 0x7F bytes: 0x80 - b per byte never borrows across
+// bytes, and the low 7 bits cover every 7-bit digit it is ANDed with.  (A
+// shift and subtract, x * 255, is turned into a quarter-rate multiply.)
+__device__ __forceinline__ v4i digit_mask(v4i b) {
+    const v4i k80 = {(int)0x80808080u, (int)0x80808080u, (int)0x80808080u, (int)0x80808080u};
+    return (k80 - b) & 0x7F7F7F7F;
+}
+
 // 16 bits -> 16 bytes of 0 / 1, bit j into byte j (four nibbles, each spread
 // by one multiply: the shifted copies do not overlap, so nothing carries).
 // Both factors fit 24 bits, so the full-rate 24-bit multiply is exact.
@@ -87,7 +95,7 @@ __device__ __forceinline__ u32 word_of(const uint4& q, int s) {
 // h-edges at a time (4 words per row; thread t holds rows t and t + 256 of
 // the tile's A rows, D rows, A columns, D columns).  For each 32 h-edges the
 // threads expand their words once into bytes in shared memory (A columns as
-// 0x00 / 0xFF masks, ready to be ANDed with the digit bytes), double
+// 0x00 / 0x7F masks, ready to be ANDed with the digit bytes), double
 // buffered, and every wave reads its MFMA operands from there: the expansion
 // is done once per workgroup instead of once per wave that uses a row.
 // Lane l holds row (l mod 32) of its A-side block and column (l mod 32) of
@@ -156,8 +164,8 @@ __global__ __launch_bounds__(256, NP <= 2 ? 2 : 1) void k_dense_gemm(int ntile, 
                 const v4i e0 = spread16(wa & 0xFFFFu), e1 = spread16(wa >> 16);
                 v4i f0 = spread16(wb & 0xFFFFu), f1 = spread16(wb >> 16);
                 if (amask) {
-                    f0 = (f0 << 8) - f0;  // 0x00 / 0xFF bytes
-                    f1 = (f1 << 8) - f1;
+                    f0 = digit_mask(f0);
+                    f1 = digit_mask(f1);
                 }
                 *(v4i*)&sx[buf][mrow][rr][0] = e0;
                 *(v4i*)&sx[buf][mrow][rr][16] = e1;
@@ -289,7 +297,7 @@ __global__ __launch_bounds__(256) void k_saving(i32 N, const i64* __restrict__ i
 
 // One workgroup per (node tile, partition tile, K split), 4 waves of 64 x 64
 // as in k_dense_gemm: node rows expanded to 0/1 bytes, partition rows (B
-// word-major) to 0x00 / 0xFF masks ANDed with the weight digits, once per
+// word-major) to 0x00 / 0x7F masks ANDed with the weight digits, once per
 // workgroup per 32 h-edges in shared memory.  Writes conn partials (int32) of
 // the split.
 template <int NP>
@@ -343,8 +351,8 @@ __global__ __launch_bounds__(256, 2) void k_conn_gemm(int ntile_p, i32 W4, i32 w
                 const u32 wd = word_of(x, s);
                 v4i e0 = spread16(wd & 0xFFFFu), e1 = spread16(wd >> 16);
                 if (mrow) {
-                    e0 = (e0 << 8) - e0;  // 0x00 / 0xFF bytes
-                    e1 = (e1 << 8) - e1;
+                    e0 = digit_mask(e0);
+                    e1 = digit_mask(e1);
                 }
                 *(v4i*)&sx[buf][mrow][rr][0] = e0;
                 *(v4i*)&sx[buf][mrow][rr][16] = e1;
