@@ -8,7 +8,9 @@
 // reaches both the lane's PI-th best (once the lane holds PI) and the block
 // floor (the largest PI-th best of any full lane list): PI valid candidates
 // already beat anything below either.  That bound is one compare on the packed
-// bin.  Bins that pass are compacted through a per-wave ring in shared memory
+// bin.  After each scoring round the wave also raises the floor to the best
+// score that PI of its lanes all reach with their best entries.  Bins that
+// pass are compacted through a per-wave ring in shared memory
 // and scored 64 at a time (noise hash, validity operands, insertion), so the
 // costly part runs on full waves however sparse the survivors are.  Which lane
 // scores a bin does not matter: every bin reaches exactly one lane list or is
@@ -111,6 +113,23 @@ __device__ __forceinline__ void sel_drain(SelQueue<BIN>& q, u32& qh, u32& qn, u3
     const int ok = pick & (int)(c.nw_n + nwm <= c.omega) & (int)((i64)c.nin_n + ninm - itr <= c.delta);
     if (ok) L.insert(sc, m);  // ok is computed bitwise; the insertion is branch-free
     if ((int)L.full() & (int)(L.s[PI - 1] > fl)) atomicMax(c.floor, (unsigned long long)L.s[PI - 1]);
+    // Union bound across the wave: if G lanes (G the smallest power of two
+    // >= PI) all hold a best entry scoring at least x, the block already has
+    // PI distinct valid candidates scoring >= x, so x is a floor too.  It
+    // rises long before any single lane list fills with high scores.
+    constexpr int G = PI <= 1 ? 1 : PI <= 2 ? 2 : PI <= 4 ? 4 : 8;
+    u64 gb = L.m[0] >= 0 ? L.s[0] : 0ull;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        const u64 t = __shfl_xor(gb, o, kWave);
+        gb = t < gb ? t : gb;
+    }
+#pragma unroll
+    for (int o = G; o < kWave; o <<= 1) {
+        const u64 t = __shfl_xor(gb, o, kWave);
+        gb = t > gb ? t : gb;
+    }
+    if ((int)(lane == 0) & (int)(gb > fl)) atomicMax(c.floor, (unsigned long long)gb);
 }
 
 // Wave-collective: every lane of the wave calls it, keep says whether the
