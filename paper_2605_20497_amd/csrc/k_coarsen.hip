@@ -277,6 +277,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_propose(
     sn.nw = nw;
     sn.inc_nin = inc_nin;
     sn.floor = &s_floor;
+    sn.union_floor = 1;
     const int npass = (int)((N + R - 1) / R);
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     const int nalloc4 = propose_bins_alloc(R) / kBinsPerVec;
@@ -444,6 +445,7 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     sn.nw = nw;
     sn.inc_nin = inc_nin;
     sn.floor = &s_floor;
+    sn.union_floor = 1;
     const u32 cmask = (u32)C - 1;
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     for (int i = threadIdx.x; i < C; i += blockDim.x) {

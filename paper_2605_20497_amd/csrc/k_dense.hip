@@ -485,6 +485,7 @@ __global__ __launch_bounds__(256) void k_dense_select(i32 N, i64 Npad, int kspli
     sn.nw = nw;
     sn.inc_nin = inc_nin;
     sn.floor = &s_floor;
+    sn.union_floor = 0;  // dense rows fill the lane lists with high scores early: the bound would not pay
     const int wv = wave_id();
     for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
         sn.n = n;

@@ -8,7 +8,7 @@
 // reaches both the lane's PI-th best (once the lane holds PI) and the block
 // floor (the largest PI-th best of any full lane list): PI valid candidates
 // already beat anything below either.  That bound is one compare on the packed
-// bin.  After each scoring round the wave also raises the floor to the best
+// bin.  After each scoring round the wave can also raise the floor to the best
 // score that PI of its lanes all reach with their best entries.  Bins that
 // pass are compacted through a per-wave ring in shared memory
 // and scored 64 at a time (noise hash, validity operands, insertion), so the
@@ -66,6 +66,7 @@ struct SelNode {
     i32 n, nin_n;
     i64 nw_n, omega, delta;
     int all_valid;  // every pair (n, m) is valid: no per-candidate loads
+    int union_floor;  // raise the floor by the wave-wide union bound after each scoring round
     const i32* nw;
     const i32* inc_nin;
     unsigned long long* floor;  // block floor, in shared memory
@@ -117,6 +118,7 @@ __device__ __forceinline__ void sel_drain(SelQueue<BIN>& q, u32& qh, u32& qn, u3
     // >= PI) all hold a best entry scoring at least x, the block already has
     // PI distinct valid candidates scoring >= x, so x is a floor too.  It
     // rises long before any single lane list fills with high scores.
+    if (!c.union_floor) return;
     constexpr int G = PI <= 1 ? 1 : PI <= 2 ? 2 : PI <= 4 ? 4 : 8;
     u64 gb = L.m[0] >= 0 ? L.s[0] : 0ull;
 #pragma unroll
