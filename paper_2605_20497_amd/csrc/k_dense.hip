@@ -85,6 +85,17 @@ __device__ __forceinline__ v4i spread16(u32 bits) {
     return r;
 }
 
+// Workgroups are handed to the 8 XCDs round robin (b mod 8), each XCD with
+// its own L2.  The product tiles are remapped so that each XCD takes a
+// contiguous run of tile indices, whose neighbours share a row tile: its bit
+// rows stay in that XCD's L2 instead of being fetched by all eight.  A
+// bijection on the first 8 * (nb / 8) indices, the identity on the rest.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / kXcds;
+    return b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
+}
+
 __device__ __forceinline__ u32 word_of(const uint4& q, int s) {
     return s == 0 ? q.x : s == 1 ? q.y : s == 2 ? q.z : q.w;
 }
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(256, NP <= 2 ? 2 : 1) void k_dense_gemm(int ntile, 
                                                     i32 Epad, u64* part, i64 Npad, int ib) {
     __shared__ __align__(16) unsigned char sx[2][4][kTile][kRowB];  // [buffer][A rows, D rows, A cols, D cols]
     __shared__ uint4 sdig[2][NP][8];  // [buffer][plane][16-byte group of the 128 h-edges]
-    int ti = 0, rem = blockIdx.x;
+    int ti = 0, rem = xcd_tile(blockIdx.x, gridDim.x);
     while (rem >= ntile - ti) {
         rem -= ntile - ti;
         ++ti;
@@ -306,7 +317,8 @@ __global__ __launch_bounds__(256, 2) void k_conn_gemm(int ntile_p, i32 W4, i32 w
                                                       i32 Epad, i32* out, i64 Npad, i64 Ppad) {
     __shared__ __align__(16) unsigned char sx[2][2][kTile][kRowB];  // [buffer][node rows, partition rows]
     __shared__ uint4 sdig[2][NP][8];
-    const int ti = blockIdx.x / ntile_p, tj = blockIdx.x % ntile_p;
+    const int tb = xcd_tile(blockIdx.x, gridDim.x);
+    const int ti = tb / ntile_p, tj = tb % ntile_p;
     const i32 wbeg = blockIdx.y * wsplit;
     const i32 wend = min(W4, wbeg + wsplit);
     const int t = threadIdx.x;
