@@ -42,10 +42,10 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "f7fa976e5169cc9f47705fbc397cf58da6bed201c7fde1a3c8baa275bd260bd7"): 6490969441,
-    ("k_gains16", "9192abfcaf825eca499f68826bc1c8bb215c6713f946c73b7ea02067de5d6563"): 5212460893,
-    ("k_dense_gemm", "ee3a084bbfca6e33a35ec0f3ce6594c54c591f1ebadb8c270001238d4ddf746b"): 2538597844,
-    ("k_conn_gemm", "ee3a084bbfca6e33a35ec0f3ce6594c54c591f1ebadb8c270001238d4ddf746b"): 779279995,
+    ("k_propose", "f7fa976e5169cc9f47705fbc397cf58da6bed201c7fde1a3c8baa275bd260bd7"): 6491750192,
+    ("k_gains16", "9192abfcaf825eca499f68826bc1c8bb215c6713f946c73b7ea02067de5d6563"): 5215199965,
+    ("k_dense_gemm", "a31e6aa2136bc7c4b852743d8e041bc2754fb1b017b51296e981a9eda0b502c9"): 1777847794,
+    ("k_conn_gemm", "a31e6aa2136bc7c4b852743d8e041bc2754fb1b017b51296e981a9eda0b502c9"): 556106454,
 }
 
 
