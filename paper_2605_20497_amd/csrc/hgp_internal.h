@@ -2,6 +2,8 @@
 // Device helpers, the context layout and the kernel launchers.
 #pragma once
 
+#include <initializer_list>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -161,6 +163,18 @@ void sort_pairs_u32(Ctx* c, const u32* kin, u32* kout, const i32* vin, i32* vout
 void sort_pairs_u64(Ctx* c, const u64* kin, u64* kout, const i32* vin, i32* vout, i64 n, int bits);
 void sort_pairs_u32_u64(Ctx* c, const u32* kin, u32* kout, const u64* vin, u64* vout, i64 n, int bits);
 void fill_i32(Ctx* c, i32* p, i32 v, i64 n);
+// Sets up to kFillMax buffers to a 32-bit pattern in one launch (n in 32-bit
+// words; entries with n <= 0 are skipped).
+struct FillItem {
+    void* p;
+    i64 n;
+    u32 v;
+};
+constexpr int kFillMax = 8;
+struct FillList {
+    FillItem it[kFillMax];
+};
+void fill_many(Ctx* c, std::initializer_list<FillItem> items);
 void fill_i64(Ctx* c, i64* p, i64 v, i64 n);
 void iota_i32(Ctx* c, i32* p, i64 n);
 void gather_i32(Ctx* c, const i32* src, const i32* idx, i32* dst, i64 n);  // dst[i] = src[idx[i]]

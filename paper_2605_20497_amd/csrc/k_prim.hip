@@ -100,6 +100,13 @@ __global__ void k_fill(T* p, T v, i64 n) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// One grid row per buffer of the list.
+__global__ void k_fill_many(FillList L) {
+    const FillItem f = L.it[blockIdx.y];
+    u32* p = (u32*)f.p;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < f.n; i += (i64)gridDim.x * blockDim.x) p[i] = f.v;
+}
+
 __global__ void k_iota(i32* p, i64 n) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = (i32)i;
 }
@@ -167,6 +174,18 @@ void sort_pairs_u64(Ctx* c, const u64* kin, u64* kout, const i32* vin, i32* vout
 
 void fill_i32(Ctx* c, i32* p, i32 v, i64 n) {
     if (n > 0) LAUNCH(c, KF_MISC, k_fill<i32>, grid_for(n, 256, 4096), 256, 0, p, v, n);
+}
+void fill_many(Ctx* c, std::initializer_list<FillItem> items) {
+    FillList L{};
+    int k = 0;
+    i64 mx = 0;
+    for (const FillItem& it : items) {
+        if (it.n <= 0) continue;
+        if (k == kFillMax) fail(HGP_E_INVALID, "fill_many: more than kFillMax buffers");
+        L.it[k++] = it;
+        mx = std::max(mx, it.n);
+    }
+    if (k > 0) LAUNCH(c, KF_MISC, k_fill_many, dim3(grid_for(mx, 256, 4096), k), 256, 0, L);
 }
 void fill_i64(Ctx* c, i64* p, i64 v, i64 n) {
     if (n > 0) LAUNCH(c, KF_MISC, k_fill<i64>, grid_for(n, 256, 4096), 256, 0, p, v, n);

@@ -1378,8 +1378,7 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsign
         LAUNCH(c, KF_PHI, k_narrow16, grid_for(L.P, 256, c->num_cu * 8), 256, 0, L.P, (const i32*)f.part,
                (const i32*)f.cnt, f.part16);
     }
-    HIPC(hipMemsetAsync(f.psize, 0, sizeof(i64) * nparts, c->stream));
-    HIPC(hipMemsetAsync(f.pD, 0, sizeof(i64) * nparts, c->stream));
+    fill_many(c, {{f.psize, 2 * (i64)nparts, 0u}, {f.pD, 2 * (i64)nparts, 0u}});
     LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), f.psize);
     if (L.E > 0) {
         const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
@@ -1449,6 +1448,24 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     info.moves = M;
     if (M == 0) return info;
     const int nbM = grid_for(M, 256, c->num_cu * 8);
+    // Every buffer of the rest of the repetition that starts from a constant,
+    // set in one launch.
+    i32* sidx = wsp<i32>(c, WS_SIDX, N);
+    i32* segb = wsp<i32>(c, WS_SEGB, nparts);
+    i32* sege = wsp<i32>(c, WS_SEGE, nparts);
+    i32* pred = wsp<i32>(c, WS_PRED, M);
+    i32* succ = wsp<i32>(c, WS_SUCC, M);
+    i64* cg = wsp<i64>(c, WS_CG, M);
+    i32* clen = wsp<i32>(c, WS_CLEN, M);
+    i32* dvq = wsp<i32>(c, WS_DVQ, M);
+    fill_many(c, {{sidx, N, ~0u},
+                  {segb, nparts, 0u},
+                  {sege, nparts, 0u},
+                  {pred, M, ~0u},
+                  {succ, M, ~0u},
+                  {cg, 2 * M, 0u},
+                  {clen, M, 0u},
+                  {dvq, M, 0u}});
 
     // Moves sorted by (p_s, -gain, id) (Sec. VI-C).
     u64* mkey = wsp<u64>(c, WS_MKEY, M);
@@ -1462,19 +1479,11 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i64* sg = wsp<i64>(c, WS_SG, M);
     i32* snw = wsp<i32>(c, WS_SNW, M);
     i32* snin = wsp<i32>(c, WS_SNIN, M);
-    i32* sidx = wsp<i32>(c, WS_SIDX, N);
-    fill_i32(c, sidx, -1, N);
     LAUNCH(c, KF_MOVES, k_sorted_attrs, nbM, 256, 0, (i32)M, snode, rho, mdst, mgain, L.nw(), L.inc_nin(), sps, spd,
            sg, snw, snin, sidx);
-    i32* segb = wsp<i32>(c, WS_SEGB, nparts);
-    i32* sege = wsp<i32>(c, WS_SEGE, nparts);
-    HIPC(hipMemsetAsync(segb, 0, sizeof(i32) * nparts, c->stream));
-    HIPC(hipMemsetAsync(sege, 0, sizeof(i32) * nparts, c->stream));
     LAUNCH(c, KF_MOVES, k_segments, nbM, 256, 0, (i32)M, sps, segb, sege);
 
     // Chain rounds.
-    i32* pred = wsp<i32>(c, WS_PRED, M);
-    i32* succ = wsp<i32>(c, WS_SUCC, M);
     i32* pl = wsp<i32>(c, WS_PL, M);
     i32* pls = wsp<i32>(c, WS_PLS, M + 1);
     i32* cl = wsp<i32>(c, WS_CL, M);
@@ -1482,8 +1491,6 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i64* propG = wsp<i64>(c, WS_PROPG, M);
     u64* accG = wsp<u64>(c, WS_ACCG, M);
     i32* accN = wsp<i32>(c, WS_ACCN, M);
-    fill_i32(c, pred, -1, M);
-    fill_i32(c, succ, -1, M);
     LAUNCH(c, KF_CHAINS, k_set_flag, 1, 1, 0, rs);
     const int wblocks = grid_for(M, 4, c->num_cu * 16);
     // flags bit 5: the ablation without chain rounds (every move its own chain)
@@ -1552,10 +1559,6 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         std::swap(R0, R1);
         std::swap(H0, H1);
     }
-    i64* cg = wsp<i64>(c, WS_CG, M);
-    i32* clen = wsp<i32>(c, WS_CLEN, M);
-    HIPC(hipMemsetAsync(cg, 0, sizeof(i64) * M, c->stream));
-    HIPC(hipMemsetAsync(clen, 0, sizeof(i32) * M, c->stream));
     LAUNCH(c, KF_RANK, k_chain_accum, nbM, 256, 0, (i32)M, H0, sg, cg, clen);
     i32* hf = wsp<i32>(c, WS_HF, N);
     i32* hpos = wsp<i32>(c, WS_HPOS, (size_t)N + 1);
@@ -1625,8 +1628,6 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     scan_excl_i64(c, ed, dex, M2);
     i32* segst = wsp<i32>(c, WS_SEGST, nparts);
     LAUNCH(c, KF_EVENTS, k_ev_segstart, nbE, 256, 0, M2, evk2, segst);
-    i32* dvq = wsp<i32>(c, WS_DVQ, M);
-    HIPC(hipMemsetAsync(dvq, 0, sizeof(i32) * M, c->stream));
     LAUNCH(c, KF_EVENTS, k_ev_transitions, nbE, 256, 0, M2, evk2, evi2, segst, sex, dex, f.psize, f.pD, c->omega,
            c->delta, dvq);
     i64* cex = wsp<i64>(c, WS_CEX, M + 1);
