@@ -42,10 +42,10 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "f7fa976e5169cc9f47705fbc397cf58da6bed201c7fde1a3c8baa275bd260bd7"): 6491750192,
-    ("k_gains16", "9192abfcaf825eca499f68826bc1c8bb215c6713f946c73b7ea02067de5d6563"): 5215199965,
-    ("k_dense_gemm", "a31e6aa2136bc7c4b852743d8e041bc2754fb1b017b51296e981a9eda0b502c9"): 1777847794,
-    ("k_conn_gemm", "a31e6aa2136bc7c4b852743d8e041bc2754fb1b017b51296e981a9eda0b502c9"): 556106454,
+    ("k_propose", "d67cc2b673d2efe632ec33285bccf0026b910079dcb412744d199253a4567321"): 6490584967,
+    ("k_gains16", "b5b11ca0e76f7ca5050bd209888309cc3e6c0d524927441c436cb89cfaba438e"): 5215055747,
+    ("k_dense_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 1778768553,
+    ("k_conn_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 556123040,
 }
 
 
