@@ -601,7 +601,10 @@ __global__ void k_round_end(unsigned long long* rs) {
     rs[1] = 0;
 }
 
-constexpr i64 kChainCompactMax = 1 << 16;  // largest move count of k_chain_compact1
+// Largest move count of k_chain_compact1 / k_chain_tail1.  One workgroup
+// takes about 2 us per 1,000 moves per round; the device-wide round (eight
+// launches) about 50 us, so larger move sets take the device-wide kernels.
+constexpr i64 kChainCompactMax = 1 << 14;
 
 // First step of a chain round for at most kChainCompactMax moves, in one
 // workgroup: fold the previous round's links into the totals (the
