@@ -410,6 +410,87 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
     }
 }
 
+// The same moves with one wave per node, for levels whose nodes have few
+// incident h-edges (at most kGainsWaveDeg on average) and at most
+// kGainsWaveParts partitions.  Each wave owns R bins, so a node costs no block
+// barriers or block reductions; with a 4-wave block per node those dominate
+// when a node has a handful of h-edges.
+constexpr i32 kGainsWaveParts = 2048;
+constexpr i64 kGainsWaveDeg = 128;
+
+__global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
+    i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
+    const unsigned short* __restrict__ partf, const i32* __restrict__ len, const i32* __restrict__ hw,
+    const i32* __restrict__ nw, const i32* __restrict__ rho, const i64* __restrict__ psize, i64 omega,
+    i32* move_dst, i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R, unsigned long long* work) {
+    extern __shared__ u32 bins_all[];  // R bins per wave, R >= nparts
+    const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
+    u32* bins = bins_all + (size_t)wv * R;
+    for (int i = lane; i < R; i += kWave) bins[i] = 0;
+    wave_sync();
+    const i64 stride = (i64)gridDim.x * nwv;
+    for (i64 n = (i64)blockIdx.x * nwv + wv; n < N; n += stride) {
+        const i32 ps = rho[n];
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        i64 saving = 0, wi = 0;
+        u64 visits = 0;
+        const i64 nw_n = nw[n];
+        for (i64 kb = a; kb < b; kb += kWave) {
+            const int nb = (int)min((i64)kWave, b - kb);
+            const int valid = (int)(lane < nb);
+            const i32 e = inc[valid ? kb + lane : kb];
+            const i64 r0 = he_off[e];
+            const i32 Le = len[e], we = hw[e];
+            const i32 L = valid ? Le : 0;
+            const i32 w = valid ? we : 0;
+            wi += w;
+            const i32 tot = wave_sum(L);
+            visits += (u64)tot;
+            const i32 avg = tot / max(nb, 1);
+            if (avg <= 64)
+                gains_group<16, 1, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+            else if (avg <= 128)
+                gains_group<8, 2, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+            else if (avg <= 192)
+                gains_group<6, 3, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+            else
+                gains_group<4, 4, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+        }
+        saving = wave_sum(saving);
+        wi = wave_sum(wi);
+        wave_sync();  // the wave's bin updates are visible to all its lanes
+        // Only partitions with conn(n,p) > W_I(n) - saving(n) give a positive gain.
+        const i64 need = wi - saving;
+        i64 bg = 0, bg2 = 0;  // best move, and best move that keeps size(p) + size(n) <= Omega
+        i32 bp = -1, bp2 = -1;
+        for (int sidx = lane; sidx < nparts; sidx += kWave) {
+            const u32 v = bins[sidx];
+            if (v == 0) continue;
+            bins[sidx] = 0;
+            if ((i64)v <= need) continue;
+            const i32 p = sidx;
+            const i64 g = (i64)v - need;
+            const int fits = (int)(nw_n + psize[p] <= omega);
+            const bool t = lex_better(g, p, bg, bp);
+            bg = t ? g : bg;
+            bp = t ? p : bp;
+            const bool t2 = (fits & (int)lex_better(g, p, bg2, bp2)) != 0;
+            bg2 = t2 ? g : bg2;
+            bp2 = t2 ? p : bp2;
+        }
+        wave_sync();  // bins cleared before the next node's updates
+        wave_lexmax_i64(bg, bp);
+        wave_lexmax_i64(bg2, bp2);
+        if (lane == 0) {
+            move_dst[n] = bp;
+            move_gain[n] = bp >= 0 ? bg : 0;
+            move_dst_sa[n] = bp2;
+            move_gain_sa[n] = bp2 >= 0 ? bg2 : 0;
+            if (work != nullptr) atomicAdd(work, (unsigned long long)visits);
+        }
+    }
+}
+
 __global__ void k_move_flags(i32 N, const i32* __restrict__ move_dst, i32* flag) {
     for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
         flag[n] = move_dst[n] >= 0 ? 1 : 0;
@@ -1423,7 +1504,15 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const size_t lds = sizeof(u32) * (size_t)R;
         const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 3 * 1024))));
         const int grid = (int)std::min<i64>(N, (i64)c->num_cu * per_cu * 2);
-        if (f.part16 && nparts <= R)  // half the bytes per row visit, one pass
+        if (f.part16 && nparts <= kGainsWaveParts && (i64)L.P <= kGainsWaveDeg * (i64)N) {
+            // few h-edges per node: one wave per node, bins per wave
+            const int Rw = (nparts + kWave - 1) / kWave * kWave;
+            const size_t ldsw = sizeof(u32) * (size_t)Rw * kGainsWaves;
+            const int gridw = (int)std::min<i64>((N + kGainsWaves - 1) / kGainsWaves, (i64)c->num_cu * 16);
+            LAUNCH(c, KF_GAINS, k_gains16w, gridw, kGainsWaves * kWave, ldsw, N, nparts, L.inc_off(), L.inc(),
+                   L.he_off(), (const unsigned short*)f.part16, f.len, c->hw(), L.nw(), rho, f.psize, c->omega,
+                   mdst_any, mgain_any, mdst_sa, mgain_sa, Rw, prof_work(c, KF_GAINS));
+        } else if (f.part16 && nparts <= R)  // half the bytes per row visit, one pass
             LAUNCH(c, KF_GAINS, k_gains16<true>, grid, kGainsWaves * kWave, lds, N, nparts, L.inc_off(), L.inc(),
                    L.he_off(), (const unsigned short*)f.part16, f.len, c->hw(), L.nw(), rho, f.psize, c->omega,
                    mdst_any, mgain_any, mdst_sa, mgain_sa, R, prof_work(c, KF_GAINS));
