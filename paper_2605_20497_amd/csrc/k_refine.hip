@@ -415,8 +415,8 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
 // kGainsWaveParts partitions.  Each wave owns R bins, so a node costs no block
 // barriers or block reductions; with a 4-wave block per node those dominate
 // when a node has a handful of h-edges.
-constexpr i32 kGainsWaveParts = 2048;
-constexpr i64 kGainsWaveDeg = 128;
+constexpr i32 kGainsWaveParts = 4096;  // 64 KiB of bins for the 4 waves of a block
+constexpr i64 kGainsWaveDeg = 256;
 
 __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
