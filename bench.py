@@ -42,10 +42,10 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "d67cc2b673d2efe632ec33285bccf0026b910079dcb412744d199253a4567321"): 6491125604,
-    ("k_gains16", "e351f14506effb464f53ae21d5d72abf44fc987c498b7c7ab440bbab0aaae5c8"): 5217062213,
-    ("k_dense_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 1778178872,
-    ("k_conn_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 556115894,
+    ("k_propose", "d67cc2b673d2efe632ec33285bccf0026b910079dcb412744d199253a4567321"): 6492284725,
+    ("k_gains16", "9add569fcb1bf581861266e7849e1af19a3f3d782b5d58384d9954aa51b6b435"): 5173471137,
+    ("k_dense_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 1777133399,
+    ("k_conn_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 556130590,
 }
 
 
