@@ -19,6 +19,8 @@ LIB = os.path.join(_HERE, "libhgp_oracle.so")
 
 def build(force: bool = False) -> str:
     """Compile the oracle with the host compiler (it is plain serial C++)."""
+    if os.environ.get("HGP_ORACLE_LIB"):
+        return os.environ["HGP_ORACLE_LIB"]
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, SRC])
@@ -32,9 +34,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        # HGP_ORACLE_LIB names another build of this source (the mutation
+        # tests load deliberately broken copies through it)
+        path = os.environ.get("HGP_ORACLE_LIB") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         P, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
         sig = {
             "hgpo_graph_new": (C.c_int, [i32, i32, P, P, P, P, P, C.POINTER(C.c_void_p), C.c_char_p, C.c_int]),
@@ -57,6 +62,7 @@ def lib():
             "hgpo_moves": (C.c_int, [P, P, i32, i32, i32, i64, P, P]),
             "hgpo_refine_rep": (C.c_int, [P, P, i32, i32, i32, i64, i64, P, P, P, P, P, P, P]),
             "hgpo_kway_initial": (C.c_int, [P, i32, i64, i64, P, C.c_char_p, C.c_int]),
+            "hgpo_sequence": (C.c_int, [i32, P, P, i64, P, P, P, P, i32, P, P, P]),
             "hgpo_partition": (C.c_int, [P, i64, i64, i32, i32, i32, u64, i32, C.POINTER(C.c_void_p), C.c_char_p, C.c_int]),
             "hgpo_result_free": (None, [P]),
             "hgpo_result_nlevels": (i32, [P]),
@@ -90,6 +96,26 @@ def mix64(x: int) -> int:
 
 def noise(seed: int, a: int, b: int, cap: int) -> int:
     return int(lib().hgpo_noise(seed, a, b, cap))
+
+
+def sequence(node_w, n_in, moves, rounds=16):
+    """Sequence of an explicit move list (Sec. VI-C): `moves` = rows of (node,
+    p_s, p_d, gain); node_w / n_in give each node's size and |in(n)|.  Returns
+    (node ids in sequence order, chain lengths, links, rounds run)."""
+    mv = np.asarray(moves, np.int64).reshape(-1, 4)
+    M = mv.shape[0]
+    nw = np.ascontiguousarray(node_w, np.int64)
+    nin = np.ascontiguousarray(n_in, np.int32)
+    cols = [np.ascontiguousarray(mv[:, i], np.int32) for i in range(3)]
+    gain = np.ascontiguousarray(mv[:, 3], np.int64)
+    seq = np.zeros(max(M, 1), np.int32)
+    cl = np.zeros(max(M, 1), np.int32)
+    info = np.zeros(3, np.int64)
+    rc = lib().hgpo_sequence(int(nw.shape[0]), _p(nw), _p(nin), M, _p(cols[0]), _p(cols[1]), _p(cols[2]),
+                             _p(gain), int(rounds), _p(seq), _p(cl), _p(info))
+    if rc != 0:
+        raise OracleError("bad move list")
+    return seq[:M].tolist(), cl[:int(info[2])].tolist(), int(info[0]), int(info[1])
 
 
 def relabel(he_off, he_nsrc, pins, mode):

@@ -21,11 +21,19 @@
 //   gain / moves              pinned: Conn difference of single moves
 //   refine_rep (sequence,     pinned: C_k equals the Conn drop after k moves,
 //   in-sequence gain, events) V_k equals the recomputed violation count
-//   chain rounds / ranking    parity unpinned (heuristic with no closed form;
-//                             only structural properties are checked)
+//   sort_moves,               pinned: hand-worked move lists whose sequence
+//   sequence_moves            follows from Readings R15-R17 alone (grade
+//                             terms and weights, the 256-move window, both
+//                             tie-breaks, acceptance, retries, cycle start,
+//                             ranking), plus the structural checks
+//   isolated pairing, noise   pinned: hand-worked cases of Readings R8, R3
+//   cap, k-way seating        and R21
 //   partition (driver)        pinned by validity, Conn >= brute-force optimum,
-//                             special cases; the exact decision sequence is
-//                             parity unpinned by the paper (no worked example)
+//                             special cases, and the early exit against the
+//                             run of all repetitions (Reading R25); the paper
+//                             prints no worked example of a whole run
+// tests/test_oracle_mutants.py builds single-slip copies of this file and
+// checks that the pins above catch each one.
 
 #include <algorithm>
 #include <chrono>
@@ -504,25 +512,29 @@ std::vector<Move> propose_moves(const Graph& g, const i32* rho, i32 nparts, int 
     return mv;
 }
 
-// One refinement repetition: moves, sequence of chains (Sec. VI-C), in-sequence
-// gains, validity of every prefix (Sec. VI-D) and the applied prefix.
-RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 omega, i64 delta,
-                  int chain_rounds = 16) {
-    RepOut out;
-    auto rows = phi_rows(g, rho);
-    std::vector<i64> psize(nparts, 0), D(nparts, 0);
-    for (i32 n = 0; n < g.N; ++n) psize[rho[n]] += g.nw[n];
-    for (i32 e = 0; e < g.E; ++e)
-        for (auto& t : rows[e]) if (t.cnt_in > 0) D[t.part] += 1;
-
-    std::vector<Move> mv = propose_moves(g, rho, nparts, rep, theta, omega, rows, psize);
-    // Sort by (p_s asc, gain desc) (Sec. VI-C), then node id (Reading R15).
+// Moves sorted by (p_s asc, gain desc) (Sec. VI-C), then node id asc
+// (Reading R15).
+void sort_moves(std::vector<Move>& mv) {
     std::sort(mv.begin(), mv.end(), [](const Move& a, const Move& b) {
         if (a.ps != b.ps) return a.ps < b.ps;
         if (a.gain != b.gain) return a.gain > b.gain;
         return a.n < b.n;
     });
-    i64 M = (i64)mv.size();
+}
+
+// Order of the moves after chaining (Sec. VI-C): `order` lists indices into
+// the sorted moves chain by chain, chain_len the length of each chain.
+struct Sequence {
+    std::vector<i64> order;
+    std::vector<i32> chain_len;
+    i32 links = 0, rounds = 0;
+};
+
+// Chain rounds and ranking over the sorted moves `mv` (Sec. VI-C, Readings
+// R16 and R17); nw and nin are the node sizes and |in(n)| the grade uses.
+Sequence sequence_moves(const std::vector<Move>& mv, const i64* nw, const i32* nin, int chain_rounds) {
+    const i64 M = (i64)mv.size();
+    Sequence out;
     std::map<i32, std::pair<i64, i64>> seg;  // part -> [begin, end) in sorted order
     for (i64 i = 0; i < M; ++i) {
         auto it = seg.find(mv[i].ps);
@@ -550,7 +562,7 @@ RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 
                 seen++;
                 i32 a = mv[i].n, b = mv[j].n;
                 i64 G = mv[j].gain * 10000000LL -
-                        (10 * std::llabs(g.nw[a] - g.nw[b]) + std::llabs((i64)g.inc_nin[a] - g.inc_nin[b]));
+                        (10 * std::llabs(nw[a] - nw[b]) + std::llabs((i64)nin[a] - nin[b]));
                 if (bj < 0 || G > bG || (G == bG && b > mv[bj].n)) { bj = j; bG = G; }
             }
             prop[i] = bj;
@@ -599,11 +611,33 @@ RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 
     std::sort(chains.begin(), chains.end(), [](const Chain& a, const Chain& b) {
         return a.gain != b.gain ? a.gain > b.gain : a.first < b.first;
     });
-    std::vector<i64> order;
+    std::vector<i64>& order = out.order;
     for (auto& c : chains) {
         out.chain_len.push_back((i32)c.items.size());
         for (i64 x : c.items) order.push_back(x);
     }
+    return out;
+}
+
+// One refinement repetition: moves, sequence of chains (Sec. VI-C), in-sequence
+// gains, validity of every prefix (Sec. VI-D) and the applied prefix.
+RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 omega, i64 delta,
+                  int chain_rounds = 16) {
+    RepOut out;
+    auto rows = phi_rows(g, rho);
+    std::vector<i64> psize(nparts, 0), D(nparts, 0);
+    for (i32 n = 0; n < g.N; ++n) psize[rho[n]] += g.nw[n];
+    for (i32 e = 0; e < g.E; ++e)
+        for (auto& t : rows[e]) if (t.cnt_in > 0) D[t.part] += 1;
+
+    std::vector<Move> mv = propose_moves(g, rho, nparts, rep, theta, omega, rows, psize);
+    sort_moves(mv);
+    const i64 M = (i64)mv.size();
+    Sequence sq = sequence_moves(mv, g.nw.data(), g.inc_nin.data(), chain_rounds);
+    const std::vector<i64>& order = sq.order;
+    out.chain_len = sq.chain_len;
+    out.links = sq.links;
+    out.rounds = sq.rounds;
     // Simulation of the sequence: the exact connectivity change of each move
     // after all earlier ones (Reading R18), and the violated-partition count
     // after every prefix (Sec. VI-D, Reading R19).
@@ -991,6 +1025,26 @@ int hgpo_refine_rep(void* gp, i32* rho, i32 nparts, i32 rep, i32 theta, i64 omeg
     if (chain_len) std::copy(o.chain_len.begin(), o.chain_len.end(), chain_len);
     info[0] = M; info[1] = o.kstar; info[2] = o.applied_gain; info[3] = o.links; info[4] = o.rounds;
     info[5] = (i64)o.chain_len.size();
+    return 0;
+}
+
+// Sequence of an explicit move list (Sec. VI-C): moves (node, p_s, p_d, gain)
+// are sorted (Reading R15) and chained in `rounds` chain rounds (Readings R16,
+// R17).  nw / nin give every node's size and |in(n)| (N entries).  seq
+// receives the M node ids in sequence order, chain_len the chain lengths
+// (at most M entries); info: links, rounds run, number of chains.
+int hgpo_sequence(i32 N, const i64* nw, const i32* nin, i64 M, const i32* node, const i32* ps, const i32* pd,
+                  const i64* gain, i32 rounds, i32* seq, i32* chain_len, i64* info) {
+    std::vector<Move> mv;
+    for (i64 i = 0; i < M; ++i) {
+        if (node[i] < 0 || node[i] >= N) return -1;
+        mv.push_back({node[i], ps[i], pd[i], gain[i]});
+    }
+    sort_moves(mv);
+    Sequence sq = sequence_moves(mv, nw, nin, rounds);
+    for (i64 i = 0; i < M; ++i) seq[i] = mv[sq.order[i]].n;
+    std::copy(sq.chain_len.begin(), sq.chain_len.end(), chain_len);
+    info[0] = sq.links; info[1] = sq.rounds; info[2] = (i64)sq.chain_len.size();
     return 0;
 }
 
