@@ -1,0 +1,110 @@
+// Stand-in for the partitioner's context calls, for running the batch
+// scheduler (hgp_batch.cpp) on the CPU under ThreadSanitizer and
+// AddressSanitizer.  Each context copies its inputs like the library does,
+// spends time in proportion to the job's pins, and returns a result that is a
+// fixed function of the input (rho[n] = (n * 7 + P) % 13, conn = P), so the
+// driver can check every job's outputs.  Contexts share no state except a
+// counter of live contexts.
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "../../include/hgp.h"
+
+std::atomic<int> g_live_contexts{0};
+
+struct hgp_ctx {
+    hgp_options opt;
+    std::vector<int64_t> he_off;
+    std::vector<int32_t> he_nsrc, pins, hw, nw;
+    int32_t N = 0, E = 0;
+    int64_t omega = 0, delta = 0;
+    int32_t k = 0;
+    bool loaded = false, limited = false, coarsened = false, refined = false;
+    std::vector<int32_t> rho;
+};
+
+extern "C" {
+
+void hgp_default_options(hgp_options* opt) {
+    std::memset(opt, 0, sizeof(*opt));
+    opt->pi = 4;
+    opt->theta = 16;
+}
+
+hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt) {
+    hgp_ctx* c = new hgp_ctx();
+    c->opt = *opt;
+    *out = c;
+    g_live_contexts++;
+    return HGP_OK;
+}
+
+void hgp_destroy(hgp_ctx* c) {
+    if (!c) return;
+    g_live_contexts--;
+    delete c;
+}
+
+hgp_status hgp_load_csr(hgp_ctx* c, int32_t n, int32_t e, const int64_t* he_off, const int32_t* he_nsrc,
+                        const int32_t* pins, const int32_t* hedge_w, const int32_t* node_w, hgp_mem where) {
+    if (!c || where != HGP_MEM_HOST || n < 1 || e < 0) return HGP_E_INVALID;
+    c->N = n;
+    c->E = e;
+    c->he_off.assign(he_off, he_off + e + 1);
+    c->he_nsrc.assign(he_nsrc, he_nsrc + e);
+    c->pins.assign(pins, pins + he_off[e]);
+    c->hw = hedge_w ? std::vector<int32_t>(hedge_w, hedge_w + e) : std::vector<int32_t>(e, 1);
+    c->nw = node_w ? std::vector<int32_t>(node_w, node_w + n) : std::vector<int32_t>(n, 1);
+    c->loaded = true;
+    c->limited = c->coarsened = c->refined = false;
+    return HGP_OK;
+}
+
+hgp_status hgp_set_limits(hgp_ctx* c, int64_t omega, int64_t delta, int32_t k) {
+    if (!c->loaded) return HGP_E_STATE;
+    if (omega < 1 || delta < 0 || k < 0) return HGP_E_INVALID;
+    c->omega = omega;
+    c->delta = delta;
+    c->k = k;
+    c->limited = true;
+    return HGP_OK;
+}
+
+hgp_status hgp_coarsen(hgp_ctx* c, int32_t* nl) {
+    if (!c->limited) return HGP_E_STATE;
+    std::this_thread::sleep_for(std::chrono::microseconds(c->pins.size() / 64));
+    *nl = 3;
+    c->coarsened = true;
+    return HGP_OK;
+}
+
+hgp_status hgp_refine(hgp_ctx* c) {
+    if (!c->coarsened) return HGP_E_STATE;
+    std::this_thread::sleep_for(std::chrono::microseconds(c->pins.size() / 128));
+    const int64_t P = (int64_t)c->pins.size();
+    c->rho.resize(c->N);
+    for (int32_t n = 0; n < c->N; ++n) c->rho[n] = (int32_t)(((int64_t)n * 7 + P) % 13);
+    c->refined = true;
+    return HGP_OK;
+}
+
+hgp_status hgp_get_partition(hgp_ctx* c, int32_t* rho, int64_t cap, int32_t* np) {
+    if (!c->refined) return HGP_E_STATE;
+    if (cap < c->N) return HGP_E_INVALID;
+    std::memcpy(rho, c->rho.data(), sizeof(int32_t) * c->N);
+    if (np) *np = 13;
+    return HGP_OK;
+}
+
+hgp_status hgp_evaluate(hgp_ctx* c, const int32_t* rho, int32_t, hgp_eval* out) {
+    if (!c->refined || rho) return HGP_E_STATE;
+    std::memset(out, 0, sizeof(*out));
+    out->conn = (int64_t)c->pins.size();
+    out->n_parts = 13;
+    return HGP_OK;
+}
+
+}  // extern "C"

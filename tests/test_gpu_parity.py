@@ -385,3 +385,12 @@ def test_dense_work_counters():
                  ((((int(levels[lv, 1]) + 31) // 32 + 3) // 4 * 4) * 32) for lv in range(nl)]
     assert work["gains_gemm"] % 1 == 0 and work["gains_gemm"] >= sum(per_level)
     g.close()
+
+
+@pytest.mark.parametrize("theta", [2, 4])
+def test_early_exit_with_second_half_commit(theta):
+    # A graph whose level-0 first-half repetitions apply nothing while a
+    # second-half (size-aware) one applies a move (Reading R25): the library's
+    # early exit must still run the second half.
+    hg = W.random_small(14, 16, 4, 1, max_src=1, max_hw=3, max_nw=3)
+    _compare_runs(hg, 7, 10 ** 6, theta=theta, label="r25-theta%d" % theta)
