@@ -194,6 +194,25 @@ typedef struct hgp_eval {
  * partition) on the input hypergraph with the current limits. */
 hgp_status hgp_evaluate(hgp_ctx* ctx, const int32_t* rho, int32_t n_parts, hgp_eval* out);
 
+/*
+ * hgp_evaluate for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * rho: N int32 in [0, n_parts) in DEVICE memory, read on the context's stream
+ * (the caller orders its writes before the call); out: host struct.  Same
+ * results as hgp_evaluate.  Calls no allocator: the pins(p,e) rows,
+ * partition sizes, D(p) and the results live in one static device workspace
+ * of 64 MiB per device (set up by hgp_create).  It holds 64 B of results,
+ * sizes and D (8 * n_parts B each), lambda (4 * E B) and three row arrays
+ * (4 * P B each), each rounded up to 256 B; an input needing more gives
+ * HGP_E_UNSUPPORTED with the bytes needed (about 5.5 M pins fit).
+ * Entries of rho out of range give HGP_E_INVALID.  Waits for the context's
+ * stream twice (range check, results).  Every context on one device shares
+ * that workspace and it keeps the last call's contents: calls that overlap on
+ * one device (contexts on different streams or host threads) race and must
+ * be serialised by the caller.
+ */
+hgp_status hgp_evaluate_noalloc(hgp_ctx* ctx, const int32_t* rho, int32_t n_parts, hgp_eval* out);
+
 /* One refinement repetition on level 0 for a caller-supplied rho (host, N
  * entries, updated in place) with n_parts partitions; `rep` and theta select
  * the size-aware half (Sec. VI-B).  info[0..3] = moves proposed M, moves

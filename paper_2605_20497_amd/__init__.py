@@ -88,6 +88,7 @@ def lib():
             "hgp_get_partition": (C.c_int, [P, P, i64, C.POINTER(i32)]),
             "hgp_get_phi": (C.c_int, [P, P, P, P, P, i64, C.POINTER(i64)]),
             "hgp_evaluate": (C.c_int, [P, P, i32, C.POINTER(hgp_eval)]),
+            "hgp_evaluate_noalloc": (C.c_int, [P, P, i32, C.POINTER(hgp_eval)]),
             "hgp_refine_rep": (C.c_int, [P, P, i32, i32, P, P, P, P, P, P, P, P]),
             "hgp_kernel_stats": (C.c_int, [P, C.POINTER(C.c_char_p), P, P, C.POINTER(i32)]),
             "hgp_reset_kernel_stats": (C.c_int, [P]),
@@ -112,6 +113,7 @@ KERNEL_FAMILIES = ["validate", "transpose", "radix_sort", "scan", "level_stats",
 EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
             "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
             "hgp_get_proposal", "hgp_get_level_graph", "hgp_get_partition", "hgp_get_phi", "hgp_evaluate",
+            "hgp_evaluate_noalloc",
             "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_kernel_work", "hgp_level_times",
             "hgp_run_jobs"]
 
@@ -315,6 +317,17 @@ class Partitioner:
         ev = hgp_eval()
         r = None if rho is None else np.ascontiguousarray(rho, np.int32)
         self._chk(lib().hgp_evaluate(self.h, _p(r), int(n_parts), C.byref(ev)))
+        return dict(conn=ev.conn, cutnet=ev.cutnet, max_size=ev.max_size, max_inbound=ev.max_inbound,
+                    violations=ev.violations, n_parts=ev.n_parts)
+
+    def hgp_evaluate_noalloc(self, rho, n_parts):
+        """rho: int32 torch tensor on this context's device (N entries)."""
+        import torch
+        if rho.dtype != torch.int32 or not rho.is_cuda or not rho.is_contiguous():
+            raise ValueError("rho must be a contiguous int32 device tensor")
+        self._stream.wait_stream(torch.cuda.current_stream())
+        ev = hgp_eval()
+        self._chk(lib().hgp_evaluate_noalloc(self.h, C.c_void_p(rho.data_ptr()), int(n_parts), C.byref(ev)))
         return dict(conn=ev.conn, cutnet=ev.cutnet, max_size=ev.max_size, max_inbound=ev.max_inbound,
                     violations=ev.violations, n_parts=ev.n_parts)
 

@@ -300,6 +300,8 @@ hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt) {
         hipDeviceProp_t prop;
         HIPC(hipGetDeviceProperties(&prop, c->device));
         c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        // device address of the static workspace (hgp_evaluate_noalloc), with the device current
+        c->noalloc_scratch = noalloc_scratch_init(c->device);
         if (c->opt.stream) {
             c->stream = (hipStream_t)c->opt.stream;
         } else {
@@ -629,6 +631,15 @@ hgp_status hgp_evaluate(hgp_ctx* h, const int32_t* rho, int32_t n_parts, hgp_eva
         HIPC(hipMemcpyAsync(d, rho, sizeof(i32) * (size_t)L.N, hipMemcpyHostToDevice, c->stream));
         evaluate_dev(c, L, d, n_parts, out);
     }
+    API_END
+}
+
+hgp_status hgp_evaluate_noalloc(hgp_ctx* h, const int32_t* rho, int32_t n_parts, hgp_eval* out) {
+    API_BEGIN(h)
+    require(c->loaded && c->limits_set, HGP_E_STATE, "load and set limits first");
+    require(rho != nullptr && out != nullptr && n_parts >= 1, HGP_E_INVALID, "rho, out and n_parts >= 1 required");
+    HIPC(hipSetDevice(c->device));
+    evaluate_noalloc(c, c->levels[0], (const i32*)rho, n_parts, out);
     API_END
 }
 

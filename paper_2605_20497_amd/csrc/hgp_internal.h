@@ -126,6 +126,9 @@ struct Ctx {
 
     // Pinned host staging for scalars read back by the driver.
     i64* host_scalars = nullptr;
+    // Device address of the library's static workspace on this context's
+    // device (hgp_evaluate_noalloc), looked up once per device at creation.
+    void* noalloc_scratch = nullptr;
 
     // Profiling.
     Prof prof;
@@ -240,5 +243,17 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
                    bool reuse = false);
 void project_rho(Ctx* c, const i32* rho_coarse, const i32* gamma, i32* rho_fine, i32 N);
 void evaluate_dev(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out);
+
+// Static device workspace of the evaluation that allocates nothing: Phi rows,
+// partition sizes and D(p), the range check of rho and the results.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+// Device address of that workspace on the current device; the symbol lookup
+// runs once per device (later calls return the kept address).
+void* noalloc_scratch_init(int device);
+// Bytes of that workspace an evaluation of L with nparts partitions needs.
+size_t noalloc_eval_bytes(const Level& L, i32 nparts);
+// hgp_evaluate on a device-resident rho, with every buffer in the static
+// workspace: no allocation, two host synchronisations (range check, results).
+void evaluate_noalloc(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out);
 
 }  // namespace hgp

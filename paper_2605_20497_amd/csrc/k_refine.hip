@@ -2,8 +2,16 @@
 // gains, the moves sequence of ranked chains, in-sequence gains, event-based
 // validity of every prefix, and the application of the best valid prefix.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "dev_util.h"
+
+// Workspace of hgp_evaluate_noalloc, for callers that cannot allocate device
+// memory.  Every device the library runs on holds its own copy until the
+// process ends.  Host code never passes this name to a kernel or a copy: it
+// uses the device address looked up by noalloc_scratch_init.
+static __device__ __align__(256) unsigned char scratch[hgp::kNoAllocScratchBytes];
 
 namespace hgp {
 
@@ -1763,6 +1771,116 @@ void evaluate_dev(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* 
            c->delta, rs);
     i64 v[6];
     read_back(c, rs, v, 6, 8);
+    out->conn = v[0];
+    out->cutnet = v[1];
+    out->max_size = v[2];
+    out->max_inbound = v[3];
+    out->violations = v[4];
+    out->n_parts = v[5];
+}
+
+// Entries of rho outside [0, nparts).
+__global__ void k_rho_check(i32 N, const i32* __restrict__ rho, i32 nparts, unsigned long long* bad) {
+    unsigned long long c = 0;
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
+        c += (u32)rho[n] >= (u32)nparts ? 1 : 0;
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(bad, c);
+}
+
+void* noalloc_scratch_init(int device) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;  // device ordinal -> address of `scratch` there
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = addr.find(device);
+    if (it != addr.end()) return it->second;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        fail(HGP_E_DEVICE, std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e));
+    }
+    addr[device] = p;
+    return p;
+}
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace layout: results (8 words: conn, cut-net, max size, max D,
+// violations, non-empty parts, invalid rho entries), psize [nparts], D
+// [nparts], lambda [E], then the rows part / cnt / cnt_in [P] each.
+struct NoAllocLayout {
+    size_t res, psize, pD, len, part, cnt, cin, total;
+    NoAllocLayout(const Level& L, i32 nparts) {
+        size_t o = 0;
+        res = o;
+        o += align256(8 * sizeof(u64));
+        psize = o;
+        o += align256(sizeof(i64) * (size_t)nparts);
+        pD = o;
+        o += align256(sizeof(i64) * (size_t)nparts);
+        len = o;
+        o += align256(sizeof(i32) * (size_t)std::max<i32>(L.E, 1));
+        part = o;
+        o += align256(sizeof(i32) * (size_t)std::max<i64>(L.P, 1));
+        cnt = o;
+        o += align256(sizeof(i32) * (size_t)std::max<i64>(L.P, 1));
+        cin = o;
+        o += align256(sizeof(i32) * (size_t)std::max<i64>(L.P, 1));
+        total = o;
+    }
+};
+
+// Records no profiling events while alive (event creation allocates).
+struct ProfPause {
+    Ctx* c;
+    int saved;
+    explicit ProfPause(Ctx* cc) : c(cc), saved(cc->opt.profile) { c->opt.profile = 0; }
+    ~ProfPause() { c->opt.profile = saved; }
+};
+
+}  // namespace
+
+size_t noalloc_eval_bytes(const Level& L, i32 nparts) { return NoAllocLayout(L, nparts).total; }
+
+void evaluate_noalloc(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out) {
+    const NoAllocLayout lay(L, nparts);
+    if (lay.total > kNoAllocScratchBytes)
+        fail(HGP_E_UNSUPPORTED, "hgp_evaluate_noalloc needs " + std::to_string(lay.total) +
+                                    " bytes of workspace (12 per pin, 4 per h-edge, 16 per partition); the static "
+                                    "workspace holds " +
+                                    std::to_string(kNoAllocScratchBytes));
+    if (c->noalloc_scratch == nullptr) fail(HGP_E_STATE, "static workspace not set up on this device");
+    unsigned char* base = (unsigned char*)c->noalloc_scratch;
+    unsigned long long* res = (unsigned long long*)(base + lay.res);
+    i64* psize = (i64*)(base + lay.psize);
+    i64* pD = (i64*)(base + lay.pD);
+    i32* len = (i32*)(base + lay.len);
+    i32* part = (i32*)(base + lay.part);
+    i32* cnt = (i32*)(base + lay.cnt);
+    i32* cin = (i32*)(base + lay.cin);
+    ProfPause pause(c);
+    // The workspace keeps the previous call's contents: clear what the
+    // atomics accumulate into (the rows are rewritten whole).
+    fill_many(c, {{res, 16, 0u}, {psize, 2 * (i64)nparts, 0u}, {pD, 2 * (i64)nparts, 0u}});
+    LAUNCH(c, KF_EVAL, k_rho_check, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, nparts, res + 6);
+    i64 bad = 0;
+    read_back(c, res + 6, &bad, 1, 8);
+    if (bad != 0) fail(HGP_E_INVALID, std::to_string(bad) + " entries of rho outside [0, n_parts)");
+    build_phi(c, L, rho, part, cnt, cin, len, nullptr);
+    LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), psize);
+    if (L.E > 0) {
+        const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
+        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 4, c->num_cu * 2), 256, sizeof(u32) * nbins, L.E,
+               L.he_off(), (const i32*)part, (const i32*)cin, (const i32*)len, pD, nbins);
+        LAUNCH(c, KF_EVAL, k_conn, grid_for(L.E, 256, c->num_cu * 4), 256, 0, L.E, (const i32*)len, c->hw(), res);
+    }
+    LAUNCH(c, KF_EVAL, k_part_eval, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, (const i64*)psize,
+           (const i64*)pD, c->omega, c->delta, res);
+    i64 v[6];
+    read_back(c, res, v, 6, 8);
     out->conn = v[0];
     out->cutnet = v[1];
     out->max_size = v[2];
