@@ -185,10 +185,18 @@ def config3a(seed: int = 0) -> Hypergraph:
 # ---------------------------------------------------------------------------
 
 def conv_snn(layers: int, hw: int, channels: int, mean_fanout: float, seed: int = 0,
-             omega: int = 0, delta: int = 0, name: str = "", progress=None) -> Hypergraph:
+             omega: int = 0, delta: int = 0, name: str = "", progress=None, threads: int = 0) -> Hypergraph:
     """Node (l, y, x, c) drives clamp(Poisson(mean), 1, |W|) distinct destinations in
     layer (l+1) mod layers at |y'-y|<=1, |x'-x|<=1, any channel (|W| <= 9*channels).
-    `progress(done, total)` is called after each block of rows when given."""
+    `progress(done, total)` is called after each block of rows when given.
+
+    The random draws are taken in one fixed order on the calling thread (the
+    fan-outs, then one block of uniform keys per block of rows); turning a
+    block's keys into destination ids runs on `threads` worker threads (0 =
+    up to 16 by the host's CPUs), which changes nothing in the output."""
+    import concurrent.futures as cf
+    import os
+
     rng = np.random.default_rng(seed)
     per_layer = hw * hw * channels
     n = layers * per_layer
@@ -208,12 +216,11 @@ def conv_snn(layers: int, hw: int, channels: int, mean_fanout: float, seed: int 
     np.cumsum(k + 1, out=he_off[1:])
     pins = np.empty(int(he_off[-1]), dtype=np.int32)
     chunk = 1 << 15
-    for c0 in range(0, n, chunk):
-        c1 = min(n, c0 + chunk)
+
+    def rows_to_pins(c0, c1, keys):
         rows = c1 - c0
         ws = wsize[c0:c1]
-        wmax = int(ws.max())
-        keys = rng.random((rows, wmax))
+        wmax = keys.shape[1]
         keys[np.arange(wmax)[None, :] >= ws[:, None]] = 2.0
         kk = k[c0:c1]
         kmax = int(kk.max())
@@ -232,8 +239,21 @@ def conv_snn(layers: int, hw: int, channels: int, mean_fanout: float, seed: int 
         row_pins[:, 1:] = ids
         m = np.concatenate([np.ones((rows, 1), bool), valid], axis=1)
         pins[he_off[c0]:he_off[c1]] = row_pins[m].astype(np.int32)
-        if progress is not None and (c1 == n or (c1 // chunk) % 32 == 0):
-            progress(c1, n)
+
+    if threads <= 0:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    pending = []
+    with cf.ThreadPoolExecutor(threads) as ex:
+        for c0 in range(0, n, chunk):
+            c1 = min(n, c0 + chunk)
+            keys = rng.random((c1 - c0, int(wsize[c0:c1].max())))
+            pending.append(ex.submit(rows_to_pins, c0, c1, keys))
+            if len(pending) >= 2 * threads:  # bounds the keys held at once
+                pending.pop(0).result()
+            if progress is not None and (c1 == n or (c1 // chunk) % 32 == 0):
+                progress(c1, n)
+        for f in pending:
+            f.result()
     return Hypergraph(n, he_off, np.ones(n, np.int32), pins, np.ones(n, np.int32),
                       np.ones(n, np.int32), omega=omega, delta=delta, name=name)
 
