@@ -54,6 +54,7 @@ def lib():
             "hgpo_pair": (None, [P, i32, i32, P, P]),
             "hgpo_propose": (C.c_int, [P, i64, i64, u64, i32, P, i32, P, P]),
             "hgpo_match_round": (C.c_int, [i32, P, P, P, P, C.c_char_p, C.c_int]),
+            "hgpo_match_round_greedy": (C.c_int, [i32, P, P, P, P, C.c_char_p, C.c_int]),
             "hgpo_match": (C.c_int, [P, i64, i64, i32, P, P, P, P, C.c_char_p, C.c_int]),
             "hgpo_contract": (C.c_int, [P, P, P, C.POINTER(C.c_void_p)]),
             "hgpo_evaluate": (C.c_int, [P, P, i32, i64, i64, P, P, P]),
@@ -310,12 +311,15 @@ class Graph:
             raise OracleError(err.value.decode())
         return rho
 
-    def partition(self, omega, delta, k=0, Pi=4, theta=16, seed=0, early_exit=True, chains=True) -> "Result":
+    def partition(self, omega, delta, k=0, Pi=4, theta=16, seed=0, early_exit=True, chains=True,
+                  greedy=False) -> "Result":
         # chains=False: the ablation without chain rounds (moves sequenced by gain alone)
+        # greedy=True: the ablation with the prototype's greedy matching (Reading R28)
         h = C.c_void_p()
         err = C.create_string_buffer(256)
         rc = lib().hgpo_partition(self.h, int(omega), int(delta), int(k), Pi, theta, C.c_uint64(seed),
-                                  int(bool(early_exit)) | (0 if chains else 2), C.byref(h), err, 256)
+                                  int(bool(early_exit)) | (0 if chains else 2) | (4 if greedy else 0),
+                                  C.byref(h), err, 256)
         if rc != 0:
             raise OracleError(err.value.decode())
         return Result(h.value, Pi)

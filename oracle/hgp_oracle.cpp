@@ -16,6 +16,8 @@
 //                             brute force over all partitions of tiny graphs
 //   pair / propose            pinned: matrix-product histogram, symmetry, sort
 //   match_round               pinned: brute-force maximum-weight matching
+//   match_round_greedy        pinned: hand-worked proposal forests (Reading
+//                             R28; an ablation, not the method)
 //   contract                  pinned: score/connectivity duality, level
 //                             invariance of Conn and D, size conservation
 //   gain / moves              pinned: Conn difference of single moves
@@ -357,10 +359,51 @@ std::string match_round(i32 N, const char* active, const i32* target, const u64*
     return "";
 }
 
+// The prototype's greedy matching, the ablation of Sec. VII-D (Reading R28):
+// every two-cycle of the proposal graph is matched, and the decision is
+// carried down the trees from the roots: a node left unmatched by its parent
+// (or a root without a partner) takes the child that proposes to it with the
+// highest score, ties to the larger id.
+std::string match_round_greedy(i32 N, const char* active, const i32* target, const u64* sc, i32* match) {
+    std::vector<std::vector<i32>> child(N);
+    std::vector<char> paired(N, 0);
+    for (i32 n = 0; n < N; ++n) {
+        match[n] = -1;
+        if (!active[n] || target[n] < 0) continue;
+        i32 t = target[n];
+        if (!active[t]) return "target of an active node is inactive";
+        if (target[t] == n) paired[n] = 1;
+        else child[t].push_back(n);
+    }
+    std::vector<i32> order;
+    for (i32 r = 0; r < N; ++r) {
+        if (!active[r] || !(target[r] < 0 || paired[r])) continue;
+        if (paired[r]) match[r] = target[r];
+        order.push_back(r);
+    }
+    for (size_t i = 0; i < order.size(); ++i) {
+        i32 n = order[i];
+        if (match[n] < 0) {
+            i32 bc = -1;
+            for (i32 c : child[n])
+                if (bc < 0 || sc[c] > sc[bc] || (sc[c] == sc[bc] && c > bc)) bc = c;
+            if (bc >= 0) {
+                match[n] = bc;
+                match[bc] = n;
+            }
+        }
+        for (i32 c : child[n]) order.push_back(c);
+    }
+    if ((i64)order.size() != std::count(active, active + N, (char)1))
+        return "cycle longer than two in the proposal graph";
+    return "";
+}
+
 // Pi matching rounds, matched nodes leaving all later rounds (Sec. V-D), then
 // best-effort pairing of nodes with no valid neighbour (Sec. V-C, Reading R8).
+// greedy: the prototype's matching of each round instead of the exact one.
 std::string match_all(const Graph& g, i64 omega, i64 delta, int Pi, const i32* cand, const u64* score,
-                      i32* match, i32* round_pairs) {
+                      i32* match, i32* round_pairs, bool greedy = false) {
     i32 N = g.N;
     std::vector<char> U(N, 1);
     std::vector<i32> t(N), mr(N);
@@ -372,7 +415,8 @@ std::string match_all(const Graph& g, i64 omega, i64 delta, int Pi, const i32* c
             t[n] = (U[n] && c >= 0 && U[c]) ? c : -1;
             s[n] = score[(i64)n * Pi + r];
         }
-        std::string err = match_round(N, U.data(), t.data(), s.data(), mr.data());
+        std::string err = greedy ? match_round_greedy(N, U.data(), t.data(), s.data(), mr.data())
+                                 : match_round(N, U.data(), t.data(), s.data(), mr.data());
         if (!err.empty()) return err + " (round " + std::to_string(r) + ")";
         i32 pairs = 0;
         for (i32 n = 0; n < N; ++n)
@@ -696,7 +740,8 @@ RepOut refine_rep(const Graph& g, i32* rho, i32 nparts, int rep, int theta, i64 
 // Multilevel driver (Sec. III) and the k-way adapter (Sec. VII-A).
 // ---------------------------------------------------------------------------
 // early_exit: bit 0 = Reading R25's early exit of repetitions; bit 1 = the
-// ablation without chain rounds.
+// ablation without chain rounds; bit 2 = the ablation with the prototype's
+// greedy matching (Reading R28).
 struct Params { i64 omega, delta; i32 k, Pi, Theta; u64 seed; int early_exit; };
 
 struct LevelLog {
@@ -783,7 +828,8 @@ void run_partition(Result& R, const Graph& g0, const Params& prm) {
         for (i32 n = 0; n < g.N; ++n)
             propose_node(g, n, prm.omega, prm.delta, prm.seed, cap, Pi, s, &cand[(size_t)n * Pi], &score[(size_t)n * Pi]);
         std::vector<i32> match(g.N);
-        std::string err = match_all(g, prm.omega, prm.delta, Pi, cand.data(), score.data(), match.data(), L.pairs);
+        std::string err = match_all(g, prm.omega, prm.delta, Pi, cand.data(), score.data(), match.data(), L.pairs,
+                                    (prm.early_exit & 4) != 0);
         if (!err.empty()) { R.err = err; return; }
         i64 merges = 0;
         for (i32 n = 0; n < g.N; ++n) merges += match[n] > n ? 1 : 0;
@@ -935,6 +981,13 @@ int hgpo_propose(void* gp, i64 omega, i64 delta, u64 seed, i32 Pi, const i32* no
 int hgpo_match_round(i32 N, const char* active, const i32* target, const u64* score, i32* match, char* err,
                      int errlen) {
     std::string e = match_round(N, active, target, score, match);
+    if (!e.empty()) { set_err(err, errlen, e); return -1; }
+    return 0;
+}
+
+int hgpo_match_round_greedy(i32 N, const char* active, const i32* target, const u64* score, i32* match, char* err,
+                            int errlen) {
+    std::string e = match_round_greedy(N, active, target, score, match);
     if (!e.empty()) { set_err(err, errlen, e); return -1; }
     return 0;
 }

@@ -17,7 +17,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hgp_oracle.cpp")
 PIN_TESTS = ["tests/test_oracle_readings.py", "tests/test_oracle_refine.py", "tests/test_oracle_coarsen.py",
-             "tests/test_oracle_driver.py", "tests/test_oracle_eval.py"]
+             "tests/test_oracle_driver.py", "tests/test_oracle_eval.py", "tests/test_oracle_greedy.py"]
 
 # name -> (exact text in the oracle, replacement); each text occurs once.
 MUTANTS = {
@@ -47,6 +47,10 @@ MUTANTS = {
     # k-way seating (Reading R21)
     "kway_heaviest_first": ("return pw[a] != pw[b] ? pw[a] < pw[b] : a < b;",
                             "return pw[a] != pw[b] ? pw[a] > pw[b] : a < b;"),
+    # greedy matching of the ablation (Reading R28)
+    "greedy_skips_root_pairs": ("        if (paired[r]) match[r] = target[r];\n", ""),
+    "greedy_tie_smaller_id": ("(sc[c] == sc[bc] && c > bc)", "(sc[c] == sc[bc] && c < bc)"),
+    "greedy_lowest_score": ("if (bc < 0 || sc[c] > sc[bc] ||", "if (bc < 0 || sc[c] < sc[bc] ||"),
     # early exit (Reading R25)
     "early_exit_leaves_level": ("                if (rep < prm.Theta / 2) rep = prm.Theta / 2 - 1;\n                else break;",
                                 "                break;"),
