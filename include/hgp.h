@@ -72,7 +72,12 @@ typedef struct hgp_options {
                               (MFMA) product wherever it fits; bit 4: never; by default per
                               level by an estimate.  Results are identical in every case.
                               bit 5: ablation without chain rounds (Sec. VII): every move is a
-                              chain of its own, sequenced by gain alone (changes results). */
+                              chain of its own, sequenced by gain alone (changes results).
+                              bit 6: ablation with the prototype's greedy matching (Sec. VII-D)
+                              instead of the exact one: every two-cycle of a round's proposal
+                              graph is matched, and from the roots down each node left
+                              unmatched takes the child proposing to it with the highest
+                              score, ties to the larger id (changes results). */
     uint32_t profile_families; /* with profile = 1: bit i times only kernel family i (the order of
                                 * hgp_kernel_stats' names); 0 = every family */
     int32_t delta_mode;    /* which h-edges Delta counts for a partition (constraint variants of
@@ -134,6 +139,17 @@ hgp_status hgp_load_csr(hgp_ctx* ctx, int32_t n_nodes, int32_t n_hedges, const i
 hgp_status hgp_set_limits(hgp_ctx* ctx, int64_t omega, int64_t delta, int32_t k);
 
 /*
+ * The k-way adapter of Sec. VII-A with the balance parameter eps =
+ * eps_num / eps_den: Omega = floor((eps_den + eps_num) * ceil(W / k) /
+ * eps_den), W the total node weight, then hgp_set_limits(ctx, Omega, delta,
+ * k).  The paper leaves Delta uncapped in this mode; pass INT64_MAX for that,
+ * or a cap to keep both constraints.  *omega_out (may be NULL) receives Omega.
+ * Errors as hgp_set_limits; k >= 1, eps_num >= 0, eps_den >= 1.
+ */
+hgp_status hgp_set_kway_limits(hgp_ctx* ctx, int32_t k, int32_t eps_num, int32_t eps_den, int64_t delta,
+                               int64_t* omega_out);
+
+/*
  * Coarsening (Sec. III, Sec. V): repeats levels (candidate proposal, Pi
  * matching rounds, isolated pairing, contraction) until the node count reaches
  * ceil(W/Omega), a level merges nothing, or (k > 0) fewer than 4,096 nodes
@@ -154,8 +170,10 @@ hgp_status hgp_refine(hgp_ctx* ctx);
  * level l, for l < n_levels (cap >= 4*n_levels). */
 hgp_status hgp_get_levels(hgp_ctx* ctx, int64_t* out, int64_t cap);
 
-/* Cluster map gamma of level `level` (maps level-`level` node ids to
- * level-(level+1) ids), N_level entries.  0 <= level < n_levels - 1. */
+/* Cluster map gamma of level `level` (Sec. III: each node of G_level to
+ * the node of G_(level+1) that its cluster becomes; Sec. V-E), N_level
+ * entries.  Coarse ids number the clusters by their smallest member.
+ * 0 <= level < n_levels - 1; cap >= N_level. */
 hgp_status hgp_get_cluster_map(hgp_ctx* ctx, int32_t level, int32_t* out, int64_t cap);
 
 /* Candidate targets and scores computed while coarsening `level`
@@ -169,7 +187,10 @@ hgp_status hgp_get_proposal(hgp_ctx* ctx, int32_t level, int32_t* cand, uint64_t
 hgp_status hgp_get_level_graph(hgp_ctx* ctx, int32_t level, int64_t* he_off, int32_t* he_nsrc, int32_t* pins,
                                int32_t* node_w);
 
-/* Current partition of the input nodes (N entries) and the partition count. */
+/* Current partitioning rho of the input nodes (Sec. II-B: rho(n) is the
+ * partition holding n, after uncoarsening and refinement, Sec. III and VI),
+ * N entries in [0, *n_parts_out); partitions keep the coarsest level's ids, so
+ * some may be empty.  Requires hgp_refine; cap >= N. */
 hgp_status hgp_get_partition(hgp_ctx* ctx, int32_t* rho_out, int64_t cap, int32_t* n_parts_out);
 
 /*
@@ -247,6 +268,21 @@ hgp_status hgp_reset_kernel_stats(hgp_ctx* ctx);
  * hgp_reset_kernel_stats clears them.  Waits for the context's stream.
  */
 hgp_status hgp_kernel_work(hgp_ctx* ctx, int64_t* work, int32_t* count);
+
+/*
+ * Per-level view of the profiled launches (opt.profile = 1): for level l <
+ * *n_levels_out and family f (the order of hgp_kernel_stats),
+ * out[3 * (l * count + f) + {0, 1, 2}] = launches, nanoseconds and algorithmic
+ * bytes.  Launches belong to coarsening level l (building level l + 1 from
+ * level l; loading counts as level 0) or to the refinement of level l.  The
+ * bytes are counted by the streaming kernels themselves while profiled (the
+ * compulsory reads and writes of what each launch processed: pins, offsets,
+ * gathered partition or cluster ids, rows written) for the families phi,
+ * part_stats, inseq, contract_edges and pack; other families read 0.  Pass
+ * out = NULL to query *n_levels_out; cap >= 3 * levels * count.  Cleared by
+ * hgp_reset_kernel_stats.
+ */
+hgp_status hgp_kernel_level_stats(hgp_ctx* ctx, int64_t* out, int64_t cap, int32_t* n_levels_out);
 
 /* Per-level phase times of the last hgp_coarsen / hgp_refine (HIP events on
  * the context's stream): out[2*l] = coarsen ns of level l, out[2*l+1] =

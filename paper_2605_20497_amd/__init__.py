@@ -79,6 +79,7 @@ def lib():
             "hgp_last_error": (C.c_char_p, [P]),
             "hgp_load_csr": (C.c_int, [P, i32, i32, P, P, P, P, P, C.c_int]),
             "hgp_set_limits": (C.c_int, [P, i64, i64, i32]),
+            "hgp_set_kway_limits": (C.c_int, [P, i32, i32, i32, i64, C.POINTER(i64)]),
             "hgp_coarsen": (C.c_int, [P, C.POINTER(i32)]),
             "hgp_refine": (C.c_int, [P]),
             "hgp_get_levels": (C.c_int, [P, P, i64]),
@@ -94,6 +95,7 @@ def lib():
             "hgp_reset_kernel_stats": (C.c_int, [P]),
             "hgp_kernel_work": (C.c_int, [P, P, C.POINTER(i32)]),
             "hgp_level_times": (C.c_int, [P, P, i64]),
+            "hgp_kernel_level_stats": (C.c_int, [P, P, i64, C.POINTER(i32)]),
             "hgp_run_jobs": (C.c_int, [C.POINTER(hgp_options), C.POINTER(hgp_job), i64, i32, i64]),
         }
         for name, (res, args) in sig.items():
@@ -111,10 +113,11 @@ KERNEL_FAMILIES = ["validate", "transpose", "radix_sort", "scan", "level_stats",
                    "gains_gemm"]
 
 EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
-            "hgp_set_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
+            "hgp_set_limits", "hgp_set_kway_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
             "hgp_get_proposal", "hgp_get_level_graph", "hgp_get_partition", "hgp_get_phi", "hgp_evaluate",
             "hgp_evaluate_noalloc",
             "hgp_refine_rep", "hgp_kernel_stats", "hgp_reset_kernel_stats", "hgp_kernel_work", "hgp_level_times",
+            "hgp_kernel_level_stats",
             "hgp_run_jobs"]
 
 
@@ -187,16 +190,18 @@ class Partitioner:
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
                  use_torch: bool = True, stream=None, sparse_proposal: bool = False, profile_families=(),
-                 dense_proposal=None, dense_gains=None, delta_mode=0, no_chains=False):
+                 dense_proposal=None, dense_gains=None, delta_mode=0, no_chains=False, greedy_matching=False):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
         opt.device, opt.pi, opt.theta, opt.seed, opt.profile = device, pi, theta, seed, int(profile)
         # flags: bit 0 hashed proposal everywhere; bit 1 dense (MFMA) proposal wherever it
         # fits; bit 2 never dense; neither of bits 1-2 = chosen per level by cost; bits 3-4
-        # the same choice for the in-isolation moves of refinement
+        # the same choice for the in-isolation moves of refinement; bit 5 the ablation
+        # without chain rounds; bit 6 the ablation with the prototype's greedy matching
         opt.flags = ((1 if sparse_proposal else 0) | {None: 0, True: 2, False: 4}[dense_proposal]
-                     | {None: 0, True: 8, False: 16}[dense_gains] | (32 if no_chains else 0))
+                     | {None: 0, True: 8, False: 16}[dense_gains] | (32 if no_chains else 0)
+                     | (64 if greedy_matching else 0))
         # what Delta counts: 0 inbound h-edges (the paper's), 1 outbound, 2 incident
         opt.delta_mode = int(delta_mode)
         # kernel families to time (names as in hgp_kernel_stats); empty = all
@@ -256,6 +261,11 @@ class Partitioner:
 
     def hgp_set_limits(self, omega, delta, k=0):
         self._chk(lib().hgp_set_limits(self.h, int(omega), int(delta), int(k)))
+
+    def hgp_set_kway_limits(self, k, eps_num, eps_den, delta=INT64_MAX):
+        om = C.c_int64()
+        self._chk(lib().hgp_set_kway_limits(self.h, int(k), int(eps_num), int(eps_den), int(delta), C.byref(om)))
+        return om.value
 
     def hgp_coarsen(self):
         n = C.c_int32()
@@ -375,6 +385,16 @@ class Partitioner:
         out = np.zeros(2 * self.nlevels, np.int64)
         self._chk(lib().hgp_level_times(self.h, _p(out), out.size))
         return out.reshape(-1, 2)
+
+    def hgp_kernel_level_stats(self):
+        """{family: array [levels, 3] of (launches, ns, algorithmic bytes)}."""
+        nl = C.c_int32()
+        self._chk(lib().hgp_kernel_level_stats(self.h, None, 0, C.byref(nl)))
+        F = len(KERNEL_FAMILIES)
+        out = np.zeros(nl.value * F * 3, np.int64)
+        self._chk(lib().hgp_kernel_level_stats(self.h, _p(out), out.size, C.byref(nl)))
+        out = out.reshape(nl.value, F, 3)
+        return {f: out[:, i, :] for i, f in enumerate(KERNEL_FAMILIES)}
 
     # -- convenience -------------------------------------------------------
     def load(self, hg):

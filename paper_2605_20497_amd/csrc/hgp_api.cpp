@@ -42,11 +42,19 @@ static void prof_flush(Ctx* c) {
     Prof& P = c->prof;
     if (P.open.empty()) return;
     HIPC(hipStreamSynchronize(c->stream));
+    if (P.lv_ns.empty()) {
+        P.lv_ns.assign((size_t)kProfLevels * KF_COUNT, 0);
+        P.lv_launches.assign((size_t)kProfLevels * KF_COUNT, 0);
+    }
     for (auto& o : P.open) {
         float ms = 0.f;
-        HIPC(hipEventElapsedTime(&ms, o.second.first, o.second.second));
-        P.ns[o.first] += (i64)((double)ms * 1e6);
-        P.launches[o.first] += 1;
+        HIPC(hipEventElapsedTime(&ms, o.begin, o.end));
+        const i64 ns = (i64)((double)ms * 1e6);
+        P.ns[o.kf] += ns;
+        P.launches[o.kf] += 1;
+        const size_t at = (size_t)o.level * KF_COUNT + o.kf;
+        P.lv_ns[at] += ns;
+        P.lv_launches[at] += 1;
     }
     P.open.clear();
     P.used = 0;
@@ -67,11 +75,25 @@ void prof_end(Ctx* c, int kf) {
     if (!prof_on(c, kf)) return;
     hipEvent_t e = prof_event(c);
     HIPC(hipEventRecord(e, c->stream));
-    c->prof.open.push_back({kf, {c->prof.cur_begin, e}});
+    c->prof.open.push_back({kf, c->prof.level, c->prof.cur_begin, e});
 }
 
 void prof_add_work(Ctx* c, int kf, i64 units) {
     if (prof_on(c, kf)) c->prof.host_work[kf] += units;
+}
+
+void prof_level(Ctx* c, int lv) { c->prof.level = std::max(0, std::min(lv, kProfLevels - 1)); }
+
+unsigned long long* prof_bytes(Ctx* c, int kf) {
+    if (!prof_on(c, kf)) return nullptr;
+    Prof& P = c->prof;
+    if (!P.lv_bytes) {
+        const size_t sz = sizeof(unsigned long long) * (size_t)kProfLevels * KF_COUNT;
+        P.b_lv_bytes = c->alloc(sz);
+        P.lv_bytes = (unsigned long long*)P.b_lv_bytes.p;
+        HIPC(hipMemsetAsync(P.lv_bytes, 0, sz, c->stream));
+    }
+    return P.lv_bytes + (size_t)P.level * KF_COUNT + kf;
 }
 
 unsigned long long* prof_work(Ctx* c, int kf) {
@@ -331,6 +353,7 @@ void hgp_destroy(hgp_ctx* h) {
         c->release(c->b_hw);
         for (auto& b : c->ws) c->release(b);
         c->release(c->prof.b_work);
+        c->release(c->prof.b_lv_bytes);
         (void)hipStreamSynchronize(c->stream);
         for (auto e : c->prof.pool) (void)hipEventDestroy(e);
         if (c->host_scalars) (void)hipHostFree(c->host_scalars);
@@ -355,6 +378,7 @@ hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int
     c->levels.clear();
     c->release(c->b_hw);
     c->loaded = c->limits_set = false;
+    prof_level(c, 0);
     const hipMemcpyKind kind = where == HGP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     i64 P = 0;
     if (where == HGP_MEM_HOST) {
@@ -437,6 +461,27 @@ hgp_status hgp_set_limits(hgp_ctx* h, int64_t omega, int64_t delta, int32_t k) {
     API_END
 }
 
+hgp_status hgp_set_kway_limits(hgp_ctx* h, int32_t k, int32_t eps_num, int32_t eps_den, int64_t delta,
+                               int64_t* omega_out) {
+    if (!h) return HGP_E_INVALID;
+    Ctx* c = &h->c;
+    if (!c->loaded) {
+        c->err = "load a hypergraph first";
+        return HGP_E_STATE;
+    }
+    if (k < 1 || eps_num < 0 || eps_den < 1) {
+        c->err = "need k >= 1, eps_num >= 0, eps_den >= 1";
+        return HGP_E_INVALID;
+    }
+    // Omega = (1 + eps) * W / k (Sec. VII-A), with W / k rounded up and the
+    // product rounded down; W is the total node weight
+    const i64 per = (c->total_nw + k - 1) / k;
+    const i64 omega = ((i64)eps_den + eps_num) * per / eps_den;
+    const hgp_status st = hgp_set_limits(h, omega, delta, k);
+    if (st == HGP_OK && omega_out) *omega_out = omega;
+    return st;
+}
+
 hgp_status hgp_coarsen(hgp_ctx* h, int32_t* n_levels_out) {
     API_BEGIN(h)
     require(c->loaded && c->limits_set, HGP_E_STATE, "load a hypergraph and set limits first");
@@ -449,6 +494,7 @@ hgp_status hgp_coarsen(hgp_ctx* h, int32_t* n_levels_out) {
         if (c->k > 0 && N < 4096) break;
         auto ev = new_event_pair(c);
         HIPC(hipEventRecord(ev.first, c->stream));
+        prof_level(c, lv);
         coarsen_level(c, lv);
         HIPC(hipEventRecord(ev.second, c->stream));
         c->level_ev_coarsen.push_back(ev);
@@ -491,14 +537,17 @@ static void refine_all(Ctx* c) {
         const Level& L = c->levels[lv];
         auto ev = new_event_pair(c);
         HIPC(hipEventRecord(ev.first, c->stream));
+        prof_level(c, lv);
         if (lv < l) {
             project_rho(c, cur, L.gamma(), nxt, L.N);
             std::swap(cur, nxt);
         }
         bool unchanged = false;  // rho as the previous repetition found it
+        i64 applied = 0;         // moves the previous repetition applied (0: rows built in full)
         for (int rep = 0; rep < theta; ++rep) {
-            RepInfo ri = refine_rep(c, L, cur, c->nparts, rep, theta, nullptr, unchanged);
+            RepInfo ri = refine_rep(c, L, cur, c->nparts, rep, theta, nullptr, unchanged, applied);
             unchanged = ri.kstar == 0;
+            applied = ri.kstar;
             // A repetition that applies nothing leaves rho and the sizes as
             // they were, so the rest of its half would repeat it exactly.
             if (ri.kstar == 0) {
@@ -691,6 +740,11 @@ hgp_status hgp_reset_kernel_stats(hgp_ctx* h) {
     prof_flush(c);
     for (int i = 0; i < KF_COUNT; ++i) c->prof.launches[i] = c->prof.ns[i] = c->prof.host_work[i] = 0;
     if (c->prof.work) HIPC(hipMemsetAsync(c->prof.work, 0, sizeof(unsigned long long) * KF_COUNT, c->stream));
+    std::fill(c->prof.lv_ns.begin(), c->prof.lv_ns.end(), 0);
+    std::fill(c->prof.lv_launches.begin(), c->prof.lv_launches.end(), 0);
+    if (c->prof.lv_bytes)
+        HIPC(hipMemsetAsync(c->prof.lv_bytes, 0, sizeof(unsigned long long) * (size_t)kProfLevels * KF_COUNT,
+                            c->stream));
     API_END
 }
 
@@ -704,6 +758,29 @@ hgp_status hgp_kernel_work(hgp_ctx* h, int64_t* work, int32_t* count) {
             HIPC(hipStreamSynchronize(c->stream));
         }
         for (int i = 0; i < KF_COUNT; ++i) work[i] = (int64_t)w[i] + c->prof.host_work[i];
+    }
+    API_END
+}
+
+hgp_status hgp_kernel_level_stats(hgp_ctx* h, int64_t* out, int64_t cap, int32_t* n_levels_out) {
+    API_BEGIN(h)
+    const i64 L = std::min<i64>((i64)c->levels.size(), kProfLevels);
+    if (n_levels_out) *n_levels_out = (int32_t)L;
+    if (out) {
+        require(cap >= L * KF_COUNT * 3, HGP_E_INVALID, "cap too small");
+        prof_flush(c);
+        std::vector<unsigned long long> b((size_t)L * KF_COUNT, 0);
+        if (c->prof.lv_bytes && L > 0) {
+            HIPC(hipMemcpyAsync(b.data(), c->prof.lv_bytes, sizeof(unsigned long long) * b.size(),
+                                hipMemcpyDeviceToHost, c->stream));
+            HIPC(hipStreamSynchronize(c->stream));
+        }
+        for (i64 i = 0; i < L * KF_COUNT; ++i) {
+            const bool any = !c->prof.lv_ns.empty();
+            out[3 * i] = any ? c->prof.lv_launches[i] : 0;
+            out[3 * i + 1] = any ? c->prof.lv_ns[i] : 0;
+            out[3 * i + 2] = (int64_t)b[i];
+        }
     }
     API_END
 }

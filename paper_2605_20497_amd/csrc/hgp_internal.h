@@ -51,6 +51,12 @@ unsigned long long* prof_work(Ctx* c, int kf);
 // Adds work units known on the host (e.g. the MACs of a dense product) to
 // family kf's counter when the family is profiled.
 void prof_add_work(Ctx* c, int kf, i64 units);
+// Device counter of the algorithmic bytes (compulsory reads and writes) of
+// family kf's launches at the current level, or null when kf is not profiled;
+// streaming kernels add to it once per wave when non-null.
+unsigned long long* prof_bytes(Ctx* c, int kf);
+// Attributes the following launches to level `lv`.
+void prof_level(Ctx* c, int lv);
 
 #define LAUNCH(ctx, kf, kern, grid, block, shmem, ...)                                  \
     do {                                                                                \
@@ -86,9 +92,18 @@ struct Level {
     i32* gamma() const { return (i32*)b_gamma.p; }
 };
 
+// Launches are attributed to a level: coarsening level l (building G_(l+1)
+// from G_l, the load counting as level 0) or the refinement of level l.
+constexpr int kProfLevels = 1024;
+
+struct ProfOpen {
+    int kf, level;
+    hipEvent_t begin, end;
+};
+
 struct Prof {
     std::vector<hipEvent_t> pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open;
+    std::vector<ProfOpen> open;
     i64 launches[KF_COUNT] = {0};
     i64 ns[KF_COUNT] = {0};
     size_t used = 0;
@@ -96,6 +111,11 @@ struct Prof {
     unsigned long long* work = nullptr;  // device, KF_COUNT counters; allocated when first asked for
     Buf b_work;
     i64 host_work[KF_COUNT] = {0};
+    int level = 0;                        // level the next launches belong to
+    std::vector<i64> lv_launches, lv_ns;  // [level * KF_COUNT + kf]
+    // device [kProfLevels * KF_COUNT]: algorithmic bytes counted by the kernels
+    unsigned long long* lv_bytes = nullptr;
+    Buf b_lv_bytes;
 };
 
 struct Ctx {
@@ -201,9 +221,13 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out);
 // destinations, no sources).
 void retarget_pins(Ctx* c, Level& L, int mode);
 // Phi rows of every h-edge at its pin offset; with `single`, one byte per pin
-// slot that is 1 when pins(rho(m), e) = 1 for the slot's pin m.
+// slot that is 1 when pins(rho(m), e) = 1 for the slot's pin m; with `part16`,
+// a 16-bit copy of each row's partition id whose top bit marks pins(p,e) = 1
+// (partition ids below 2^15).  With `elist`, only the *ecount h-edges it lists
+// (a device count) are rebuilt; the other rows are left as they are.
 void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len,
-               unsigned char* single = nullptr);
+               unsigned char* single = nullptr, unsigned short* part16 = nullptr, const i32* elist = nullptr,
+               const u32* ecount = nullptr);
 
 // ---------------------------------------------------------------------------
 // Coarsening launchers (k_coarsen.hip).
@@ -239,8 +263,10 @@ struct RepTrace {
 };
 // reuse = rho is unchanged since the previous call on this level (it applied
 // no move), so its pins rows, sizes and moves are taken as they are.
+// incr_k > 0 = the previous call on this level applied the first incr_k moves
+// of its sequence: only the pins rows of their h-edges are rebuilt.
 RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace = nullptr,
-                   bool reuse = false);
+                   bool reuse = false, i64 incr_k = 0);
 void project_rho(Ctx* c, const i32* rho_coarse, const i32* gamma, i32* rho_fine, i32 N);
 void evaluate_dev(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_eval* out);
 

@@ -409,14 +409,153 @@ __global__ __launch_bounds__(WAVES * kWave) void k_propose(
 // Sparse variant of the proposal for levels with many nodes and modest
 // neighbourhoods: the histogram is an open-addressing table of C slots in
 // shared memory (key, packed (eta << ib) | inter, and a list of used slots).
-// When a node's neighbour bound sum_{e in I(n)} (|e| - 1) exceeds half the
-// table, neighbours are split into B passes by a hash of their id; a pass whose
-// keys do not fit restarts the node with twice as many passes.  The result is
-// the same exact top-PI as the dense variant.
+// Neighbours may be split into B passes by a hash of their id.  A node starts
+// with the pass count its block's previous node needed; a pass that meets more
+// than `cap` distinct keys is abandoned at once and the node restarts with
+// twice as many passes.  The result is the same exact top-PI as the dense
+// variant whatever B is.
+//
+// Pin sweep: h-edges G at a time, GU coalesced loads per h-edge and lane,
+// software pipelined, as in the id-range variant (propose_group).
 constexpr u32 kEmpty = 0xFFFFFFFFu;
+constexpr u32 kNoSlot = 0xFFFFFFFFu;  // a ticket whose slot claim lost its race
 
 __device__ __forceinline__ u32 slot_hash(u32 m) { return m * 0x9E3779B1u; }
 __device__ __forceinline__ u32 pass_hash(u32 m) { return (m * 0x85EBCA77u) ^ (m >> 15); }
+
+template <typename BIN>
+struct HashTab {
+    u32* keys;
+    BIN* vals;
+    u32* touched;   // ticket -> slot (kNoSlot when the claim lost)
+    u32* nticket;   // tickets taken this pass
+    int* overflow;  // set once a ticket reaches cap
+    u32 cmask, cap;
+};
+
+// Adds v to key m's slot.  A new key first takes a ticket; tickets at or beyond
+// cap abandon the pass, so fewer than cap slots are ever claimed and the probe
+// always meets an empty slot or the key.
+template <typename BIN>
+__device__ __forceinline__ void hash_add(const HashTab<BIN>& T, u32 m, BIN v) {
+    u32 sl = slot_hash(m) & T.cmask;
+    for (;;) {
+        const u32 kk = T.keys[sl];
+        if (kk == m) {
+            atomicAdd(&T.vals[sl], v);
+            return;
+        }
+        if (kk == kEmpty) {
+            const u32 t = atomicAdd(T.nticket, 1u);
+            if (t >= T.cap) {
+                *T.overflow = 1;
+                return;
+            }
+            const u32 prev = atomicCAS(&T.keys[sl], kEmpty, m);
+            T.touched[t] = prev == kEmpty ? sl : kNoSlot;
+            if ((int)(prev == kEmpty) | (int)(prev == m)) {
+                atomicAdd(&T.vals[sl], v);
+                return;
+            }
+        }
+        sl = (sl + 1) & T.cmask;
+    }
+}
+
+// Entries that miss their home slot wait in a per-wave ring in shared memory
+// and are inserted 64 at a time, one per lane, so the probing loop runs on
+// full waves instead of once per entry with a few lanes.
+template <typename BIN>
+struct MissQueue {
+    SelQueue<BIN>* q;  // the wave's ring (the selection's queue, idle during the sweep)
+    u32 head, count;
+};
+
+template <typename BIN>
+__device__ __forceinline__ void miss_drain(MissQueue<BIN>& Q, u32 cnt, const HashTab<BIN>& T) {
+    wave_sync();  // the ring's writes are visible to every lane
+    const int lane = lane_id();
+    const int on = (int)((u32)lane < cnt);
+    const u32 at = (Q.head + (u32)lane) & (u32)(kSelQ - 1);
+    const i32 m = on ? Q.q->m[at] : 0;
+    const BIN v = on ? Q.q->v[at] : (BIN)0;
+    wave_sync();  // the slots may be refilled from here on
+    Q.head += cnt;
+    Q.count -= cnt;
+    if (on) hash_add(T, (u32)m, v);
+}
+
+template <typename BIN>
+__device__ __forceinline__ void miss_push(MissQueue<BIN>& Q, int miss, i32 m, BIN v, const HashTab<BIN>& T) {
+    const u64 mask = __ballot(miss);
+    if (mask == 0) return;
+    if (miss) {
+        const u32 below = __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+        const u32 at = (Q.head + Q.count + below) & (u32)(kSelQ - 1);
+        Q.q->m[at] = m;
+        Q.q->v[at] = v;
+    }
+    Q.count += (u32)__popcll(mask);
+    if (Q.count >= (u32)kWave) miss_drain(Q, (u32)kWave, T);
+}
+
+// The chunk's home slots are read together first; entries whose key already
+// sits in its home slot (most of them once a node's neighbours are in the
+// table) add without waiting, the rest go to the wave's miss ring.
+template <int G, int GU, typename BIN>
+__device__ __forceinline__ void group_apply_hash(const GroupChunk<G, GU, BIN>& c, i32 n, u32 bmask, u32 pass,
+                                                 const HashTab<BIN>& T, MissQueue<BIN>& Q) {
+    u32 home[G][GU], seen[G][GU];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const u32 m = (u32)c.m[g][u];
+            home[g][u] = slot_hash(m) & T.cmask;
+            seen[g][u] = T.keys[home[g][u]];
+        }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const i32 m = c.m[g][u];
+            const int mine = (int)(m != n) & (int)((pass_hash((u32)m) & bmask) == pass);
+            const int hit = mine & (int)(seen[g][u] == (u32)m);
+            if (hit) atomicAdd(&T.vals[home[g][u]], c.ad[g][u]);
+            miss_push(Q, mine & !hit, m, c.ad[g][u], T);
+        }
+}
+
+// One wave batch: the grouped, pipelined sweep of propose_group with hashed
+// updates; stops early once the pass has overflowed.
+template <int G, int GU, typename BIN>
+__device__ __forceinline__ void hash_group(int nb, int lane, i32 n, u32 bmask, u32 pass, const i32* __restrict__ pins,
+                                           i64 e0, i32 cs, i32 cd, BIN add, BIN add_in, const HashTab<BIN>& T,
+                                           MissQueue<BIN>& Q) {
+    if (nb <= 0) return;
+    GroupChunk<G, GU, BIN> c0, c1;
+    int i0 = 0;
+    i32 q0 = 0;
+    auto next = [&](i32 mt) {
+        q0 += GU * kWave;
+        if (q0 >= mt) {
+            i0 += G;
+            q0 = 0;
+        }
+    };
+    const volatile int* ovf = T.overflow;
+    i32 mt = group_load<G, GU>(i0, q0, nb, lane, n, pins, e0, cs, cd, 0, add, add_in, c0);
+    while (true) {
+        next(mt);
+        if (i0 < nb) mt = group_load<G, GU>(i0, q0, nb, lane, n, pins, e0, cs, cd, 0, add, add_in, c1);
+        group_apply_hash(c0, n, bmask, pass, T, Q);
+        if ((int)(i0 >= nb) | *ovf) break;
+        next(mt);
+        if (i0 < nb) mt = group_load<G, GU>(i0, q0, nb, lane, n, pins, e0, cs, cd, 0, add, add_in, c0);
+        group_apply_hash(c1, n, bmask, pass, T, Q);
+        if ((int)(i0 >= nb) | *ovf) break;
+    }
+}
 
 template <typename BIN, int PI>
 __global__ __launch_bounds__(256) void k_propose_hash(
@@ -428,11 +567,10 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     BIN* vals = (BIN*)smem_raw;
     u32* keys = (u32*)(vals + C);
     u32* touched = keys + C;
-    __shared__ u32 ntouched;
+    __shared__ u32 nticket;
     __shared__ int overflow;
     __shared__ u64 red_s[16];
     __shared__ i32 red_m[16];
-    __shared__ u64 red_b[16];
     __shared__ SelQueue<BIN> selq[4];
     __shared__ unsigned long long s_floor;
     SelNode sn;
@@ -446,98 +584,80 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     sn.inc_nin = inc_nin;
     sn.floor = &s_floor;
     sn.union_floor = 1;
-    const u32 cmask = (u32)C - 1;
+    HashTab<BIN> T;
+    T.keys = keys;
+    T.vals = vals;
+    T.touched = touched;
+    T.nticket = &nticket;
+    T.overflow = &overflow;
+    T.cmask = (u32)C - 1;
+    T.cap = (u32)C - (u32)C / 4;  // load factor at most 3/4
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     for (int i = threadIdx.x; i < C; i += blockDim.x) {
         vals[i] = 0;
         keys[i] = kEmpty;
     }
     if (threadIdx.x == 0) {
-        ntouched = 0;
+        nticket = 0;
         overflow = 0;
     }
     __syncthreads();
+    u64 Bhint = 1;  // passes the block's previous node needed
     for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i32 nin_n = inc_nin[n];
         const i64 nw_n = nw[n];
-        // Upper bound on the number of distinct neighbours.
-        u64 bound = 0;
-        for (i64 k = a + threadIdx.x; k < b; k += blockDim.x) {
-            const i32 e = inc[k];
-            bound += (u64)(he_off[e + 1] - he_off[e] - 1);
-        }
-        bound = block_sum(bound, red_b);
         // Passes split the neighbours by a hash of their id; any split gives the
         // same result, so the count is a power of two (a mask, not a division).
-        u64 B = 1;
-        while (B * (u64)(C / 2) < bound) B <<= 1;
+        u64 B = Bhint;
         sn.n = n;
         sn.nin_n = nin_n;
         sn.nw_n = nw_n;
         sn.all_valid = (int)(nw_n + (i64)stats[11] <= omega) & (int)((i64)nin_n + (i64)stats[1] <= delta);
+        // h-edges per wave batch: spread the node's h-edges evenly over the waves.
+        const i64 deg = b - a;
+        const bool one_batch = deg <= (i64)nwv * kWave;
+        const i64 chunk = one_batch ? (deg + nwv - 1) / nwv : (i64)kWave;
         TopList<PI> top;
-        for (;;) {  // restarts with more passes if a pass overflows the table
+        u32 most = 0;  // most keys any pass of the node held
+        for (;;) {     // restarts with more passes if a pass overflows the table
             top.clear();
+            most = 0;
             if (threadIdx.x == 0) s_floor = 0;  // read after the first pass's barrier
             bool again = false;
-            for (u64 pass = 0; pass < B && bound > 0; ++pass) {
-                for (i64 kb = a + (i64)wv * kWave; kb < b; kb += (i64)nwv * kWave) {
+            for (u64 pass = 0; pass < B && a < b; ++pass) {
+                MissQueue<BIN> Q{&selq[wv], 0u, 0u};
+                for (i64 kb = a + (i64)wv * chunk; kb < b; kb += (i64)nwv * chunk) {
                     const i64 k = kb + lane;
-                    const int valid = (int)(k < b);
+                    const int valid = (int)(lane < chunk) & (int)(k < b);
                     const i32 e = inc[valid ? k : kb];
-                    const i64 e0 = he_off[e], e1v = he_off[e + 1];
-                    const i64 e1 = valid ? e1v : e0;
-                    const i64 d0 = e0 + he_nsrc[e];
-                    const BIN add = ((BIN)norm_weight(hw[e], e1v - e0)) << ib;
-                    const int ein = (int)((k - a) < nin_n);
-                    const int nb = (int)((b - kb) < kWave ? (b - kb) : kWave);
-                    for (int i = 0; i < nb; ++i) {
-                        const i64 s0 = __shfl(e0, i, kWave), s1 = __shfl(e1, i, kWave), sd = __shfl(d0, i, kWave);
-                        const BIN sadd = __shfl(add, i, kWave);
-                        const int sin = __shfl(ein, i, kWave);
-                        for (i64 j = s0 + lane; j < s1; j += kWave) {
-                            const i32 m = pins[j];
-                            const int mine = (int)(m != n) & (int)(((u64)pass_hash((u32)m) & (B - 1)) == pass);
-                            if (!mine) continue;
-                            const BIN v = sadd + ((sin & (int)(j >= sd)) ? (BIN)1 : (BIN)0);
-                            u32 sl = slot_hash((u32)m) & cmask;
-                            int done = 0;
-                            for (int probe = 0; probe < C; ++probe) {
-                                const u32 kk = keys[sl];
-                                if (kk == (u32)m) {
-                                    atomicAdd(&vals[sl], v);
-                                    done = 1;
-                                    break;
-                                }
-                                if (kk == kEmpty) {
-                                    const u32 prev = atomicCAS(&keys[sl], kEmpty, (u32)m);
-                                    if (prev == kEmpty) {
-                                        touched[atomicAdd(&ntouched, 1u)] = sl;
-                                        atomicAdd(&vals[sl], v);
-                                        done = 1;
-                                        break;
-                                    }
-                                    if (prev == (u32)m) {
-                                        atomicAdd(&vals[sl], v);
-                                        done = 1;
-                                        break;
-                                    }
-                                }
-                                sl = (sl + 1) & cmask;
-                            }
-                            if (!done) overflow = 1;
-                        }
-                    }
+                    const i64 e0 = he_off[e], e1 = he_off[e + 1];
+                    const i32 ns = he_nsrc[e];
+                    const BIN add = ((BIN)norm_weight(hw[e], e1 - e0)) << ib;
+                    const BIN add_in = add + (((k - a) < nin_n) ? (BIN)1 : (BIN)0);  // dsts of e lie in in(n)
+                    const i32 cs = valid ? ns : 0;
+                    const i32 cd = valid ? (i32)(e1 - e0) - ns : 0;
+                    const i32 tot = wave_sum(cs + cd);
+                    const int nb = __popcll(__ballot(valid));
+                    const i32 avg = tot / max(nb, 1);
+                    const u32 bm = (u32)(B - 1), ps = (u32)pass;
+                    if (avg <= 64)
+                        hash_group<16, 1>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
+                    else if (avg <= 128)
+                        hash_group<8, 2>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
+                    else
+                        hash_group<4, 4>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
                 }
+                if (Q.count > 0) miss_drain(Q, Q.count, T);  // the rest of the wave's misses
                 __syncthreads();
-                const u32 nt = ntouched;
+                const u32 nt = min(nticket, T.cap);
                 const int ov = overflow;
+                most = max(most, nt);
                 u32 qh = 0, qn = 0;
                 for (u32 t0 = 0; t0 < nt; t0 += blockDim.x) {
                     const u32 t = t0 + threadIdx.x;
-                    const int in = (int)(t < nt);
-                    const u32 sl = in ? touched[t] : 0u;
+                    const u32 sl = t < nt ? touched[t] : kNoSlot;
+                    const int in = (int)(sl != kNoSlot);
                     const i32 m = in ? (i32)keys[sl] : 0;
                     const BIN v = in ? vals[sl] : (BIN)0;
                     if (in) {
@@ -550,7 +670,7 @@ __global__ __launch_bounds__(256) void k_propose_hash(
                 sel_flush(selq[wv], qh, qn, top, sn);
                 __syncthreads();
                 if (threadIdx.x == 0) {
-                    ntouched = 0;
+                    nticket = 0;
                     overflow = 0;
                 }
                 __syncthreads();
@@ -562,6 +682,9 @@ __global__ __launch_bounds__(256) void k_propose_hash(
             if (!again) break;
             B *= 2;
         }
+        // the next node starts from this node's pass count, one fewer halving
+        // step when the table stayed at most a quarter full
+        Bhint = (most <= (u32)C / 4 && B > 1) ? B / 2 : B;
         sel_merge(top, red_s, red_m, cand + (i64)n * PI, score + (i64)n * PI);
     }
 }
@@ -700,7 +823,60 @@ __device__ __forceinline__ void down_elem(i64 n, int d, const i32* __restrict__ 
     }
 }
 
+// The prototype's greedy matching (the ablation of Sec. VII-D, Reading R28):
+// every node's best child by (score, id), the lexicographic maximum taken in
+// two phases (scores, then the ids holding the maximum score); two-cycles
+// always matched; then, from the roots down, a node left unmatched takes its
+// best child.
+__device__ __forceinline__ void greedy_best_a_elem(i64 n, const i32* __restrict__ parent, const u64* __restrict__ s,
+                                                   u64* accBV) {
+    const i32 p = parent[n];
+    if (p >= 0) atomicMax((unsigned long long*)&accBV[p], (unsigned long long)s[n]);
+}
+
+__device__ __forceinline__ void greedy_best_b_elem(i64 n, const i32* __restrict__ parent, const u64* __restrict__ s,
+                                                   const u64* __restrict__ accBV, i32* accBC) {
+    const i32 p = parent[n];
+    const u64 bv = load_l2(&accBV[p >= 0 ? p : 0]);
+    if ((int)(p >= 0) & (int)(s[n] == bv)) atomicMax(&accBC[p], (i32)n);
+}
+
+__device__ __forceinline__ void greedy_pairs_elem(i64 n, const i32* __restrict__ t, i32* match) {
+    const i32 m = t[n];
+    const i32 tm = t[m >= 0 ? m : 0];
+    if ((int)(m >= 0) & (int)(tm == (i32)n)) match[n] = m;
+}
+
+__device__ __forceinline__ void greedy_down_elem(i64 n, int d, const i32* __restrict__ depth,
+                                                 const i32* __restrict__ accBC, i32* match) {
+    const i32 dn = depth[n], mn = match[n];
+    if ((int)(dn != d) | (int)(mn >= 0)) return;
+    const i32 bc = load_l2(&accBC[n]);
+    if (bc >= 0) {
+        match[n] = bc;
+        match[bc] = (i32)n;
+    }
+}
+
 #define HGP_GRID_LOOP(i, n) for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
+
+__global__ void k_greedy_best_a(i32 N, const i32* __restrict__ parent, const u64* __restrict__ s, u64* accBV) {
+    HGP_GRID_LOOP(n, N) greedy_best_a_elem(n, parent, s, accBV);
+}
+
+__global__ void k_greedy_best_b(i32 N, const i32* __restrict__ parent, const u64* __restrict__ s,
+                                const u64* __restrict__ accBV, i32* accBC) {
+    HGP_GRID_LOOP(n, N) greedy_best_b_elem(n, parent, s, accBV, accBC);
+}
+
+__global__ void k_greedy_pairs(i32 N, const i32* __restrict__ t, i32* match) {
+    HGP_GRID_LOOP(n, N) greedy_pairs_elem(n, t, match);
+}
+
+__global__ void k_greedy_down(i32 N, int d, const i32* __restrict__ depth, const i32* __restrict__ accBC,
+                              i32* match) {
+    HGP_GRID_LOOP(n, N) greedy_down_elem(n, d, depth, accBC, match);
+}
 
 __global__ void k_round_targets(i32 N, int Pi, int r, const i32* __restrict__ cand, const u64* __restrict__ score,
                                 const i32* __restrict__ match, i32* t, u64* s) {
@@ -757,7 +933,7 @@ constexpr int kMatchSingleMax = 16384;
 __global__ __launch_bounds__(1024) void k_match_rounds(i32 N, int Pi, int jump_iters, const i32* __restrict__ cand,
                                                        const u64* __restrict__ score, i32* match, i32* t, u64* s,
                                                        i32* parent, i32* j0, i32* j1, i32* d0, i32* d1, i64* accA,
-                                                       u64* accBV, i32* accBC, i64* ss0, i64* ss10) {
+                                                       u64* accBV, i32* accBC, i64* ss0, i64* ss10, int greedy) {
     __shared__ unsigned long long red[16];
     __shared__ i32 redi[16];
     for (int r = 0; r < Pi; ++r) {
@@ -788,6 +964,18 @@ __global__ __launch_bounds__(1024) void k_match_rounds(i32 N, int Pi, int jump_i
         for (int w = 0; w < (int)(blockDim.x / kWave); ++w) maxd = max(maxd, redi[w]);
         __syncthreads();
         const i32* depth = da;
+        if (greedy) {
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x) greedy_best_a_elem(n, parent, s, accBV);
+            __syncthreads();
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x) greedy_best_b_elem(n, parent, s, accBV, accBC);
+            for (i64 n = threadIdx.x; n < N; n += blockDim.x) greedy_pairs_elem(n, t, match);
+            __syncthreads();
+            for (int d = 0; d <= maxd; ++d) {
+                for (i64 n = threadIdx.x; n < N; n += blockDim.x) greedy_down_elem(n, d, depth, accBC, match);
+                __syncthreads();
+            }
+            continue;
+        }
         for (int d = maxd; d >= 0; --d) {
             for (i64 n = threadIdx.x; n < N; n += blockDim.x)
                 up_a_elem(n, d, depth, parent, s, accA, accBV, accBC, ss0, ss10);
@@ -904,7 +1092,11 @@ void launch_propose_hash(Ctx* c, const Level& L, int Pi, const unsigned long lon
                          u64* score) {
     const int C = 4096;  // slots; shared memory = C * (8 + sizeof(BIN)) bytes
     const size_t lds = (size_t)C * (8 + sizeof(BIN));
-    const int grid = std::min<i64>(L.N, (i64)c->num_cu * 4);
+    // as many blocks as are resident at once (shared memory, at most 4 per CU
+    // by registers): a second, partial round of blocks would leave most of the
+    // chip idle while it runs
+    const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / (lds + (sizeof(BIN) == 4 ? 5 : 7) * 1024))));
+    const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu);
 #define HGP_PROPH(PIV)                                                                                             \
     case PIV:                                                                                                      \
         LAUNCH(c, KF_PROPOSE, (k_propose_hash<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(),          \
@@ -1039,9 +1231,10 @@ void coarsen_level(Ctx* c, int lv) {
     i64* ss10 = wsp<i64>(c, WS_SS10, N);
     fill_i32(c, match, -1, N);
     const int jump_iters = bits_for((u64)N) + 1;
+    const int greedy = (c->opt.flags & 64) ? 1 : 0;  // the prototype's greedy matching (ablation)
     if (N <= kMatchSingleMax)
         LAUNCH(c, KF_MATCH, k_match_rounds, 1, 1024, 0, N, Pi, jump_iters, cand, (const u64*)score, match, t, s,
-               parent, j0, j1, d0, d1, accA, accBV, accBC, ss0, ss10);
+               parent, j0, j1, d0, d1, accA, accBV, accBC, ss0, ss10, greedy);
     for (int r = 0; r < Pi && N > kMatchSingleMax; ++r) {
         LAUNCH(c, KF_MATCH, k_round_targets, nb, 256, 0, N, Pi, r, cand, score, match, t, s);
         LAUNCH(c, KF_MATCH, k_round_parent, nb, 256, 0, N, t, parent, j0, d0, accA, accBV, accBC);
@@ -1062,6 +1255,14 @@ void coarsen_level(Ctx* c, int lv) {
         i64 maxd = 0;
         read_back(c, stats + 5, &maxd, 1, 8);
         const i32* depth = da;
+        if (greedy) {
+            LAUNCH(c, KF_MATCH, k_greedy_best_a, nb, 256, 0, N, parent, s, accBV);
+            LAUNCH(c, KF_MATCH, k_greedy_best_b, nb, 256, 0, N, parent, s, accBV, accBC);
+            LAUNCH(c, KF_MATCH, k_greedy_pairs, nb, 256, 0, N, t, match);
+            for (int d = 0; d <= (int)maxd; ++d)
+                LAUNCH(c, KF_MATCH, k_greedy_down, nb, 256, 0, N, d, depth, accBC, match);
+            continue;
+        }
         for (int d = (int)maxd; d >= 0; --d) {
             LAUNCH(c, KF_MATCH, k_up_a, nb, 256, 0, N, d, depth, parent, s, accA, accBV, accBC, ss0, ss10);
             LAUNCH(c, KF_MATCH, k_up_b, nb, 256, 0, N, d, depth, parent, ss10, accBV, accBC);

@@ -156,9 +156,11 @@ __global__ void k_inc_offsets(i32 N, i64 P, const u32* __restrict__ skeys, i64* 
 __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __restrict__ he_off,
                                                         const i32* __restrict__ he_nsrc,
                                                         const i32* __restrict__ pins, const i32* __restrict__ gamma,
-                                                        i32* tmp, i32* card_out, i32* nsrc_out, int skip_le) {
+                                                        i32* tmp, i32* card_out, i32* nsrc_out, int skip_le,
+                                                        unsigned long long* bytes) {
     extern __shared__ u32 keys[];
     __shared__ i32 red[16];
+    u64 acc = 0;  // algorithmic bytes of the h-edges this block handled
     for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
@@ -196,20 +198,35 @@ __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __rest
             card_out[e] = run_s + run_d;
             nsrc_out[e] = run_s;
         }
+        // offsets and |src| read, pins and their cluster ids read, the
+        // coarse pins and the two counts written
+        acc += 20 + 8 * (u64)card + 4 * (u64)(run_s + run_d);
         __syncthreads();
     }
+    if ((bytes != nullptr) & (threadIdx.x == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // Compacts per-h-edge segments written at old offsets into the new layout.
 __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict__ old_off,
                                                     const i64* __restrict__ new_off, const i32* __restrict__ tmp,
-                                                    i32* out) {
+                                                    i32* out, unsigned long long* bytes) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
+    u64 acc = 0;
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
         const i64 a = old_off[e], o = new_off[e], n = new_off[e + 1] - o;
         for (i64 j = lane; j < n; j += kWave) out[o + j] = tmp[a + j];
+        acc += 16 + 8 * (u64)n;  // both offsets; each pin read once and written once
     }
+    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+}
+
+// Algorithmic bytes of one h-edge's rows: offsets, |src| and lambda (16), its
+// pins and their partition ids read (8 per pin), part / cnt / cnt_in written
+// (12 per row), plus the 16-bit copy (2 per row) and the `single` bytes (1 per
+// pin) when asked for.
+__device__ __forceinline__ u64 phi_edge_bytes(int card, int rows, bool single, bool part16) {
+    return 16 + 8 * (u64)card + (12 + (part16 ? 2 : 0)) * (u64)rows + (single ? (u64)card : 0);
 }
 
 // pins(p,e) and pins_in(p,e) of one h-edge per block: sort (rho(pin), is_dst)
@@ -222,10 +239,15 @@ __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict
 __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc,
                                              const i32* __restrict__ pins, const i32* __restrict__ rho,
                                              i32* part, i32* cnt, i32* cnt_in, i32* len, unsigned char* single,
-                                             int npad_max, int skip_le) {
+                                             unsigned short* part16, const i32* __restrict__ elist,
+                                             const u32* __restrict__ ecount, int npad_max, int skip_le,
+                                             unsigned long long* bytes) {
     extern __shared__ u32 sm[];
     __shared__ i32 red[16];
-    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+    u64 acc = 0;
+    const i64 ne = elist ? (i64)*ecount : (i64)E;
+    for (i64 i = blockIdx.x; i < ne; i += gridDim.x) {
+        const i64 e = elist ? (i64)elist[i] : i;
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
         if (card <= skip_le) continue;  // taken by the wave kernel
@@ -233,8 +255,9 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
         u32* keys = sm;
         i32* c_all = (i32*)(sm + npad);
         i32* c_in = c_all + npad;
-        u32* orig = sm + 3 * npad_max;                // unsorted keys (with `single`)
-        i32* rowat = (i32*)(sm + 4 * npad_max);       // row of each sorted position
+        i32* rpart = (i32*)(sm + 3 * npad_max);       // partition of each row
+        u32* orig = sm + 4 * npad_max;                // unsorted keys (with `single`)
+        i32* rowat = (i32*)(sm + 5 * npad_max);       // row of each sorted position
         for (int i = threadIdx.x; i < npad; i += blockDim.x) {
             const u32 k = i < card ? (((u32)rho[pins[a + i]] << 1) | (i >= ns ? 1u : 0u)) : 0xFFFFFFFFu;
             keys[i] = k;
@@ -254,7 +277,10 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
             const i32 x = block_excl_scan((i32)head, red, &tot);
             if (i < card) {
                 const i32 r = rows + x + (head ? 1 : 0) - 1;  // row of element i
-                if (head) part[a + r] = (i32)(kc >> 1);
+                if (head) {
+                    part[a + r] = (i32)(kc >> 1);
+                    rpart[r] = (i32)(kc >> 1);
+                }
                 atomicAdd(&c_all[r], 1);
                 if (kc & 1u) atomicAdd(&c_in[r], 1);
                 if (single) rowat[i] = r;
@@ -265,6 +291,8 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
         for (int r = threadIdx.x; r < rows; r += blockDim.x) {
             cnt[a + r] = c_all[r];
             cnt_in[a + r] = c_in[r];
+            // 16-bit copy for the gains sweep: partition id, top bit where pins(p,e) = 1
+            if (part16) part16[a + r] = (unsigned short)((u32)rpart[r] | (c_all[r] == 1 ? 0x8000u : 0u));
         }
         if (single) {
             for (int i = threadIdx.x; i < card; i += blockDim.x) {
@@ -280,8 +308,10 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
             }
         }
         if (threadIdx.x == 0) len[e] = rows;
+        acc += phi_edge_bytes(card, rows, single != nullptr, part16 != nullptr);
         __syncthreads();
     }
+    if ((bytes != nullptr) & (threadIdx.x == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // ---- one wave per h-edge of at most 256 pins --------------------------------
@@ -342,8 +372,9 @@ __global__ __launch_bounds__(256) void k_contract_edges_wave(i32 E, const i64* _
                                                              const i32* __restrict__ he_nsrc,
                                                              const i32* __restrict__ pins,
                                                              const i32* __restrict__ gamma, i32* tmp, i32* card_out,
-                                                             i32* nsrc_out) {
+                                                             i32* nsrc_out, unsigned long long* bytes) {
     const int wpb = blockDim.x / kWave;
+    u64 acc = 0;
     for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
@@ -356,7 +387,11 @@ __global__ __launch_bounds__(256) void k_contract_edges_wave(i32 E, const i64* _
             card_out[e] = nc;
             nsrc_out[e] = nsv;
         }
+        // offsets and |src| read, pins and their cluster ids read, the
+        // coarse pins and the two counts written
+        acc += 20 + 8 * (u64)card + 4 * (u64)nc;
     }
+    if ((bytes != nullptr) & (lane_id() == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // Phi rows of one h-edge in one wave.  Shared memory per wave: the sorted
@@ -366,12 +401,13 @@ struct PhiWaveShared {
     i32 rowat[kWaveEdgeMax];
     i32 c_all[kWaveEdgeMax];
     i32 c_in[kWaveEdgeMax];
+    i32 rpart[kWaveEdgeMax];  // partition of each row
 };
 
 template <int KPL>
 __device__ __forceinline__ void phi_edge_wave(PhiWaveShared& sh, i64 a, int card, int ns, const i32* __restrict__ pins,
                                               const i32* __restrict__ rho, i32* part, i32* cnt, i32* cnt_in,
-                                              unsigned char* single, i32& rows) {
+                                              unsigned char* single, unsigned short* part16, i32& rows) {
     const int lane = lane_id();
     u32 v[KPL], orig[KPL];
 #pragma unroll
@@ -399,7 +435,10 @@ __device__ __forceinline__ void phi_edge_wave(PhiWaveShared& sh, i64 a, int card
         const int pos = lane * KPL + r;
         if (pos < card) {
             const i32 row = off + pre[r] - 1;
-            if (hd[r]) part[a + row] = (i32)(v[r] >> 1);
+            if (hd[r]) {
+                part[a + row] = (i32)(v[r] >> 1);
+                sh.rpart[row] = (i32)(v[r] >> 1);
+            }
             atomicAdd(&sh.c_all[row], 1);
             if (v[r] & 1u) atomicAdd(&sh.c_in[row], 1);
             sh.keys[pos] = v[r];
@@ -410,6 +449,8 @@ __device__ __forceinline__ void phi_edge_wave(PhiWaveShared& sh, i64 a, int card
     for (int r = lane; r < rows; r += kWave) {
         cnt[a + r] = sh.c_all[r];
         cnt_in[a + r] = sh.c_in[r];
+        // 16-bit copy for the gains sweep: partition id, top bit where pins(p,e) = 1
+        if (part16) part16[a + r] = (unsigned short)((u32)sh.rpart[r] | (sh.c_all[r] == 1 ? 0x8000u : 0u));
     }
     if (single) {
 #pragma unroll
@@ -431,23 +472,31 @@ __device__ __forceinline__ void phi_edge_wave(PhiWaveShared& sh, i64 a, int card
     wave_sync();  // shared memory is reused by the wave's next h-edge
 }
 
+// With elist, only the h-edges it lists (*ecount of them) are rebuilt.
 __global__ __launch_bounds__(256) void k_phi_wave(i32 E, const i64* __restrict__ he_off,
                                                   const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
                                                   const i32* __restrict__ rho, i32* part, i32* cnt, i32* cnt_in,
-                                                  i32* len, unsigned char* single) {
+                                                  i32* len, unsigned char* single, unsigned short* part16,
+                                                  const i32* __restrict__ elist, const u32* __restrict__ ecount,
+                                                  unsigned long long* bytes) {
     __shared__ PhiWaveShared sh[4];
     const int wpb = blockDim.x / kWave;
     PhiWaveShared& my = sh[wave_id()];
-    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
+    u64 acc = 0;
+    const i64 ne = elist ? (i64)*ecount : (i64)E;
+    for (i64 i = (i64)blockIdx.x * wpb + wave_id(); i < ne; i += (i64)gridDim.x * wpb) {
+        const i64 e = elist ? (i64)elist[i] : i;
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
         if (card > kWaveEdgeMax) continue;  // taken by the block kernel
         i32 rows;
-        if (card <= 64) phi_edge_wave<1>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, rows);
-        else if (card <= 128) phi_edge_wave<2>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, rows);
-        else phi_edge_wave<4>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, rows);
+        if (card <= 64) phi_edge_wave<1>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, part16, rows);
+        else if (card <= 128) phi_edge_wave<2>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, part16, rows);
+        else phi_edge_wave<4>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, part16, rows);
         if (lane_id() == 0) len[e] = rows;
+        acc += phi_edge_bytes(card, rows, single != nullptr, part16 != nullptr);
     }
+    if ((bytes != nullptr) & (lane_id() == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 int bits_for(u64 v) {
@@ -508,11 +557,11 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
         // the input's largest h-edge bounds every level (|e'| <= |e|)
         const int npad = next_pow2(c->max_card);
         LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges_wave, grid_for(E, 4, c->num_cu * 16), 256, 0, E, L.he_off(),
-               L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc());
+               L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(), prof_bytes(c, KF_CONTRACT_EDGES));
         if (c->max_card > kWaveEdgeMax)
             LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges, grid_for(E, 1, c->num_cu * 16), 256,
                    sizeof(u32) * npad, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(),
-                   kWaveEdgeMax);
+                   kWaveEdgeMax, prof_bytes(c, KF_CONTRACT_EDGES));
     }
     scan_excl_i32_to_i64(c, card, out.he_off(), E);
     i64 P2 = 0;
@@ -521,7 +570,7 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
     out.b_pins = c->alloc(sizeof(i32) * (size_t)(P2 > 0 ? P2 : 1));
     if (E > 0)
         LAUNCH(c, KF_PACK, k_pack_edges, grid_for(E, 4, c->num_cu * 16), 256, 0, E, L.he_off(),
-               (const i64*)out.he_off(), (const i32*)tmp, out.pins());
+               (const i64*)out.he_off(), (const i32*)tmp, out.pins(), prof_bytes(c, KF_PACK));
 }
 
 // Pin roles of one h-edge per block, staged in shared memory (|e| <= 4,096):
@@ -568,14 +617,15 @@ void retarget_pins(Ctx* c, Level& L, int mode) {
 }
 
 void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32* cnt_in, i32* len,
-               unsigned char* single) {
+               unsigned char* single, unsigned short* part16, const i32* elist, const u32* ecount) {
     if (L.E == 0) return;
     const int npad = next_pow2(c->max_card);
     LAUNCH(c, KF_PHI, k_phi_wave, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(), L.pins(),
-           rho, part, cnt, cnt_in, len, single);
+           rho, part, cnt, cnt_in, len, single, part16, elist, ecount, prof_bytes(c, KF_PHI));
     if (c->max_card > kWaveEdgeMax)
-        LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * (single ? 5 : 3) * npad, L.E,
-               L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, npad, kWaveEdgeMax);
+        LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * (single ? 6 : 4) * npad, L.E,
+               L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, part16, elist, ecount, npad,
+               kWaveEdgeMax, prof_bytes(c, KF_PHI));
 }
 
 }  // namespace hgp

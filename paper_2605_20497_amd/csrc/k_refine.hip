@@ -29,7 +29,7 @@ enum {
     WS_EVK = 119, WS_EVK2 = 120, WS_EVI = 121, WS_EVI2 = 122, WS_EVDS = 123, WS_EVDD = 124, WS_ES = 125,
     WS_ED = 126, WS_SEX = 127, WS_DEX = 128, WS_SEGST = 129, WS_DVQ = 130, WS_CEX = 131, WS_VEX = 132,
     WS_RSTATS = 133, WS_DDS = 134, WS_DDD = 135, WS_MDST_SA = 136, WS_MGAIN_SA = 137, WS_CODE = 138, WS_PHI_PART16 = 139,
-    WS_SINGLE = 140
+    WS_SINGLE = 140, WS_EMARK = 141, WS_ELIST = 142, WS_ECOUNT = 143, WS_ELIST2 = 144
 };
 
 // rstats: [0] active chain rounds flag, [1] links this round, [2] total links,
@@ -54,36 +54,99 @@ __device__ __forceinline__ void row_find(const i32* __restrict__ part, const i32
     ci = hit ? civ : 0;
 }
 
-__global__ void k_part_sizes(i32 N, const i32* __restrict__ rho, const i32* __restrict__ nw, i64* psize) {
-    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x)
-        atomicAdd((unsigned long long*)&psize[rho[n]], (unsigned long long)nw[n]);
-}
-
-// D(p) = |{e : pins_in(p,e) > 0}| from the rows.  With nbins > 0 (all
-// partition ids fit) each block counts in shared memory and adds its nonzero
-// counts once at the end.
-__global__ __launch_bounds__(256) void k_part_inbound(i32 E, const i64* __restrict__ he_off,
-                                                      const i32* __restrict__ part, const i32* __restrict__ cin,
-                                                      const i32* __restrict__ len, i64* pD, int nbins) {
+// size(p) = sum of node weights in p (Sec. II-B).  With nbins > 0 (all
+// partition ids fit) each block sums in shared memory and adds its nonzero
+// totals once at the end, so the device atomics per partition are one per
+// block rather than one per node.
+__global__ __launch_bounds__(256) void k_part_sizes(i32 N, const i32* __restrict__ rho, const i32* __restrict__ nw,
+                                                    i64* psize, int nbins, unsigned long long* bytes) {
     extern __shared__ u32 hist[];
-    const int lane = lane_id();
-    const int wpb = blockDim.x / kWave;
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
-        const i64 a = he_off[e];
-        const i32 L = len[e];
-        for (int r = lane; r < L; r += kWave) {
-            const i32 ci = cin[a + r], p = part[a + r];
-            if (ci > 0) {
-                if (nbins > 0) atomicAdd(&hist[p], 1u);
-                else atomicAdd((unsigned long long*)&pD[p], 1ull);
-            }
-        }
+    u64 nodes = 0;
+    for (i64 n = (i64)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (i64)gridDim.x * blockDim.x) {
+        const i32 p = rho[n], w = nw[n];
+        if (nbins > 0) atomicAdd(&hist[p], (u32)w);
+        else atomicAdd((unsigned long long*)&psize[p], (unsigned long long)w);
+        nodes += 1;
     }
     __syncthreads();
+    u64 parts = 0;
     for (int i = threadIdx.x; i < nbins; i += blockDim.x)
-        if (hist[i]) atomicAdd((unsigned long long*)&pD[i], (unsigned long long)hist[i]);
+        if (hist[i]) {
+            atomicAdd((unsigned long long*)&psize[i], (unsigned long long)hist[i]);
+            parts += 1;
+        }
+    // per node its partition and weight (8); per partition total added (8)
+    const u64 acc = wave_sum(8 * nodes + 8 * parts);
+    if ((bytes != nullptr) & (lane_id() == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+}
+
+// D(p) = |{e : pins_in(p,e) > 0}| from the rows.  Each wave takes 64 h-edges,
+// one per lane, and walks the concatenation of their rows 64 entries at a
+// time (kRowU loads per lane in flight), so every lane is busy whatever the
+// row lengths.  With nbins > 0 (all partition ids fit) each block counts in
+// shared memory and adds its nonzero counts once at the end.
+constexpr int kRowU = 4;
+
+__global__ __launch_bounds__(256) void k_part_inbound(i32 E, const i64* __restrict__ he_off,
+                                                      const i32* __restrict__ part, const i32* __restrict__ cin,
+                                                      const i32* __restrict__ len, i64* pD, int nbins,
+                                                      unsigned long long* bytes) {
+    extern __shared__ u32 hist[];
+    __shared__ i32 s_start[4][kWave];
+    __shared__ i64 s_base[4][kWave];
+    const int lane = lane_id(), wv = wave_id();
+    const int wpb = blockDim.x / kWave;
+    u64 acc = 0;
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (i64 e0 = ((i64)blockIdx.x * wpb + wv) * kWave; e0 < E; e0 += (i64)gridDim.x * wpb * kWave) {
+        const i64 e = e0 + lane;
+        const int in_e = (int)(e < E);
+        const i32 L = in_e ? len[e] : 0;
+        const i64 base = in_e ? he_off[e] : 0;
+        const i32 incl = wave_incl_scan(L);
+        const i32 excl = incl - L;
+        const i32 T = __shfl(incl, kWave - 1, kWave);
+        s_start[wv][lane] = excl;
+        s_base[wv][lane] = base - excl;  // row entry j of this segment is at s_base + j
+        wave_sync();
+        int cur = 0;
+        for (i32 j0 = 0; j0 < T; j0 += kRowU * kWave) {
+            i32 pp[kRowU], cc[kRowU];
+#pragma unroll
+            for (int u = 0; u < kRowU; ++u) {
+                const i32 j = j0 + u * kWave + lane;
+                const int in = (int)(j < T);
+                while ((int)(cur + 1 < kWave) & in) {
+                    if (s_start[wv][cur + 1] > j) break;
+                    ++cur;
+                }
+                const i64 pos = in ? s_base[wv][cur] + j : 0;
+                pp[u] = in ? part[pos] : 0;
+                cc[u] = in ? cin[pos] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowU; ++u)
+                if (cc[u] > 0) {
+                    if (nbins > 0) atomicAdd(&hist[pp[u]], 1u);
+                    else atomicAdd((unsigned long long*)&pD[pp[u]], 1ull);
+                }
+        }
+        wave_sync();  // the table is rewritten by the next batch
+        // per h-edge its offset and lambda (12), per row entry part and cnt_in (8)
+        acc += 12 * (u64)__popcll(__ballot(in_e)) + 8 * (u64)T;
+    }
+    __syncthreads();
+    u64 parts = 0;
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        if (hist[i]) {
+            atomicAdd((unsigned long long*)&pD[i], (unsigned long long)hist[i]);
+            parts += 1;
+        }
+    acc += wave_sum(8 * parts);
+    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // Violated partitions before any move.
@@ -262,12 +325,38 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
 // per-h-edge count load; with a single pass the bins need no range test.
 constexpr i32 kGainsFlagParts = 32767;
 
+// Batches whose rows all have at most kLaneRow entries are swept one row per
+// lane: every lane loads its own row whole (kLaneRow loads in flight), one
+// dependent round for the batch instead of one per G rows.
+constexpr int kLaneRow = 8;
+
+// One row entry of the 16-bit copy: the bin update of its partition, or for
+// the row of p_s the saving (e counts when p_s holds one pin of it).
+template <bool ONE_PASS>
+__device__ __forceinline__ void gains_entry(u32 raw, u32 w, int pass, i32 ps, i32 lo, i32 hi, i64& saving,
+                                            u32* bins) {
+    const i32 p = (i32)(raw & 0x7FFFu);
+    const int in = (int)(raw != 0xFFFFFFFFu);
+    if ((pass == 0) & in & (int)(p == ps)) saving += (raw >> 15) ? (i64)w : 0;
+    const int range = ONE_PASS ? 1 : (int)((u32)(p - lo) < (u32)(hi - lo));
+    if (in & (int)(p != ps) & range) atomicAdd(&bins[p - lo], w);
+}
+
 // Row sweep of one wave batch for k_gains16: rows G at a time, GU coalesced
-// loads per row and lane, so G * GU loads per lane are in flight.
+// loads per row and lane, so G * GU loads per lane are in flight; short rows
+// one per lane.
 template <int G, int GU, bool ONE_PASS>
 __device__ __forceinline__ void gains_group(int nb, int lane, int pass, i32 ps, i32 lo, i32 hi,
                                             const unsigned short* __restrict__ partf, i64 r0, i32 L, i32 w,
                                             i64& saving, u32* bins) {
+    if (wave_max(L) <= kLaneRow) {
+        u32 pp[kLaneRow];
+#pragma unroll
+        for (int u = 0; u < kLaneRow; ++u) pp[u] = u < L ? (u32)partf[r0 + u] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int u = 0; u < kLaneRow; ++u) gains_entry<ONE_PASS>(pp[u], (u32)w, pass, ps, lo, hi, saving, bins);
+        return;
+    }
     for (int i0 = 0; i0 < nb; i0 += G) {
         const unsigned short* rp[G];
         i32 sl[G];
@@ -294,15 +383,7 @@ __device__ __forceinline__ void gains_group(int nb, int lane, int pass, i32 ps, 
 #pragma unroll
             for (int g = 0; g < G; ++g)
 #pragma unroll
-                for (int u = 0; u < GU; ++u) {
-                    const u32 raw = pp[g][u];
-                    const i32 p = (i32)(raw & 0x7FFFu);
-                    const int in = (int)(raw != 0xFFFFFFFFu);
-                    // e's row of p_s: the saving counts e when p_s holds one pin of it
-                    if ((pass == 0) & in & (int)(p == ps)) saving += (raw >> 15) ? (i64)sw[g] : 0;
-                    const int range = ONE_PASS ? 1 : (int)((u32)(p - lo) < (u32)(hi - lo));
-                    if (in & (int)(p != ps) & range) atomicAdd(&bins[p - lo], sw[g]);
-                }
+                for (int u = 0; u < GU; ++u) gains_entry<ONE_PASS>(pp[g][u], sw[g], pass, ps, lo, hi, saving, bins);
         }
     }
 }
@@ -321,6 +402,7 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
     const int npass = ONE_PASS ? 1 : (int)((nparts + R - 1) / R);
     for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
     __syncthreads();
+    u64 visits = 0;  // row entries this wave read (work counter when profiling)
     for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
         const i32 ps = rho[n];
         const i64 a = inc_off[n], b = inc_off[n + 1];
@@ -332,7 +414,6 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
         i32 bp = -1, bp2 = -1;
         i64 r0 = 0;
         i32 L = 0, w = 0;
-        u64 visits = 0;  // row entries this wave read (work counter when profiling)
         const i64 nw_n = nw[n];
         for (int pass = 0; pass < npass; ++pass) {
             const i32 lo = pass * R;
@@ -413,9 +494,10 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
             md[n] = Pp;
             mg[n] = Pp >= 0 ? G : 0;
         }
-        if ((work != nullptr) & (lane == 0)) atomicAdd(work, (unsigned long long)visits);
         __syncthreads();
     }
+    // one device atomic per wave: per node they would all meet on one address
+    if ((work != nullptr) & (lane == 0) & (visits != 0)) atomicAdd(work, (unsigned long long)visits);
 }
 
 // The same moves with one wave per node, for levels whose nodes have few
@@ -437,11 +519,11 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     for (int i = lane; i < R; i += kWave) bins[i] = 0;
     wave_sync();
     const i64 stride = (i64)gridDim.x * nwv;
+    u64 visits = 0;  // row entries this wave read (work counter when profiling)
     for (i64 n = (i64)blockIdx.x * nwv + wv; n < N; n += stride) {
         const i32 ps = rho[n];
         const i64 a = inc_off[n], b = inc_off[n + 1];
         i64 saving = 0, wi = 0;
-        u64 visits = 0;
         const i64 nw_n = nw[n];
         for (i64 kb = a; kb < b; kb += kWave) {
             const int nb = (int)min((i64)kWave, b - kb);
@@ -494,7 +576,33 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
             move_gain[n] = bp >= 0 ? bg : 0;
             move_dst_sa[n] = bp2;
             move_gain_sa[n] = bp2 >= 0 ? bg2 : 0;
-            if (work != nullptr) atomicAdd(work, (unsigned long long)visits);
+        }
+    }
+    if ((work != nullptr) & (lane == 0) & (visits != 0)) atomicAdd(work, (unsigned long long)visits);
+}
+
+// Lists once each h-edge incident to the nodes nodes[0..cnt): one wave per
+// node over its incidence entries; emark[e] takes `stamp` and the lane that
+// changed it appends e (wave-aggregated appends, order immaterial).
+__global__ __launch_bounds__(256) void k_mark_edges(i32 cnt, const i32* __restrict__ nodes,
+                                                    const i64* __restrict__ inc_off, const i32* __restrict__ inc,
+                                                    u32* emark, u32 stamp, i32* elist, u32* ecount) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 j = (i64)blockIdx.x * wpb + wave_id(); j < cnt; j += (i64)gridDim.x * wpb) {
+        const i32 n = nodes[j];
+        const i64 a = inc_off[n], b = inc_off[n + 1];
+        for (i64 k0 = a; k0 < b; k0 += kWave) {
+            const i64 k = k0 + lane;
+            const i32 e = k < b ? inc[k] : -1;
+            u32 old = stamp;
+            if (e >= 0) old = atomicExch(&emark[e], stamp);
+            const int first = (int)(old != stamp);
+            const u64 bal = __ballot(first);
+            u32 base = 0;
+            if (lane == 0 && bal) base = atomicAdd(ecount, (u32)__popcll(bal));
+            base = (u32)__shfl((int)base, 0, kWave);
+            if (first) elist[base + (u32)__popcll(bal & (lane ? (~0ull >> (64 - lane)) : 0ull))] = e;
         }
     }
 }
@@ -1018,13 +1126,22 @@ __device__ __forceinline__ i32 lds_row(const i32* __restrict__ rp, const u32* __
     return hit ? (i32)(v & 0xFFFFu) : 0;
 }
 
+// Algorithmic bytes of one h-edge's in-sequence pass: offsets, |src| and
+// lambda (20), its pins and their sequence positions (8 per pin), its row (12
+// per entry), and per mover its two partitions read and its outcome byte
+// written (9).
+__device__ __forceinline__ u64 inseq_edge_bytes(i64 card, i32 rows, int movers) {
+    return 20 + 8 * (u64)card + 12 * (u64)rows + 9 * (u64)movers;
+}
+
 // All pairs of movers: for h-edges larger than the event-list kernel below
 // takes (skip_le is the largest card it handles; those are skipped here).
 __global__ __launch_bounds__(64) void k_inseq_edges(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
-    const i32* __restrict__ len, unsigned char* code, int cap, i32 skip_le) {
+    const i32* __restrict__ len, unsigned char* code, int cap, i32 skip_le, const i32* __restrict__ elist,
+    const u32* __restrict__ ecount, unsigned long long* bytes) {
     // shared memory: cap movers, then cap row parts and cap packed row counts
     extern __shared__ __align__(16) unsigned char smem_raw[];
     MoverRec* mv = (MoverRec*)smem_raw;
@@ -1032,7 +1149,10 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
     u32* rc = (u32*)(rp + cap);
     const int lane = threadIdx.x;
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+    u64 acc = 0;
+    const i64 ne = elist ? (i64)*ecount : (i64)E;
+    for (i64 ie = blockIdx.x; ie < ne; ie += gridDim.x) {
+        const i64 e = elist ? (i64)elist[ie] : ie;
         const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
         if (b - a <= (i64)skip_le) continue;
         const i32 L = len[e];
@@ -1081,8 +1201,10 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
                              ((u32)(di & (int)(cid + xid == 0)) << 3);
             code[a + (me.slot >> 1)] = (unsigned char)bits;
         }
+        acc += inseq_edge_bytes(b - a, L, k);
         __syncthreads();
     }
+    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // Same outcome bytes with per-part event lists instead of all pairs.  The
@@ -1125,9 +1247,11 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
-    const i32* __restrict__ len, unsigned char* code, int cap, int tbits) {
+    const i32* __restrict__ len, unsigned char* code, int cap, int tbits, const i32* __restrict__ elist,
+    const u32* __restrict__ ecount, unsigned long long* bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = 1 << tbits;
+    u64 acc_bytes = 0;
     i32* mq = (i32*)smem_raw;          // cap
     u32* mpk = (u32*)(mq + cap);       // cap
     i32* tkey = (i32*)(mpk + cap);     // T
@@ -1136,7 +1260,9 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     i32* ev = (i32*)(tcnt + T);        // 2 * cap
     const int lane = threadIdx.x;
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+    const i64 ne = elist ? (i64)*ecount : (i64)E;
+    for (i64 ie = blockIdx.x; ie < ne; ie += gridDim.x) {
+        const i64 e = elist ? (i64)elist[ie] : ie;
         const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
         if (b - a > (i64)cap) continue;
         const i32 L = len[e];
@@ -1238,8 +1364,10 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
                              ((u32)(di & (int)(cid == 0)) << 3);
             code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
         }
+        acc_bytes += inseq_edge_bytes(b - a, L, k);
         __syncthreads();
     }
+    if ((bytes != nullptr) & (lane == 0) & (acc_bytes != 0)) atomicAdd(bytes, (unsigned long long)acc_bytes);
 }
 
 // In-sequence gains, mover side: one wave per sequence position q sums the
@@ -1248,9 +1376,10 @@ __global__ __launch_bounds__(256) void k_inseq_movers(i32 M, const i32* __restri
                                                       const i64* __restrict__ inc_off, const i32* __restrict__ inc,
                                                       const i32* __restrict__ inc_pos, const i32* __restrict__ hw,
                                                       const unsigned char* __restrict__ code, i64* gseq, i32* dds,
-                                                      i32* ddd) {
+                                                      i32* ddd, unsigned long long* bytes) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
+    u64 acc = 0;
     for (i64 q = (i64)blockIdx.x * wpb + wave_id(); q < M; q += (i64)gridDim.x * wpb) {
         const i32 n = seqn[q];
         const i64 s = inc_off[n], t = inc_off[n + 1];
@@ -1280,7 +1409,11 @@ __global__ __launch_bounds__(256) void k_inseq_movers(i32 M, const i32* __restri
             dds[q] = -ls;
             ddd[q] = gd;
         }
+        // the mover's id and offsets (20), per incidence entry its h-edge,
+        // pin slot, weight and outcome byte (13), the three results (16)
+        acc += 36 + 13 * (u64)(t - s);
     }
+    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // Two events per mover: (p_s, q) and (p_d, q) with their size and D deltas.
@@ -1437,10 +1570,25 @@ struct PhiBufs {
     unsigned short* part16;  // flagged 16-bit copy of part when nparts <= kGainsFlagParts, else null
 };
 
-// 16-bit row copy for k_gains16: partition id, top bit set where pins(p,e) = 1.
-__global__ void k_narrow16(i64 P, const i32* __restrict__ v, const i32* __restrict__ cnt, unsigned short* v16) {
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
-        v16[i] = (unsigned short)((u32)v[i] | (cnt[i] == 1 ? 0x8000u : 0u));
+
+// Whether listing the h-edges of `movers` nodes beats sweeping all h-edges.
+// The list costs one device atomic per incidence entry of a mover (about
+// movers * P / N), the sweep reads every pin and its sequence position (2P);
+// the list is taken while the movers are under a quarter of the nodes, where
+// it also spares the per-h-edge work of every h-edge without a mover.
+bool few_touched(const Level& L, i64 movers) { return L.N > 0 && movers * 4 < (i64)L.N; }
+
+// Partition sizes and D(p) of rho from its Phi rows; psize and pD start at 0.
+void part_stats(Ctx* c, const Level& L, const i32* rho, i32 nparts, const i32* part, const i32* cin, const i32* len,
+                i64* psize, i64* pD) {
+    const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
+    // blocks resident at once with this much shared memory, 8 per CU at most
+    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (sizeof(u32) * nbins + 4096))));
+    LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * per_cu), 256, sizeof(u32) * nbins, L.N,
+           rho, L.nw(), psize, nbins, prof_bytes(c, KF_PART_STATS));
+    if (L.E > 0)
+        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 256, c->num_cu * per_cu), 256, sizeof(u32) * nbins,
+               L.E, L.he_off(), part, cin, len, pD, nbins, prof_bytes(c, KF_PART_STATS));
 }
 
 PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
@@ -1455,7 +1603,12 @@ PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
     return f;
 }
 
-PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsigned char* single = nullptr) {
+// Phi rows (with their 16-bit copy when the partition ids fit), partition
+// sizes and D(p).  With elist, only the listed h-edges' rows are rebuilt: the
+// others are those of the previous repetition, whose moves left them as they
+// were.
+PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsigned char* single = nullptr,
+                      const i32* elist = nullptr, const u32* ecount = nullptr) {
     PhiBufs f;
     f.part = wsp<i32>(c, WS_PHI_PART, (size_t)L.P + 1);
     f.cnt = wsp<i32>(c, WS_PHI_CNT, (size_t)L.P + 1);
@@ -1463,37 +1616,52 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsign
     f.len = wsp<i32>(c, WS_PHI_LEN, (size_t)L.E + 1);
     f.psize = wsp<i64>(c, WS_PSIZE, nparts);
     f.pD = wsp<i64>(c, WS_PD, nparts);
-    build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len, single);
-    f.part16 = nullptr;
-    if (nparts <= kGainsFlagParts && L.P > 0) {
-        f.part16 = wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1);
-        LAUNCH(c, KF_PHI, k_narrow16, grid_for(L.P, 256, c->num_cu * 8), 256, 0, L.P, (const i32*)f.part,
-               (const i32*)f.cnt, f.part16);
-    }
+    f.part16 = (nparts <= kGainsFlagParts && L.P > 0) ? wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1)
+                                                       : nullptr;
+    build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len, single, f.part16, elist, ecount);
     fill_many(c, {{f.psize, 2 * (i64)nparts, 0u}, {f.pD, 2 * (i64)nparts, 0u}});
-    LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), f.psize);
-    if (L.E > 0) {
-        const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
-        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 4, c->num_cu * 2), 256, sizeof(u32) * nbins, L.E,
-               L.he_off(), f.part, f.cin, f.len, f.pD, nbins);
-    }
+    part_stats(c, L, rho, nparts, f.part, f.cin, f.len, f.psize, f.pD);
     return f;
 }
 
 }  // namespace
 
 RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int theta, RepTrace* trace,
-                   bool reuse) {
+                   bool reuse, i64 incr_k) {
     RepInfo info;
     const i32 N = L.N;
     const int nbN = grid_for(N, 256, c->num_cu * 8);
+    // h-edge marks of this repetition: stamp 1 lists the h-edges whose rows the
+    // previous repetition's applied moves changed, stamp 2 those holding a
+    // mover of this one.
+    u32* emark = wsp<u32>(c, WS_EMARK, (size_t)(L.E > 0 ? L.E : 1));
+    u32* ecount = wsp<u32>(c, WS_ECOUNT, 2);
+    i32* elist = wsp<i32>(c, WS_ELIST, (size_t)(L.E > 0 ? L.E : 1));
+    bool marks_clear = false;  // emark and the counts zeroed in this repetition
+    auto clear_marks = [&]() {
+        if (!marks_clear) fill_many(c, {{emark, (i64)L.E, 0u}, {ecount, 2, 0u}});
+        marks_clear = true;
+    };
+    // With incr_k > 0, the previous repetition on this level applied the first
+    // incr_k moves of its sequence (still in the sequence buffer): only the
+    // rows of their h-edges changed.  Listing them costs one device atomic per
+    // incidence entry of a mover, so the list is used only while those entries
+    // (about incr_k * P / N) stay well below the h-edges swept without it.
+    const bool incremental = !reuse && incr_k > 0 && L.E > 0 && few_touched(L, incr_k);
+    if (incremental) {
+        clear_marks();
+        const i32* prev_seq = wsp<i32>(c, WS_SEQN, (size_t)incr_k);
+        LAUNCH(c, KF_PHI, k_mark_edges, grid_for(incr_k, 4, c->num_cu * 16), 256, 0, (i32)incr_k, prev_seq,
+               L.inc_off(), L.inc(), emark, 1u, elist, ecount);
+    }
     // With `reuse`, rho is unchanged since the previous repetition (it applied
     // nothing): its pins rows, sizes, D and both move variants still hold.
     // Small levels take the moves from a dense MFMA product, which needs one
     // byte per pin slot from the Phi kernel (pins(rho(m), e) = 1).
     const bool dense_gains = !reuse && use_dense_gains(c, L, nparts);
     unsigned char* single = dense_gains ? wsp<unsigned char>(c, WS_SINGLE, (size_t)(L.P > 0 ? L.P : 1)) : nullptr;
-    PhiBufs f = reuse ? phi_bufs(c, L, nparts) : phi_and_parts(c, L, rho, nparts, single);
+    PhiBufs f = reuse ? phi_bufs(c, L, nparts)
+                      : phi_and_parts(c, L, rho, nparts, single, incremental ? elist : nullptr, ecount);
     unsigned long long* rs = wsp<unsigned long long>(c, WS_RSTATS, 8);
     HIPC(hipMemsetAsync(rs, 0, 8 * sizeof(u64), c->stream));
     LAUNCH(c, KF_PART_STATS, k_initial_violations, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, f.psize,
@@ -1699,6 +1867,15 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     i32* ddd = wsp<i32>(c, WS_DDD, M);
     unsigned char* code = wsp<unsigned char>(c, WS_CODE, (size_t)(L.P > 0 ? L.P : 1));
     if (L.E > 0) {
+        // Only h-edges holding a mover have in-sequence effects: when the
+        // movers are few, list those once each (stamp 2) and sweep only them.
+        const bool listed = few_touched(L, M);
+        i32* elist2 = listed ? wsp<i32>(c, WS_ELIST2, (size_t)L.E) : nullptr;
+        if (listed) {
+            clear_marks();
+            LAUNCH(c, KF_INSEQ, k_mark_edges, grid_for(M, 4, c->num_cu * 16), 256, 0, (i32)M, (const i32*)seqn,
+                   L.inc_off(), L.inc(), emark, 2u, elist2, ecount + 1);
+        }
         // Event lists for h-edges of up to kInseqListMax pins, all pairs beyond.
         const int cap = std::max(1, c->max_card);
         const int capl = std::min(cap, kInseqListMax);
@@ -1707,14 +1884,15 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const size_t lds_l = (size_t)16 * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
         LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, lds_l, L.E,
                (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl,
-               tbits);
+               tbits, (const i32*)elist2, (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
         if (cap > capl)
             LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave,
                    (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn,
-                   rho, mdst, f.part, f.cnt, f.cin, f.len, code, cap, (i32)capl);
+                   rho, mdst, f.part, f.cnt, f.cin, f.len, code, cap, (i32)capl, (const i32*)elist2,
+                   (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
     }
     LAUNCH(c, KF_INSEQ, k_inseq_movers, grid_for(M, 4, c->num_cu * 16), 256, 0, (i32)M, seqn, L.inc_off(), L.inc(),
-           L.inc_pos(), c->hw(), code, gseq, dds, ddd);
+           L.inc_pos(), c->hw(), code, gseq, dds, ddd, prof_bytes(c, KF_INSEQ));
     LAUNCH(c, KF_EVENTS, k_events_build, nbM, 256, 0, (i32)M, seqn, seqs, seqd, L.nw(), dds, ddd, evk, evds, evdd);
     iota_i32(c, evi, M2);
     sort_pairs_u32(c, evk, evk2, evi, evi2, M2, bits_for((u64)nparts));
@@ -1870,13 +2048,9 @@ void evaluate_noalloc(Ctx* c, const Level& L, const i32* rho, i32 nparts, hgp_ev
     read_back(c, res + 6, &bad, 1, 8);
     if (bad != 0) fail(HGP_E_INVALID, std::to_string(bad) + " entries of rho outside [0, n_parts)");
     build_phi(c, L, rho, part, cnt, cin, len, nullptr);
-    LAUNCH(c, KF_PART_STATS, k_part_sizes, grid_for(L.N, 256, c->num_cu * 8), 256, 0, L.N, rho, L.nw(), psize);
-    if (L.E > 0) {
-        const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
-        LAUNCH(c, KF_PART_STATS, k_part_inbound, grid_for(L.E, 4, c->num_cu * 2), 256, sizeof(u32) * nbins, L.E,
-               L.he_off(), (const i32*)part, (const i32*)cin, (const i32*)len, pD, nbins);
+    part_stats(c, L, rho, nparts, part, cin, len, psize, pD);
+    if (L.E > 0)
         LAUNCH(c, KF_EVAL, k_conn, grid_for(L.E, 256, c->num_cu * 4), 256, 0, L.E, (const i32*)len, c->hw(), res);
-    }
     LAUNCH(c, KF_EVAL, k_part_eval, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, (const i64*)psize,
            (const i64*)pD, c->omega, c->delta, res);
     i64 v[6];

@@ -349,6 +349,31 @@ def test_no_chains_ablation():
         g.close()
 
 
+def test_greedy_matching_ablation():
+    # greedy matching rounds against the oracle's, every level's matching and
+    # the final partition; the 20,000-node case takes the per-depth kernels,
+    # the others the single-workgroup matching
+    from paper_2605_20497_amd import Partitioner
+    cases = ((W.random_snn(1024, 15, 3), 64, 256), (W.random_snn(4096, 95, 6), 128, 1024),
+             (W.random_snn(20000, 11, 8), 256, 1024))
+    for hg, omega, delta in cases:
+        print("case greedy N", hg.n_nodes, flush=True)
+        res = oracle.Graph(hg).partition(omega, delta, Pi=4, theta=16, seed=0, greedy=True)
+        g = Partitioner(greedy_matching=True)
+        g.load(hg)
+        g.hgp_set_limits(omega, delta, 0)
+        assert g.hgp_coarsen() == res.nlevels
+        for lv in range(res.ncoarsened):
+            oc, os_, om = res.proposal(lv)
+            gc, gs, gm = g.hgp_get_proposal(lv)
+            assert np.array_equal(gm, om), lv
+        g.hgp_refine()
+        rho, _ = g.hgp_get_partition()
+        assert np.array_equal(rho, res.rho(0))
+        assert g.hgp_evaluate()["conn"] == res.conn
+        g.close()
+
+
 def test_dense_work_counters():
     # the multiply-adds the library reports for the two dense products equal
     # the padded-size formulas: (planes + 1) x 128^2 x tile pairs x Epad for
