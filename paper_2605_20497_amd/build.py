@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhgp.so")
-SOURCES = ["k_prim.hip", "k_graph.hip", "k_coarsen.hip", "k_refine.hip", "k_dense.hip", "hgp_api.cpp", "hgp_batch.cpp"]
+SOURCES = ["k_prim.hip", "k_sort.hip", "k_graph.hip", "k_coarsen.hip", "k_refine.hip", "k_dense.hip", "hgp_api.cpp", "hgp_batch.cpp"]
 ARCH = os.environ.get("HGP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -1,7 +1,5 @@
-// Parallel primitives: prefix sums, fills, gathers, and the stable radix sort
-// used for the incidence transpose, the moves sort, the chain ranking and the
-// event sort (Sec. VI-C, VI-D).
-#include <rocprim/device/device_radix_sort.hpp>
+// Parallel primitives: prefix sums, fills and gathers.  The stable radix sort
+// is in k_sort.hip.
 
 #include "dev_util.h"
 
@@ -13,7 +11,7 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
-enum { WS_SORT_TMP = 0, WS_SCAN_PART = 1 };
+enum { WS_SCAN_PART = 1 };
 
 template <typename Tin, typename Tacc>
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const Tin* __restrict__ in, i64 n, Tacc* part) {
@@ -138,39 +136,6 @@ void scan_impl(Ctx* c, const Tin* in, Tout* out, i64 n) {
 void scan_excl_i64(Ctx* c, const i64* in, i64* out, i64 n) { scan_impl<i64, i64, i64>(c, in, out, n); }
 void scan_excl_i32_to_i64(Ctx* c, const i32* in, i64* out, i64 n) { scan_impl<i32, i64, i64>(c, in, out, n); }
 void scan_excl_i32(Ctx* c, const i32* in, i32* out, i64 n) { scan_impl<i32, i64, i32>(c, in, out, n); }
-
-void sort_pairs_u32(Ctx* c, const u32* kin, u32* kout, const i32* vin, i32* vout, i64 n, int bits) {
-    if (n <= 0) return;
-    if (bits < 1) bits = 1;
-    size_t tmp = 0;
-    HIPC(rocprim::radix_sort_pairs(nullptr, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
-    void* t = c->ws_get(WS_SORT_TMP, tmp + 256);
-    prof_begin(c, KF_SORT);
-    HIPC(rocprim::radix_sort_pairs(t, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
-    prof_end(c, KF_SORT);
-}
-
-void sort_pairs_u32_u64(Ctx* c, const u32* kin, u32* kout, const u64* vin, u64* vout, i64 n, int bits) {
-    if (n <= 0) return;
-    if (bits < 1) bits = 1;
-    size_t tmp = 0;
-    HIPC(rocprim::radix_sort_pairs(nullptr, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
-    void* t = c->ws_get(WS_SORT_TMP, tmp + 256);
-    prof_begin(c, KF_SORT);
-    HIPC(rocprim::radix_sort_pairs(t, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
-    prof_end(c, KF_SORT);
-}
-
-void sort_pairs_u64(Ctx* c, const u64* kin, u64* kout, const i32* vin, i32* vout, i64 n, int bits) {
-    if (n <= 0) return;
-    if (bits < 1) bits = 1;
-    size_t tmp = 0;
-    HIPC(rocprim::radix_sort_pairs(nullptr, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
-    void* t = c->ws_get(WS_SORT_TMP, tmp + 256);
-    prof_begin(c, KF_SORT);
-    HIPC(rocprim::radix_sort_pairs(t, tmp, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)bits, c->stream));
-    prof_end(c, KF_SORT);
-}
 
 void fill_i32(Ctx* c, i32* p, i32 v, i64 n) {
     if (n > 0) LAUNCH(c, KF_MISC, k_fill<i32>, grid_for(n, 256, 4096), 256, 0, p, v, n);
