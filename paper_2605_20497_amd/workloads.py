@@ -360,45 +360,62 @@ def random_small(n: int, e: int, max_card: int, seed: int, max_src: int = 1,
 # Job stream for batched and served runs
 # ---------------------------------------------------------------------------
 
-def job_stream(n_jobs: int = 256, min_nodes: int = 2048, max_nodes: int = 262144, seed: int = 0,
-               rate: float = 0.0, arrival_seed: int = 12345):
-    """Jobs of log-uniform size in [min_nodes, max_nodes] from the five workload
-    families (|e| = 32 and 192 random SNN, layered, conv, netlist), job i seeded
-    with seed + i.  Omega_i = min(family Omega, 2^floor(log2(N_i / 16))),
-    Delta_i = 4 Omega_i (random) or 16 Omega_i (layered, conv); netlist jobs are
-    k-way with k_i = 2^clamp(round(log2(N_i / 8000)), 1, 6).  With rate > 0,
-    arrival times follow a Poisson process of that many jobs per second.
-    Returns (jobs, arrivals)."""
+def job_specs(n_jobs: int = 256, min_nodes: int = 2048, max_nodes: int = 262144, seed: int = 0):
+    """(sizes, kinds) of the job stream: log-uniform node counts in
+    [min_nodes, max_nodes] and a family index 0..4 per job."""
     rng = np.random.default_rng(seed)
     sizes = np.floor(np.exp(rng.uniform(np.log(min_nodes), np.log(max_nodes), size=n_jobs))).astype(np.int64)
     kinds = rng.integers(0, 5, size=n_jobs)
-    jobs = []
-    for i in range(n_jobs):
-        n = int(sizes[i])
-        kind = int(kinds[i])
-        s = seed + i
-        pow_om = 1 << max(1, int(np.floor(np.log2(max(n // 16, 2)))))
-        if kind == 0:
-            om = min(1 << 8, pow_om)
-            hg = random_snn(n, 31, s, omega=om, delta=4 * om, name="job%d-rand-e32" % i)
-        elif kind == 1:
-            om = min(1 << 10, pow_om)
-            hg = random_snn(n, min(191, n - 1), s, omega=om, delta=4 * om, name="job%d-rand-e192" % i)
-        elif kind == 2:
-            width = max(64, n // 8)
-            window = max(16, min(2048, width // 4))
-            om = min(1 << 12, pow_om)
-            hg = layered_snn(8, width, min(255, window), window, 0.8, s, omega=om, delta=16 * om,
-                             name="job%d-layered" % i)
-        elif kind == 3:
-            hw = max(4, int(round(np.sqrt(n / (7 * 32)))))
-            om = min(1 << 12, pow_om)
-            hg = conv_snn(7, hw, 32, 82.0, s, omega=om, delta=16 * om, name="job%d-conv" % i)
-        else:
-            k = 1 << int(np.clip(round(np.log2(n / 8000.0)), 1, 6))
-            hg = netlist(n, int(1.1 * n), 2, min(2000, n // 2), 2.827, min(2048, n // 4), 0.9, 8, s, k=k,
-                         name="job%d-netlist" % i)
-        jobs.append(hg)
+    return sizes, kinds
+
+
+def make_job(i: int, sizes, kinds, seed: int = 0) -> Hypergraph:
+    """Job i of a stream: family kinds[i] (|e| = 32 and 192 random SNN,
+    layered, conv, netlist) on sizes[i] nodes, seeded with seed + i.
+    Omega_i = min(family Omega, 2^floor(log2(N_i / 16))), Delta_i = 4 Omega_i
+    (random) or 16 Omega_i (layered, conv); netlist jobs are k-way with
+    k_i = 2^clamp(round(log2(N_i / 8000)), 1, 6)."""
+    n = int(sizes[i])
+    kind = int(kinds[i])
+    s = seed + i
+    pow_om = 1 << max(1, int(np.floor(np.log2(max(n // 16, 2)))))
+    if kind == 0:
+        om = min(1 << 8, pow_om)
+        return random_snn(n, 31, s, omega=om, delta=4 * om, name="job%d-rand-e32" % i)
+    if kind == 1:
+        om = min(1 << 10, pow_om)
+        return random_snn(n, min(191, n - 1), s, omega=om, delta=4 * om, name="job%d-rand-e192" % i)
+    if kind == 2:
+        width = max(64, n // 8)
+        window = max(16, min(2048, width // 4))
+        om = min(1 << 12, pow_om)
+        return layered_snn(8, width, min(255, window), window, 0.8, s, omega=om, delta=16 * om,
+                           name="job%d-layered" % i)
+    if kind == 3:
+        hw = max(4, int(round(np.sqrt(n / (7 * 32)))))
+        om = min(1 << 12, pow_om)
+        return conv_snn(7, hw, 32, 82.0, s, omega=om, delta=16 * om, name="job%d-conv" % i, threads=1)
+    k = 1 << int(np.clip(round(np.log2(n / 8000.0)), 1, 6))
+    return netlist(n, int(1.1 * n), 2, min(2000, n // 2), 2.827, min(2048, n // 4), 0.9, 8, s, k=k,
+                   name="job%d-netlist" % i)
+
+
+def job_stream(n_jobs: int = 256, min_nodes: int = 2048, max_nodes: int = 262144, seed: int = 0,
+               rate: float = 0.0, arrival_seed: int = 12345):
+    """The batched/served workload: n_jobs jobs of job_specs / make_job.  With
+    rate > 0, arrival times follow a Poisson process of that many jobs per
+    second.  Returns (jobs, arrivals)."""
+    import concurrent.futures as cf
+    import os
+
+    sizes, kinds = job_specs(n_jobs, min_nodes, max_nodes, seed)
+    # every job draws from its own seed, so building them on worker threads
+    # (largest first) gives the same jobs as building them in order
+    order = sorted(range(n_jobs), key=lambda i: -int(sizes[i]))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(threads) as ex:
+        built = dict(zip(order, ex.map(lambda i: make_job(i, sizes, kinds, seed), order)))
+    jobs = [built[i] for i in range(n_jobs)]
     if rate > 0:
         arng = np.random.default_rng(arrival_seed)
         arrivals = np.cumsum(arng.exponential(1.0 / rate, size=n_jobs))
