@@ -1,16 +1,21 @@
 """Benchmark of the partitioner's hot path on one MI355X.
 
-One step = one complete partitioning of the synthetic 65,536-node random
-SNN-shaped hypergraph (one h-edge per node: source + 191 distinct uniform
-destinations, 12,582,912 pins, Omega = 2^10, Delta = 2^12): load from
-HBM-resident tensors (on-device validation and incidence build), every
-coarsening level, and refinement of every level with Theta = 16 repetitions.
+One step = one complete partitioning of the synthetic conv-shaped SNN
+hypergraph, the largest single-GPU workload: 7 layers of 176 x 176 x 32
+neurons (6,938,624 nodes), one h-edge per neuron (source + Poisson(82)
+destinations in the 3 x 3 spatial window of the next layer, 575,857,446 pins),
+Omega = 2^12, Delta = 2^16.  The step loads from HBM-resident tensors
+(on-device validation and incidence build), coarsens every level and refines
+every level with Theta = 16 repetitions.  --workload selects another of the
+five workloads.
 
 Prints one JSON line: pins/s of the whole step (input pins / step time), the
-per-level pins/s, the rooflines of the largest kernels from HIP events
-over the timed steps (`roofline` is the one that takes the most time), the
-per-family breakdown, the batched job-stream leg, and the serial oracle's rate
-on a bounded sample of the same workload family as the CPU baseline.
+rooflines of the largest kernels from HIP events over the timed steps
+(`roofline` is the one that takes the most time), the per-family breakdown and
+per-level figures (pins/s, and GB/s and HBM fraction of the streaming sweeps
+from their device-counted algorithmic bytes) from one extra profiled step, the
+batched job-stream leg, and the serial oracle's rate on a bounded sample of
+the same workload family as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -24,9 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# The proposal kernel's histogram updates are 32-bit integer adds executed by
-# the LDS: at most one per bank per clock, 32 banks per CU, 256 CUs at 2.4 GHz.
-LDS_UPDATE_PEAK_GOPS = 256 * 32 * 2.4
+# The histogram updates of the proposal and gains sweeps are 32-bit LDS atomic
+# adds.  A CU's LDS takes one 64-lane atomic instruction every 4 clocks (16
+# lane updates per clock; a conflict-free probe measured 15.2), so 256 CUs at
+# 2.4 GHz give 16 * 256 * 2.4 G = 9,830 G updates/s.
+LDS_UPDATE_PEAK_GOPS = 16 * 256 * 2.4
 # Dense int8 MFMA peak of MI355X (no sparsity), in TOP/s.
 INT8_PEAK_TOPS = 5000.0
 
@@ -54,18 +61,20 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rand-64k-e192")
+    ap.add_argument("--workload", default="conv-6.9m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
-    ap.add_argument("--cpu-nodes", type=int, default=4096)
+    ap.add_argument("--cpu-hw", type=int, default=16,
+                    help="grid side of the CPU baseline's conv-shaped sample (7 layers x hw x hw x 32)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain job stream leg")
-    ap.add_argument("--batch-jobs", type=int, default=64)
-    ap.add_argument("--batch-workers", type=int, default=8)
-    ap.add_argument("--batch-max-nodes", type=int, default=32768)
+    ap.add_argument("--batch-jobs", type=int, default=256)
+    ap.add_argument("--batch-workers", type=int, default=0,
+                    help="concurrent contexts of the batched leg (0 = the autotuned count, else 8)")
+    ap.add_argument("--batch-max-nodes", type=int, default=262144)
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the step: Pi and Theta sweeps and the chain-free ablation on --sweep-workload")
-    ap.add_argument("--sweep-workload", default="rand-64k-e192")
+    ap.add_argument("--sweep-workload", default="layered-256k-e256")
     return ap.parse_args()
 
 
@@ -94,35 +103,85 @@ def algorithmic_bytes(kernel, levels, pi):
     return tot
 
 
-def cpu_baseline(args):
-    """Serial oracle (one host core), full coarsen + refine on a bounded
-    sample of the workload family: a random SNN-shaped hypergraph with the
-    same h-edge size 192 and the same Delta, on cpu_nodes nodes, Omega scaled
-    by the node ratio.  Rate = input pins / wall time."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, hg_full):
+    """Serial oracle (one pinned host core), full coarsen + refine on a bounded
+    sample of the timed workload's family: the conv-shaped generator on a
+    smaller grid (7 layers of cpu_hw x cpu_hw x 32, the same fan-out and
+    Delta, Omega scaled by the node ratio with a floor of 64), or for the
+    random workload a 4,096-node random hypergraph of the same h-edge size.
+    Rate = input pins / wall time.  Beside it: the oracle's own time on the
+    full workload, recorded when the stored digests were written."""
     import oracle
     from paper_2605_20497_amd import workloads as W
-    n = args.cpu_nodes
-    omega = max(16, (1 << 10) * n // 65536)
-    hg = W.random_snn(n, 191, seed=0)
+    core = None
+    if hasattr(os, "sched_setaffinity"):
+        avail = sorted(os.sched_getaffinity(0))
+        core = avail[2] if len(avail) > 2 else avail[0]
+        os.sched_setaffinity(0, {core})
+    if args.workload.startswith("rand-64k"):
+        n = 4096
+        omega = max(64, hg_full.omega * n // hg_full.n_nodes)
+        hg = W.random_snn(n, 191, seed=0, omega=omega, delta=hg_full.delta)
+        sample = "rand-4096-e192 (4,096 nodes, h-edges of 192 pins)"
+    else:
+        hw = args.cpu_hw
+        n = 7 * hw * hw * 32
+        omega = max(64, (1 << 12) * n // 6938624)
+        hg = W.conv_snn(7, hw, 32, 82.0, seed=0, omega=omega, delta=1 << 16)
+        sample = "conv-shaped 7 x %d x %d x 32 (%d nodes)" % (hw, hw, n)
     g = oracle.Graph(hg)
     t0 = time.perf_counter()
-    res = g.partition(omega, 1 << 12)
+    res = g.partition(hg.omega, hg.delta)
     dt = time.perf_counter() - t0
-    return {"value": hg.n_pins / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": "rand-%d-e192 (%d nodes, %d pins, Omega=%d, Delta=4096), full coarsen+refine, %d levels, "
-                      "%.1f s on one host core" % (n, n, hg.n_pins, omega, res.nlevels, dt)}
+    out = {"value": hg.n_pins / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
+           "sample": "%s, %d pins, Omega=%d, Delta=%d, full coarsen+refine, %d levels, %.1f s"
+                     % (sample, hg.n_pins, hg.omega, hg.delta, res.nlevels, dt),
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "pinned_core": core,
+           "threads_used": 1}
+    gold = os.path.join(ROOT, "tests", "golden", args.workload + ".json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            sec = json.load(f).get("oracle_seconds")
+        if sec:
+            out["full_workload_oracle"] = {
+                "seconds": sec, "pins_per_s": round(hg_full.n_pins / sec, 1),
+                "note": "one core of the build container when the stored digests were written"}
+    return out
+
+
+# Families whose kernels count their own algorithmic bytes when profiled.
+STREAM_FAMILIES = ("phi", "part_stats", "inseq", "contract_edges", "pack")
 
 
 def batched_leg(args):
-    """Job stream (the five workload families, log-uniform 2,048 to
-    batch_max_nodes nodes): the plain one-at-a-time rate with every job
-    waiting from the start, then Poisson arrivals at 1.5x that rate served
-    by one worker (plain) and by batch_workers concurrent workers (batched).
-    Latency = arrival to partition on the host."""
+    """Job stream (config 5: the five workload families, log-uniform 2,048 to
+    batch_max_nodes nodes, job i seeded with i): the plain one-at-a-time rate
+    with every job waiting from the start, the batched rate the same way, then
+    Poisson arrivals (seed 12,345) at 1.5x the plain rate served by one worker
+    (plain) and by batch_workers concurrent workers (batched).  Latency =
+    arrival to partition on the host.  Every job's partition is compared
+    between the plain and batched runs, and with the oracle's digest where
+    tests/golden holds one for this stream."""
+    import hashlib
+
     import numpy as np
     import paper_2605_20497_amd as pkg
     from paper_2605_20497_amd import workloads as W
+    t0 = time.perf_counter()
     jobs, _ = W.job_stream(args.batch_jobs, 2048, args.batch_max_nodes, seed=0)
+    gen_s = time.perf_counter() - t0
+    print("bench: %d jobs generated in %.1f s" % (len(jobs), gen_s), file=sys.stderr, flush=True)
     pkg.hgp_run_jobs(jobs[:4], workers=1)  # warm-up
     closed = pkg.hgp_run_jobs(jobs, workers=1)
     span = max(r["end_s"] for r in closed)
@@ -137,26 +196,52 @@ def batched_leg(args):
                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)}
 
+    if args.batch_workers <= 0:
+        from paper_2605_20497_amd import autotune
+        args.batch_workers = autotune.tuned_options("job-stream")["workers"]
     closed_b = pkg.hgp_run_jobs(jobs, workers=args.batch_workers)
     span_b = max(r["end_s"] for r in closed_b)
+    print("bench: closed-loop runs done", file=sys.stderr, flush=True)
     plain = pkg.hgp_run_jobs(jobs, workers=1, arrivals=arrivals)
     batched = pkg.hgp_run_jobs(jobs, workers=args.batch_workers, arrivals=arrivals)
-    ok = all(p["status"] == 0 and b["status"] == 0 and np.array_equal(p["rho"], b["rho"])
-             for p, b in zip(plain, batched))
-    return {"jobs": len(jobs), "pins": int(sum(j.n_pins for j in jobs)),
-            "sizes": "2048-%d nodes, random e32/e192, layered, conv, netlist" % args.batch_max_nodes,
-            "plain_closed_jobs_per_s": round(len(jobs) / span, 2),
-            "batched_closed_jobs_per_s": round(len(jobs) / span_b, 2), "arrival_rate_per_s": round(rate, 2),
-            "plain": summary(plain, 1), "batched": summary(batched, args.batch_workers),
-            "bit_exact_vs_plain": bool(ok)}
+    runs = {"plain_closed": closed, "batched_closed": closed_b, "plain": plain, "batched": batched}
+    status = {k: {str(s): int(c) for s, c in zip(*np.unique([r["status"] for r in v], return_counts=True))}
+              for k, v in runs.items()}
+    differ = [jobs[i].name for i in range(len(jobs))
+              if not all(runs[k][i]["status"] == 0 and np.array_equal(closed[i]["rho"], runs[k][i]["rho"])
+                         for k in runs)]
+    ok = not differ
+    out = {"jobs": len(jobs), "pins": int(sum(j.n_pins for j in jobs)),
+           "sizes": "2048-%d nodes, random e32/e192, layered, conv, netlist" % args.batch_max_nodes,
+           "generation_s": round(gen_s, 1),
+           "plain_closed_jobs_per_s": round(len(jobs) / span, 2),
+           "batched_closed_jobs_per_s": round(len(jobs) / span_b, 2), "arrival_rate_per_s": round(rate, 2),
+           "plain": summary(plain, 1), "batched": summary(batched, args.batch_workers),
+           "status_counts": status, "bit_exact_vs_plain": bool(ok), "differing_jobs": differ[:16]}
+    gold = os.path.join(ROOT, "tests", "golden", "job_stream_%d.json" % len(jobs))
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        if (g["n_jobs"], g["min_nodes"], g["max_nodes"], g["seed"]) == (len(jobs), 2048, args.batch_max_nodes, 0):
+            checked = matched = 0
+            for gj, b in zip(g["jobs"], batched):
+                if "rho_sha256" not in gj:
+                    continue
+                checked += 1
+                rho = np.ascontiguousarray(b["rho"], np.int32)
+                matched += int(hashlib.sha256(rho.tobytes()).hexdigest() == gj["rho_sha256"])
+            out["oracle_checked_jobs"] = checked
+            out["oracle_matching_jobs"] = matched
+    return out
 
 
 def sweep(args):
     """Parameter sweeps of the method on one workload: Pi (candidates and
     matching rounds) at Theta = 16, Theta (repetitions per level) at Pi = 4,
-    and the ablation without chain rounds (moves sequenced by gain alone).
-    Per setting: the partition's connectivity and violations, the hierarchy
-    depth and the wall time of one partitioning (after one untimed run)."""
+    the ablation without chain rounds (moves sequenced by gain alone) and the
+    one with the prototype's greedy matching.  Per setting: the partition's
+    connectivity and violations, the hierarchy depth and the wall time of one
+    partitioning (after one untimed run)."""
     import torch
 
     import paper_2605_20497_amd as pkg
@@ -165,34 +250,50 @@ def sweep(args):
     hg = W.CONFIGS[args.sweep_workload]()
     torch.cuda.set_device(0)
 
-    def run(pi, theta, flags=0):
-        g = pkg.Partitioner(device=0, pi=pi, theta=theta)
-        if flags:
-            g.close()
-            g = pkg.Partitioner(device=0, pi=pi, theta=theta, no_chains=True)
-        out = None
-        for rep in range(2):
-            g.load(hg)
-            g.hgp_set_limits(hg.omega, hg.delta, hg.k)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            nl = g.hgp_coarsen()
-            g.hgp_refine()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            ev = g.hgp_evaluate()
-            out = {"pi": pi, "theta": theta, "chains": not flags, "conn": int(ev["conn"]),
-                   "violations": int(ev["violations"]), "parts": int(ev["n_parts"]), "levels": int(nl),
-                   "ms": round(dt * 1e3, 2)}
+    def run(pi, theta, no_chains=False, greedy=False):
+        g = pkg.Partitioner(device=0, pi=pi, theta=theta, no_chains=no_chains, greedy_matching=greedy)
+        out = {"pi": pi, "theta": theta, "chains": not no_chains, "matching": "greedy" if greedy else "exact"}
+        try:
+            for rep in range(2):
+                g.load(hg)
+                g.hgp_set_limits(hg.omega, hg.delta, hg.k)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                nl = g.hgp_coarsen()
+                g.hgp_refine()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ev = g.hgp_evaluate()
+                out.update(conn=int(ev["conn"]), violations=int(ev["violations"]), parts=int(ev["n_parts"]),
+                           levels=int(nl), ms=round(dt * 1e3, 2))
+        except pkg.HgpError as e:
+            # a setting whose hierarchy outgrows device memory is a result of the sweep, not a crash of it
+            import ctypes
+            import numpy as np
+            lv = np.zeros(4 * 4096, np.int64)
+            pkg.lib().hgp_get_levels(g.h, lv.ctypes.data_as(ctypes.c_void_p), lv.size)
+            lv = lv.reshape(-1, 4)
+            lv = lv[lv[:, 0] > 0]
+            out.update(error=str(e), levels_built=len(lv), nodes_last_level=int(lv[-1, 0]) if len(lv) else None,
+                       pins_last_level=int(lv[-1, 2]) if len(lv) else None)
         g.close()
+        torch.cuda.empty_cache()
         print(json.dumps(out), file=sys.stderr, flush=True)
         return out
 
     rows = [run(pi, 16) for pi in (1, 2, 3, 4, 6, 8)]
     rows += [run(4, th) for th in (0, 1, 2, 4, 8, 32, 64)]
-    rows.append(run(4, 16, flags=1))
+    rows.append(run(4, 16, no_chains=True))
+    rows.append(run(4, 16, greedy=True))
     print(json.dumps({"sweep": args.sweep_workload, "nodes": hg.n_nodes, "pins": hg.n_pins,
                       "omega": hg.omega, "delta": hg.delta, "rows": rows}))
+
+
+def _roofline_entry(kernel, bound, achieved, peak, unit, traffic_bytes, **extra):
+    out = {"kernel": kernel, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+           "frac": round(achieved / peak, 5), "traffic": traffic_bytes}
+    out.update(extra)
+    return out
 
 
 def main():
@@ -211,6 +312,8 @@ def main():
     from paper_2605_20497_amd import workloads as W
 
     hg = W.CONFIGS[args.workload]()
+    print("bench: %s generated, %d nodes, %d pins" % (args.workload, hg.n_nodes, hg.n_pins), file=sys.stderr,
+          flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t_he_off = torch.from_numpy(hg.he_off).to(dev)
@@ -230,10 +333,14 @@ def main():
 
     # Timed steps record HIP events only around the roofline kernels
     # (proposal histogram, gains sweep, the two dense GEMMs) and count the
-    # gains' row reads on the device; recording events around every launch would
-    # add about a sixth to the step.  One extra step after the timed region
-    # records every family for the breakdown.
-    part = pkg.Partitioner(device=0, profile=True, profile_families=("propose", "gains", "dense_gemm", "gains_gemm"))
+    # gains' row reads on the device (one atomic per wave); recording events
+    # around every launch would add about a sixth to a step.  One extra step
+    # after the timed region records every family for the breakdown.
+    # tile and schedule choices from the autotuner's cache (defaults without one)
+    from paper_2605_20497_amd import autotune
+    tune = autotune.tuned_options(args.workload)
+    part = pkg.Partitioner(device=0, profile=True, profile_families=("propose", "gains", "dense_gemm", "gains_gemm"),
+                           tune=tune)
 
     def step():
         part.hgp_load_csr_device(hg.n_nodes, t_he_off, t_nsrc, t_pins, t_hw, t_nw)
@@ -248,104 +355,120 @@ def main():
     level_times = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
         level_times.append(part.hgp_level_times())
+        print("bench: step %d of %d done" % (i + 1, args.steps), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     stats_timed = part.hgp_kernel_stats()
-    full = pkg.Partitioner(device=0, profile=True)
-    hg_step = (hg.n_nodes, t_he_off, t_nsrc, t_pins, t_hw, t_nw)
-    full.hgp_load_csr_device(*hg_step)
+    work_timed = part.hgp_kernel_work()
+    levels = part.hgp_get_levels()
+    ev = part.hgp_evaluate()
+    card_lv = []
+    for lv in range(int(levels.shape[0])):
+        he_off = part.hgp_get_level_graph(lv, what=("he_off",))[0]
+        card_lv.append(np.diff(he_off).astype(np.int64))
+    part.close()
+
+    full = pkg.Partitioner(device=0, profile=True, tune=tune)
+    full.hgp_load_csr_device(hg.n_nodes, t_he_off, t_nsrc, t_pins, t_hw, t_nw)
     full.hgp_set_limits(hg.omega, hg.delta, hg.k)
     full.hgp_coarsen()
     full.hgp_refine()
     torch.cuda.synchronize()
     stats = full.hgp_kernel_stats()
+    lstats = full.hgp_kernel_level_stats()
     full.close()
-    levels = part.hgp_get_levels()
-    ev = part.hgp_evaluate()
     lt = np.median(np.stack(level_times), axis=0)
 
+    # Per level: pins/s of the timed steps, and per streaming family of the
+    # profiled step its time, device-counted algorithmic bytes, GB/s and HBM
+    # fraction.
     per_level = []
+    stream_tot = {f: [0, 0] for f in STREAM_FAMILIES}
     for lv, (N, E, P, pairs) in enumerate(levels.tolist()):
         tc, tr = lt[lv] * 1e-9
-        per_level.append({"level": lv, "nodes": N, "pins": P, "coarsen_ms": round(tc * 1e3, 3),
-                          "refine_ms": round(tr * 1e3, 3),
-                          "pins_per_s": (P / (tc + tr)) if tc + tr > 0 else None})
+        row = {"level": lv, "nodes": N, "pins": P, "coarsen_ms": round(tc * 1e3, 3), "refine_ms": round(tr * 1e3, 3),
+               "pins_per_s": (P / (tc + tr)) if tc + tr > 0 else None, "streams": {}}
+        for f in STREAM_FAMILIES:
+            a = lstats[f][lv] if lv < lstats[f].shape[0] else (0, 0, 0)
+            launches, ns, nbytes = int(a[0]), int(a[1]), int(a[2])
+            if launches == 0 or ns == 0:
+                continue
+            gbs = nbytes / ns
+            stream_tot[f][0] += ns
+            stream_tot[f][1] += nbytes
+            row["streams"][f] = {"launches": launches, "ms": round(ns * 1e-6, 3), "bytes": nbytes,
+                                 "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        per_level.append(row)
+    streams = {f: {"ms_per_step": round(ns * 1e-6, 3), "bytes_per_step": nb,
+                   "gbs": round(nb / ns, 1) if ns else None,
+                   "hbm_frac": round(nb / ns / HBM_PEAK_GBS, 4) if ns else None}
+               for f, (ns, nb) in stream_tot.items() if ns}
     # per-family breakdown from the separate fully profiled step
     fam = {k: v for k, v in stats.items() if v[0] > 0}
     total_ns = sum(v[1] for v in fam.values())
     dom = max(fam, key=lambda k: fam[k][1])
     breakdown = {k: {"launches": v[0], "ms_per_step": round(v[1] * 1e-6, 3)}
                  for k, v in sorted(fam.items(), key=lambda kv: -kv[1][1])}
+
     # Rooflines of the largest kernels, from HIP events over the timed steps;
-    # `roofline` is the one that takes the most time.
-    card_lv = []
-    for lv in range(int(levels.shape[0])):
-        he_off = part.hgp_get_level_graph(lv, what=("he_off",))[0]
-        card_lv.append(np.diff(he_off).astype(np.int64))
-    work_timed = part.hgp_kernel_work()
+    # `roofline` is the one that takes the most time per step.
     roofs = {}
     prop = stats_timed.get("propose")
-    dg = stats_timed.get("dense_gemm")
     n_prop = int(round(prop[0] / args.steps)) if prop else 0
+    hist_levels = [lv for lv in range(len(card_lv)) if lv < n_prop]
+    upd_all = [int((c * (c - 1)).sum()) for c in card_lv]
     if prop and prop[0] > 0:
         # One launch per level on the histogram path (the first n_prop levels):
-        # histogram updates sum_e |e| (|e| - 1) and the compulsory HBM bytes.
+        # its work is one histogram update per (node, incident h-edge, other
+        # pin), sum_e |e| (|e| - 1), a 32-bit LDS atomic add (the hashed
+        # table's update adds a probe).
         t_launch = prop[1] / prop[0] * 1e-9
-        upd = sum(int((c * (c - 1)).sum()) for c in card_lv[:n_prop]) / max(n_prop, 1)
-        ach = upd / t_launch / 1e9
+        upd = sum(upd_all[lv] for lv in hist_levels) / max(n_prop, 1)
         nbytes = algorithmic_bytes("propose", levels.tolist()[:n_prop], part.pi) / max(n_prop, 1)
-        tr = traffic("k_propose")
-        roofs["k_propose"] = {
-            "kernel": "k_propose", "bound": "alu", "achieved": round(ach, 2), "peak": LDS_UPDATE_PEAK_GOPS,
-            "unit": "Gop/s", "frac": round(ach / LDS_UPDATE_PEAK_GOPS, 5), "traffic": tr,
-            "op": "histogram update (32-bit LDS atomic add)", "ops_per_launch": int(upd),
-            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(prop[1] * 1e-6 / args.steps, 3),
-            "hbm_compulsory_bytes_per_launch": int(nbytes),
-            "hbm_compulsory_gbs": round(nbytes / t_launch / 1e9, 2),
-            "hbm_frac": round(nbytes / t_launch / 1e9 / HBM_PEAK_GBS, 5)}
+        roofs["k_propose"] = _roofline_entry(
+            "k_propose", "alu", upd / t_launch / 1e9, LDS_UPDATE_PEAK_GOPS, "Gop/s", traffic("k_propose"),
+            op="histogram update (32-bit LDS atomic add)", ops_per_launch=int(upd),
+            avg_launch_ms=round(t_launch * 1e3, 4), ms_per_step=round(prop[1] * 1e-6 / args.steps, 3),
+            hbm_compulsory_bytes_per_launch=int(nbytes), hbm_compulsory_gbs=round(nbytes / t_launch / 1e9, 2),
+            hbm_frac=round(nbytes / t_launch / 1e9 / HBM_PEAK_GBS, 5))
     gn = stats_timed.get("gains")
     if gn and gn[0] > 0 and work_timed.get("gains", 0) > 0:
         # Phi row entries read (counted on the device): one bin update each,
         # 2 bytes each from the 16-bit row copy.
         t_launch = gn[1] / gn[0] * 1e-9
         visits = work_timed["gains"] / gn[0]
-        ach = visits / t_launch / 1e9
-        roofs["k_gains16"] = {
-            "kernel": "k_gains16", "bound": "alu", "achieved": round(ach, 2), "peak": LDS_UPDATE_PEAK_GOPS,
-            "unit": "Gop/s", "frac": round(ach / LDS_UPDATE_PEAK_GOPS, 5), "traffic": traffic("k_gains16"),
-            "op": "row entry read + bin update (32-bit LDS atomic add)", "ops_per_launch": int(visits),
-            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(gn[1] * 1e-6 / args.steps, 3),
-            "row_bytes_gbs": round(2 * visits / t_launch / 1e9, 2)}
+        roofs["k_gains16"] = _roofline_entry(
+            "k_gains16", "alu", visits / t_launch / 1e9, LDS_UPDATE_PEAK_GOPS, "Gop/s", traffic("k_gains16"),
+            op="row entry read + bin update (32-bit LDS atomic add)", ops_per_launch=int(visits),
+            avg_launch_ms=round(t_launch * 1e3, 4), ms_per_step=round(gn[1] * 1e-6 / args.steps, 3),
+            row_bytes_gbs=round(2 * visits / t_launch / 1e9, 2))
+    dg = stats_timed.get("dense_gemm")
     if dg and dg[0] > 0:
-        # int8 MACs issued by the dense proposal's products (counted by the
-        # library from the padded sizes: planes + 1 products over the upper
-        # triangle of 128 x 128 tiles, K = E rounded up to 128)
-        macs = work_timed.get("dense_gemm", 0)
+        # The dense proposal computes the same histograms as int8 products on
+        # small levels.  Its work is counted as the method's histogram updates
+        # of those levels, against the same peak; the MFMA rate of the padded
+        # products it issues is reported beside it.
         t_launch = dg[1] / dg[0] * 1e-9
-        ops = 2.0 * macs / dg[0]
-        ach = ops / t_launch / 1e12
-        roofs["k_dense_gemm"] = {
-            "kernel": "k_dense_gemm", "bound": "mfma", "achieved": round(ach, 2), "peak": INT8_PEAK_TOPS,
-            "unit": "TOP/s", "frac": round(ach / INT8_PEAK_TOPS, 5), "traffic": traffic("k_dense_gemm"),
-            "op": "int8 MAC = 2 ops (v_mfma_i32_32x32x32_i8)", "ops_per_launch": int(ops),
-            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(dg[1] * 1e-6 / args.steps, 3)}
+        dense_lv = [lv for lv in range(len(card_lv)) if lv >= n_prop][:int(round(dg[0] / args.steps))]
+        upd = sum(upd_all[lv] for lv in dense_lv) / max(len(dense_lv), 1)
+        macs = work_timed.get("dense_gemm", 0) / dg[0]
+        roofs["k_dense_gemm"] = _roofline_entry(
+            "k_dense_gemm", "alu", upd / t_launch / 1e9, LDS_UPDATE_PEAK_GOPS, "Gop/s", traffic("k_dense_gemm"),
+            op="histogram update of the method, computed as int8 MFMA products", ops_per_launch=int(upd),
+            avg_launch_ms=round(t_launch * 1e3, 4), ms_per_step=round(dg[1] * 1e-6 / args.steps, 3),
+            mfma_tops=round(2 * macs / t_launch / 1e12, 2),
+            mfma_frac=round(2 * macs / t_launch / 1e12 / INT8_PEAK_TOPS, 4))
     gg = stats_timed.get("gains_gemm")
     if gg and gg[0] > 0:
-        # int8 MACs issued by the dense in-isolation moves (counted by the
-        # library: weight planes x padded nodes x padded partitions x E
-        # rounded up to 128)
-        macs = work_timed.get("gains_gemm", 0)
         t_launch = gg[1] / gg[0] * 1e-9
-        ops = 2.0 * macs / gg[0]
-        ach = ops / t_launch / 1e12
-        roofs["k_conn_gemm"] = {
-            "kernel": "k_conn_gemm", "bound": "mfma", "achieved": round(ach, 2), "peak": INT8_PEAK_TOPS,
-            "unit": "TOP/s", "frac": round(ach / INT8_PEAK_TOPS, 5), "traffic": traffic("k_conn_gemm"),
-            "op": "int8 MAC = 2 ops (v_mfma_i32_32x32x32_i8)", "ops_per_launch": int(ops),
-            "avg_launch_ms": round(t_launch * 1e3, 4), "ms_per_step": round(gg[1] * 1e-6 / args.steps, 3)}
+        macs = work_timed.get("gains_gemm", 0) / gg[0]
+        roofs["k_conn_gemm"] = _roofline_entry(
+            "k_conn_gemm", "mfma", 2 * macs / t_launch / 1e12, INT8_PEAK_TOPS, "TOP/s", traffic("k_conn_gemm"),
+            op="int8 MAC = 2 ops of the padded product (v_mfma_i32_32x32x32_i8)", ops_per_launch=int(2 * macs),
+            avg_launch_ms=round(t_launch * 1e3, 4), ms_per_step=round(gg[1] * 1e-6 / args.steps, 3))
     roof = max(roofs.values(), key=lambda r: r["ms_per_step"]) if roofs else None
 
     out = {
@@ -357,20 +480,23 @@ def main():
                    "omega": hg.omega, "delta": hg.delta, "pi": part.pi, "theta": part.theta,
                    "levels": int(levels.shape[0]), "partitions": int(ev["n_parts"]), "conn": int(ev["conn"]),
                    "violations": int(ev["violations"])},
+        "roofline": roof,
+        "rooflines": list(roofs.values()),
+        "tuning": {k: tune[k] for k in ("hash_log2", "list_gate")},
+        "streams": streams,
         "levels": per_level,
         "kernels": breakdown,
         "dominant_kernel": dom,
-        "rooflines": list(roofs.values()),
         "kernel_time_share": round(total_ns * 1e-9 / dt, 4) if dt > 0 else None,
-        "kernels_note": "per-family times from one extra fully profiled step; the timed steps record "
-                        "events around the roofline kernels only",
-        "roofline": roof,
+        "kernels_note": "per-family times, per-level stream figures from one extra fully profiled step; the "
+                        "timed steps record events around the roofline kernels only",
     }
-    part.close()
     if not args.no_batch:
+        print("bench: batched job-stream leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(args)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args)
+        print("bench: CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args, hg)
     print(json.dumps(out))
 
 

@@ -87,7 +87,11 @@ typedef struct hgp_options {
                             * library applies it at load by relabelling pin roles: outbound
                             * swaps sources and destinations, incident makes every pin a
                             * destination.  Connectivity does not depend on roles. */
-    int32_t reserved[4];
+    int32_t tune[4];       /* tile and schedule choices (0 = default; results never depend on them):
+                            * tune[0]: log2 of the hashed proposal's table slots, 10..13 (default 12);
+                            * tune[1]: repetitions list the h-edges of their movers (instead of sweeping
+                            *          all) while movers * tune[1] < nodes, 1..64 (default 4);
+                            * tune[2], tune[3]: 0.  Written by the binding's autotuner (autotune.py). */
 } hgp_options;
 
 enum { HGP_DELTA_INBOUND = 0, HGP_DELTA_OUTBOUND = 1, HGP_DELTA_INCIDENT = 2 };

@@ -31,7 +31,7 @@ class hgp_options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", C.c_void_p), ("pi", C.c_int32), ("theta", C.c_int32), ("seed", C.c_uint64),
                 ("profile", C.c_int32), ("flags", C.c_int32), ("profile_families", C.c_uint32),
-                ("delta_mode", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("delta_mode", C.c_int32), ("tune", C.c_int32 * 4)]
 
 
 class hgp_eval(C.Structure):
@@ -190,7 +190,8 @@ class Partitioner:
 
     def __init__(self, device: int = 0, pi: int = 4, theta: int = 16, seed: int = 0, profile: bool = False,
                  use_torch: bool = True, stream=None, sparse_proposal: bool = False, profile_families=(),
-                 dense_proposal=None, dense_gains=None, delta_mode=0, no_chains=False, greedy_matching=False):
+                 dense_proposal=None, dense_gains=None, delta_mode=0, no_chains=False, greedy_matching=False,
+                 tune=None):
         L = lib()
         opt = hgp_options()
         L.hgp_default_options(C.byref(opt))
@@ -204,6 +205,10 @@ class Partitioner:
                      | (64 if greedy_matching else 0))
         # what Delta counts: 0 inbound h-edges (the paper's), 1 outbound, 2 incident
         opt.delta_mode = int(delta_mode)
+        # tile and schedule choices (autotune.py): {"hash_log2": 10..13, "list_gate": 1..64}
+        if tune:
+            opt.tune[0] = int(tune.get("hash_log2", 0))
+            opt.tune[1] = int(tune.get("list_gate", 0))
         # kernel families to time (names as in hgp_kernel_stats); empty = all
         opt.profile_families = sum(1 << KERNEL_FAMILIES.index(f) for f in profile_families)
         self._keep = []

@@ -312,7 +312,9 @@ hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt) {
     Ctx* c = &h->c;
     hgp_default_options(&c->opt);
     if (opt) c->opt = *opt;
-    if (c->opt.pi < 1 || c->opt.pi > 8 || c->opt.theta < 0 || c->opt.delta_mode < 0 || c->opt.delta_mode > 2) {
+    const int t0 = c->opt.tune[0], t1 = c->opt.tune[1];
+    if (c->opt.pi < 1 || c->opt.pi > 8 || c->opt.theta < 0 || c->opt.delta_mode < 0 || c->opt.delta_mode > 2 ||
+        (t0 != 0 && (t0 < 10 || t0 > 13)) || t1 < 0 || t1 > 64 || c->opt.tune[2] != 0 || c->opt.tune[3] != 0) {
         delete h;
         return HGP_E_INVALID;
     }

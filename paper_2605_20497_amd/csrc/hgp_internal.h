@@ -120,6 +120,7 @@ struct Prof {
 
 struct Ctx {
     i64 max_nbound = 0;  // largest neighbour bound of the level being coarsened
+    u64 sum_card_sq = 0;  // sum of |e|^2 over the h-edges of that level
     hgp_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;

@@ -1090,12 +1090,14 @@ int bits_for(u64 v) {
 template <typename BIN>
 void launch_propose_hash(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, i32* cand,
                          u64* score) {
-    const int C = 4096;  // slots; shared memory = C * (8 + sizeof(BIN)) bytes
+    const int C = 1 << (c->opt.tune[0] ? c->opt.tune[0] : 12);  // slots; shared memory = C * (8 + sizeof(BIN)) B
     const size_t lds = (size_t)C * (8 + sizeof(BIN));
     // as many blocks as are resident at once (shared memory, at most 4 per CU
     // by registers): a second, partial round of blocks would leave most of the
     // chip idle while it runs
-    const int per_cu = std::max(1, std::min(4, (int)(160 * 1024 / (lds + (sizeof(BIN) == 4 ? 5 : 7) * 1024))));
+    // (registers hold the kernel to 3 waves per SIMD with 32-bit bins, 2 with 64-bit)
+    const int per_cu = std::max(1, std::min(sizeof(BIN) == 4 ? 3 : 2,
+                                            (int)(160 * 1024 / (lds + (sizeof(BIN) == 4 ? 5 : 7) * 1024))));
     const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu);
 #define HGP_PROPH(PIV)                                                                                             \
     case PIV:                                                                                                      \
@@ -1114,12 +1116,16 @@ template <typename BIN>
 void launch_propose(Ctx* c, const Level& L, int Pi, const unsigned long long* stats, int ib, i32* cand,
                     u64* score) {
     // Dense id-range histogram while the node ids fit in a few passes over
-    // 64 KiB of bins.  Beyond, the hashed table when every neighbourhood fits
-    // it in a few passes (each pass re-reads all of a node's pins), else dense
-    // passes, which read each destination pin once.
+    // 64 KiB of bins.  Beyond, the hashed table when a node's neighbourhood
+    // typically fits it in a few passes (each pass re-reads all of a node's
+    // pins; the table adapts its pass count per node), else dense passes,
+    // which read each destination pin once.  The typical neighbourhood is
+    // bounded by the mean of sum_{e in I(n)} (|e| - 1) over the nodes,
+    // (sum_e |e|^2 - P) / N.
     const i64 dense_passes = ceil_div((i64)L.N, (i64)(65536 / (int)sizeof(BIN)));
+    const i64 mean_bound = ((i64)c->sum_card_sq - L.P) / std::max<i64>(1, L.N);
     i64 hash_passes = 1;
-    while (hash_passes * 2048 < c->max_nbound) hash_passes <<= 1;
+    while (hash_passes * 2048 < mean_bound) hash_passes <<= 1;
     const bool hashed = dense_passes > 4 && (hash_passes <= std::max<i64>(4, dense_passes / 4) || dense_passes > 256);
     if (hashed || c->force_hash_propose) {
         launch_propose_hash<BIN>(c, L, Pi, stats, ib, cand, score);
@@ -1193,6 +1199,7 @@ void coarsen_level(Ctx* c, int lv) {
     read_back(c, stats, st, 16, 8);
     const u64 max_tsum = (u64)st[0], max_nin = (u64)st[1];
     c->max_nbound = (i64)st[12];
+    c->sum_card_sq = (u64)st[13];
 
     Level& Lm = c->levels[lv];
     Lm.b_cand = c->alloc(sizeof(i32) * (size_t)N * Pi);

@@ -330,31 +330,51 @@ constexpr i32 kGainsFlagParts = 32767;
 // dependent round for the batch instead of one per G rows.
 constexpr int kLaneRow = 8;
 
+// Partitions a wave's node touched (bins that went from 0 to nonzero), so
+// that the scan after the sweep reads those bins only; past kTouchCap of them
+// the scan falls back to every bin.
+constexpr u32 kTouchCap = 128;
+struct Touched {
+    u32* count;
+    unsigned short* list;
+};
+
 // One row entry of the 16-bit copy: the bin update of its partition, or for
 // the row of p_s the saving (e counts when p_s holds one pin of it).
-template <bool ONE_PASS>
+template <bool ONE_PASS, bool TRACK = false>
 __device__ __forceinline__ void gains_entry(u32 raw, u32 w, int pass, i32 ps, i32 lo, i32 hi, i64& saving,
-                                            u32* bins) {
+                                            u32* bins, Touched tt = Touched{nullptr, nullptr}) {
     const i32 p = (i32)(raw & 0x7FFFu);
     const int in = (int)(raw != 0xFFFFFFFFu);
     if ((pass == 0) & in & (int)(p == ps)) saving += (raw >> 15) ? (i64)w : 0;
     const int range = ONE_PASS ? 1 : (int)((u32)(p - lo) < (u32)(hi - lo));
-    if (in & (int)(p != ps) & range) atomicAdd(&bins[p - lo], w);
+    if (in & (int)(p != ps) & range) {
+        if (TRACK) {
+            const u32 old = atomicAdd(&bins[p - lo], w);
+            if (old == 0) {
+                const u32 t = atomicAdd(tt.count, 1u);
+                if (t < kTouchCap) tt.list[t] = (unsigned short)p;
+            }
+        } else {
+            atomicAdd(&bins[p - lo], w);
+        }
+    }
 }
 
 // Row sweep of one wave batch for k_gains16: rows G at a time, GU coalesced
 // loads per row and lane, so G * GU loads per lane are in flight; short rows
 // one per lane.
-template <int G, int GU, bool ONE_PASS>
+template <int G, int GU, bool ONE_PASS, bool TRACK = false>
 __device__ __forceinline__ void gains_group(int nb, int lane, int pass, i32 ps, i32 lo, i32 hi,
                                             const unsigned short* __restrict__ partf, i64 r0, i32 L, i32 w,
-                                            i64& saving, u32* bins) {
+                                            i64& saving, u32* bins, Touched tt = Touched{nullptr, nullptr}) {
     if (wave_max(L) <= kLaneRow) {
         u32 pp[kLaneRow];
 #pragma unroll
         for (int u = 0; u < kLaneRow; ++u) pp[u] = u < L ? (u32)partf[r0 + u] : 0xFFFFFFFFu;
 #pragma unroll
-        for (int u = 0; u < kLaneRow; ++u) gains_entry<ONE_PASS>(pp[u], (u32)w, pass, ps, lo, hi, saving, bins);
+        for (int u = 0; u < kLaneRow; ++u)
+            gains_entry<ONE_PASS, TRACK>(pp[u], (u32)w, pass, ps, lo, hi, saving, bins, tt);
         return;
     }
     for (int i0 = 0; i0 < nb; i0 += G) {
@@ -383,7 +403,8 @@ __device__ __forceinline__ void gains_group(int nb, int lane, int pass, i32 ps, 
 #pragma unroll
             for (int g = 0; g < G; ++g)
 #pragma unroll
-                for (int u = 0; u < GU; ++u) gains_entry<ONE_PASS>(pp[g][u], sw[g], pass, ps, lo, hi, saving, bins);
+                for (int u = 0; u < GU; ++u)
+                    gains_entry<ONE_PASS, TRACK>(pp[g][u], sw[g], pass, ps, lo, hi, saving, bins, tt);
         }
     }
 }
@@ -514,9 +535,13 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     const i32* __restrict__ nw, const i32* __restrict__ rho, const i64* __restrict__ psize, i64 omega,
     i32* move_dst, i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R, unsigned long long* work) {
     extern __shared__ u32 bins_all[];  // R bins per wave, R >= nparts
+    __shared__ u32 t_count[kGainsWaves];
+    __shared__ unsigned short t_list[kGainsWaves][kTouchCap];
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     u32* bins = bins_all + (size_t)wv * R;
     for (int i = lane; i < R; i += kWave) bins[i] = 0;
+    if (lane == 0) t_count[wv] = 0;
+    const Touched tt{&t_count[wv], t_list[wv]};
     wave_sync();
     const i64 stride = (i64)gridDim.x * nwv;
     u64 visits = 0;  // row entries this wave read (work counter when profiling)
@@ -538,13 +563,13 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
             visits += (u64)tot;
             const i32 avg = tot / max(nb, 1);
             if (avg <= 64)
-                gains_group<16, 1, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+                gains_group<16, 1, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
             else if (avg <= 128)
-                gains_group<8, 2, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+                gains_group<8, 2, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
             else if (avg <= 192)
-                gains_group<6, 3, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+                gains_group<6, 3, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
             else
-                gains_group<4, 4, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins);
+                gains_group<4, 4, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
         }
         saving = wave_sum(saving);
         wi = wave_sum(wi);
@@ -553,22 +578,29 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
         const i64 need = wi - saving;
         i64 bg = 0, bg2 = 0;  // best move, and best move that keeps size(p) + size(n) <= Omega
         i32 bp = -1, bp2 = -1;
-        for (int sidx = lane; sidx < nparts; sidx += kWave) {
-            const u32 v = bins[sidx];
-            if (v == 0) continue;
-            bins[sidx] = 0;
-            if ((i64)v <= need) continue;
-            const i32 p = sidx;
-            const i64 g = (i64)v - need;
-            const int fits = (int)(nw_n + psize[p] <= omega);
-            const bool t = lex_better(g, p, bg, bp);
-            bg = t ? g : bg;
-            bp = t ? p : bp;
-            const bool t2 = (fits & (int)lex_better(g, p, bg2, bp2)) != 0;
-            bg2 = t2 ? g : bg2;
-            bp2 = t2 ? p : bp2;
+        auto consider = [&](i32 p) {
+            const u32 v = bins[p];
+            bins[p] = 0;
+            if ((int)(v != 0) & (int)((i64)v > need)) {
+                const i64 g = (i64)v - need;
+                const int fits = (int)(nw_n + psize[p] <= omega);
+                const bool t = lex_better(g, p, bg, bp);
+                bg = t ? g : bg;
+                bp = t ? p : bp;
+                const bool t2 = (fits & (int)lex_better(g, p, bg2, bp2)) != 0;
+                bg2 = t2 ? g : bg2;
+                bp2 = t2 ? p : bp2;
+            }
+        };
+        const u32 touched = t_count[wv];
+        if (touched <= kTouchCap) {
+            for (u32 i = lane; i < touched; i += kWave) consider((i32)t_list[wv][i]);
+        } else {
+            for (int sidx = lane; sidx < nparts; sidx += kWave) consider(sidx);
         }
-        wave_sync();  // bins cleared before the next node's updates
+        wave_sync();  // bins and the count cleared before the next node's updates
+        if (lane == 0) t_count[wv] = 0;
+        wave_sync();
         wave_lexmax_i64(bg, bp);
         wave_lexmax_i64(bg2, bp2);
         if (lane == 0) {
@@ -1576,7 +1608,10 @@ struct PhiBufs {
 // movers * P / N), the sweep reads every pin and its sequence position (2P);
 // the list is taken while the movers are under a quarter of the nodes, where
 // it also spares the per-h-edge work of every h-edge without a mover.
-bool few_touched(const Level& L, i64 movers) { return L.N > 0 && movers * 4 < (i64)L.N; }
+bool few_touched(const Ctx* c, const Level& L, i64 movers) {
+    const i64 gate = c->opt.tune[1] ? c->opt.tune[1] : 4;
+    return L.N > 0 && movers * gate < (i64)L.N;
+}
 
 // Partition sizes and D(p) of rho from its Phi rows; psize and pD start at 0.
 void part_stats(Ctx* c, const Level& L, const i32* rho, i32 nparts, const i32* part, const i32* cin, const i32* len,
@@ -1647,7 +1682,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     // rows of their h-edges changed.  Listing them costs one device atomic per
     // incidence entry of a mover, so the list is used only while those entries
     // (about incr_k * P / N) stay well below the h-edges swept without it.
-    const bool incremental = !reuse && incr_k > 0 && L.E > 0 && few_touched(L, incr_k);
+    const bool incremental = !reuse && incr_k > 0 && L.E > 0 && few_touched(c, L, incr_k);
     if (incremental) {
         clear_marks();
         const i32* prev_seq = wsp<i32>(c, WS_SEQN, (size_t)incr_k);
@@ -1869,7 +1904,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     if (L.E > 0) {
         // Only h-edges holding a mover have in-sequence effects: when the
         // movers are few, list those once each (stamp 2) and sweep only them.
-        const bool listed = few_touched(L, M);
+        const bool listed = few_touched(c, L, M);
         i32* elist2 = listed ? wsp<i32>(c, WS_ELIST2, (size_t)L.E) : nullptr;
         if (listed) {
             clear_marks();

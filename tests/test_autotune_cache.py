@@ -1,0 +1,14 @@
+"""The autotuner's JSON cache (no GPU): defaults without an entry, stored
+choices read back per device and workload, unknown keys ignored."""
+from paper_2605_20497_amd import autotune
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "tuning.json")
+    assert autotune.tuned_options("conv-6.9m", path=path, name="dev") == autotune.DEFAULT
+    autotune.save({"dev": {"conv-6.9m": {"hash_log2": 11, "list_gate": 8, "ms": {"x": 1.0}},
+                           "job-stream": {"workers": 12}}}, path)
+    got = autotune.tuned_options("conv-6.9m", path=path, name="dev")
+    assert got == {"hash_log2": 11, "list_gate": 8, "workers": 8}
+    assert autotune.tuned_options("job-stream", path=path, name="dev")["workers"] == 12
+    assert autotune.tuned_options("conv-6.9m", path=path, name="other") == autotune.DEFAULT

@@ -88,3 +88,22 @@ def test_nomem_mid_coarsening_leaves_context_usable():
     rho2, k2 = ref.partition(hg, 64, 1 << 12, 0)
     ref.close()
     assert k.value == k2 and np.array_equal(rho, rho2)
+
+
+def test_tuning_choices_leave_results_unchanged():
+    # the hashed proposal everywhere, with the smallest and largest tables and
+    # both extremes of the refinement edge-list gate
+    from paper_2605_20497_amd import HgpError, Partitioner
+    hg = W.random_snn(20000, 23, seed=9)
+    print("case tuning N", hg.n_nodes, "P", hg.n_pins, flush=True)
+    ref = Partitioner(sparse_proposal=True)
+    rho0, k0 = ref.partition(hg, 256, 2048, 0)
+    conn0 = ref.hgp_evaluate()["conn"]
+    ref.close()
+    for tune in ({"hash_log2": 10, "list_gate": 1}, {"hash_log2": 13, "list_gate": 64}):
+        g = Partitioner(sparse_proposal=True, tune=tune)
+        rho, k = g.partition(hg, 256, 2048, 0)
+        assert k == k0 and np.array_equal(rho, rho0) and g.hgp_evaluate()["conn"] == conn0, tune
+        g.close()
+    with pytest.raises(HgpError):
+        Partitioner(tune={"hash_log2": 9})
