@@ -198,7 +198,7 @@ def batched_leg(args):
 
     if args.batch_workers <= 0:
         from paper_2605_20497_amd import autotune
-        args.batch_workers = autotune.tuned_options("job-stream")["workers"]
+        args.batch_workers = autotune.tuned_options(autotune.stream_key(len(jobs), args.batch_max_nodes))["workers"]
     closed_b = pkg.hgp_run_jobs(jobs, workers=args.batch_workers)
     span_b = max(r["end_s"] for r in closed_b)
     print("bench: closed-loop runs done", file=sys.stderr, flush=True)

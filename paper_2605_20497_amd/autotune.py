@@ -28,8 +28,11 @@ WORKERS = (2, 4, 8, 12, 16)
 
 
 def device_name(device: int = 0) -> str:
+    """Marketing name and ISA of the device, e.g. 'AMD Radeon Graphics (gfx950)'."""
     import torch
-    return torch.cuda.get_device_name(device)
+    arch = getattr(torch.cuda.get_device_properties(device), "gcnArchName", "").split(":")[0]
+    name = torch.cuda.get_device_name(device)
+    return "%s (%s)" % (name, arch) if arch else name
 
 
 def load(path: str = CACHE) -> dict:
@@ -97,7 +100,12 @@ def tune_partition(workload: str, device: int = 0, path: str = CACHE, log=print)
     return cur
 
 
-def tune_workers(n_jobs: int = 64, max_nodes: int = 32768, device: int = 0, path: str = CACHE,
+def stream_key(n_jobs: int, max_nodes: int) -> str:
+    """Cache key of a job stream of n_jobs jobs of 2,048 to max_nodes nodes."""
+    return "job-stream-%d-%d" % (n_jobs, max_nodes)
+
+
+def tune_workers(n_jobs: int = 256, max_nodes: int = 262144, device: int = 0, path: str = CACHE,
                  log=print) -> int:
     """Closed-loop jobs/s of the job stream for each worker count."""
     import paper_2605_20497_amd as pkg
@@ -111,7 +119,7 @@ def tune_workers(n_jobs: int = 64, max_nodes: int = 32768, device: int = 0, path
         log("tune workers=%d: %.2f jobs/s" % (w, rates[w]))
     best = max(rates, key=rates.get)
     cache = load(path)
-    entry = cache.setdefault(device_name(device), {}).setdefault("job-stream", {})
+    entry = cache.setdefault(device_name(device), {}).setdefault(stream_key(n_jobs, max_nodes), {})
     entry["workers"] = best
     entry["jobs_per_s"] = {str(k): round(v, 2) for k, v in rates.items()}
     save(cache, path)

@@ -330,34 +330,25 @@ constexpr i32 kGainsFlagParts = 32767;
 // dependent round for the batch instead of one per G rows.
 constexpr int kLaneRow = 8;
 
-// Partitions a wave's node touched (bins that went from 0 to nonzero), so
-// that the scan after the sweep reads those bins only; past kTouchCap of them
-// the scan falls back to every bin.
-constexpr u32 kTouchCap = 128;
+// Partitions a wave's node touched, as a bitmap beside its bins (one bit per
+// partition, set with a no-return atomic OR, so the bin updates never wait on
+// a returned value); the scan after the sweep visits the set bits only.
 struct Touched {
-    u32* count;
-    unsigned short* list;
+    u32* bits;
 };
 
 // One row entry of the 16-bit copy: the bin update of its partition, or for
 // the row of p_s the saving (e counts when p_s holds one pin of it).
 template <bool ONE_PASS, bool TRACK = false>
 __device__ __forceinline__ void gains_entry(u32 raw, u32 w, int pass, i32 ps, i32 lo, i32 hi, i64& saving,
-                                            u32* bins, Touched tt = Touched{nullptr, nullptr}) {
+                                            u32* bins, Touched tt = Touched{nullptr}) {
     const i32 p = (i32)(raw & 0x7FFFu);
     const int in = (int)(raw != 0xFFFFFFFFu);
     if ((pass == 0) & in & (int)(p == ps)) saving += (raw >> 15) ? (i64)w : 0;
     const int range = ONE_PASS ? 1 : (int)((u32)(p - lo) < (u32)(hi - lo));
     if (in & (int)(p != ps) & range) {
-        if (TRACK) {
-            const u32 old = atomicAdd(&bins[p - lo], w);
-            if (old == 0) {
-                const u32 t = atomicAdd(tt.count, 1u);
-                if (t < kTouchCap) tt.list[t] = (unsigned short)p;
-            }
-        } else {
-            atomicAdd(&bins[p - lo], w);
-        }
+        atomicAdd(&bins[p - lo], w);
+        if (TRACK) atomicOr(&tt.bits[(p - lo) >> 5], 1u << ((p - lo) & 31));
     }
 }
 
@@ -367,7 +358,7 @@ __device__ __forceinline__ void gains_entry(u32 raw, u32 w, int pass, i32 ps, i3
 template <int G, int GU, bool ONE_PASS, bool TRACK = false>
 __device__ __forceinline__ void gains_group(int nb, int lane, int pass, i32 ps, i32 lo, i32 hi,
                                             const unsigned short* __restrict__ partf, i64 r0, i32 L, i32 w,
-                                            i64& saving, u32* bins, Touched tt = Touched{nullptr, nullptr}) {
+                                            i64& saving, u32* bins, Touched tt = Touched{nullptr}) {
     if (wave_max(L) <= kLaneRow) {
         u32 pp[kLaneRow];
 #pragma unroll
@@ -535,13 +526,13 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     const i32* __restrict__ nw, const i32* __restrict__ rho, const i64* __restrict__ psize, i64 omega,
     i32* move_dst, i64* move_gain, i32* move_dst_sa, i64* move_gain_sa, int R, unsigned long long* work) {
     extern __shared__ u32 bins_all[];  // R bins per wave, R >= nparts
-    __shared__ u32 t_count[kGainsWaves];
-    __shared__ unsigned short t_list[kGainsWaves][kTouchCap];
+    __shared__ u32 t_bits[kGainsWaves][kGainsWaveParts / 32];
     const int lane = lane_id(), wv = wave_id(), nwv = blockDim.x / kWave;
     u32* bins = bins_all + (size_t)wv * R;
     for (int i = lane; i < R; i += kWave) bins[i] = 0;
-    if (lane == 0) t_count[wv] = 0;
-    const Touched tt{&t_count[wv], t_list[wv]};
+    const int nwords = (nparts + 31) >> 5;  // nparts <= kGainsWaveParts
+    for (int i = lane; i < kGainsWaveParts / 32; i += kWave) t_bits[wv][i] = 0;
+    const Touched tt{t_bits[wv]};
     wave_sync();
     const i64 stride = (i64)gridDim.x * nwv;
     u64 visits = 0;  // row entries this wave read (work counter when profiling)
@@ -592,15 +583,16 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
                 bp2 = t2 ? p : bp2;
             }
         };
-        const u32 touched = t_count[wv];
-        if (touched <= kTouchCap) {
-            for (u32 i = lane; i < touched; i += kWave) consider((i32)t_list[wv][i]);
-        } else {
-            for (int sidx = lane; sidx < nparts; sidx += kWave) consider(sidx);
+        for (int wd = lane; wd < nwords; wd += kWave) {
+            u32 bits = t_bits[wv][wd];
+            if (bits) t_bits[wv][wd] = 0;
+            while (bits) {
+                const int bt = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                consider(wd * 32 + bt);
+            }
         }
-        wave_sync();  // bins and the count cleared before the next node's updates
-        if (lane == 0) t_count[wv] = 0;
-        wave_sync();
+        wave_sync();  // bins and bits cleared before the next node's updates
         wave_lexmax_i64(bg, bp);
         wave_lexmax_i64(bg2, bp2);
         if (lane == 0) {
@@ -1269,12 +1261,20 @@ __device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inser
     return -1;  // unreachable: the table has a slot for every part of 2 * cap movers
 }
 
-// Shared memory per h-edge (one wave): the movers' sequence positions and
-// packed (source slot | destination slot << 10 | pin slot << 20), the table
-// (keys, list heads, packed row counts) and one 32-bit link per event:
-// ((next event + 1) << 1) | destination-pin flag; event 2i leaves mover i's
-// source part, 2i + 1 enters its destination part.  16 bytes per mover and
-// 12 per table slot.
+// Shared memory of the wave: per mover its sequence position, node and
+// packed (source slot | destination slot << 10 | pin slot << 20 | destination
+// pin << 30); per row entry its table slot; the table (keys, list heads,
+// packed row counts); one 32-bit link per event: ((next event + 1) << 1) |
+// destination-pin flag, where event 2i leaves mover i's source part and
+// 2i + 1 enters its destination part.  20 bytes per mover slot and 12 per
+// table slot.
+//
+// Latency: every global load of an h-edge is issued unconditionally, with
+// out-of-range lanes reading entry 0 of the same h-edge (cards are >= 1 here),
+// so each dependent step (row and pins, positions, the movers' partitions) is
+// one round trip.  The next h-edge's id is read two h-edges ahead and its
+// offsets one ahead.  The table is cleared once; each h-edge resets the slots
+// it used.  One wave per block, so wave-level fences order shared memory.
 __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
@@ -1285,125 +1285,174 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     const int T = 1 << tbits;
     u64 acc_bytes = 0;
     i32* mq = (i32*)smem_raw;          // cap
-    u32* mpk = (u32*)(mq + cap);       // cap
-    i32* tkey = (i32*)(mpk + cap);     // T
+    i32* mnode = mq + cap;             // cap
+    u32* mpk = (u32*)(mnode + cap);    // cap
+    i32* rslot = (i32*)(mpk + cap);    // cap
+    i32* tkey = rslot + cap;           // T
     i32* thead = tkey + T;             // T
     u32* tcnt = (u32*)(thead + T);     // T
     i32* ev = (i32*)(tcnt + T);        // 2 * cap
     const int lane = threadIdx.x;
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    for (i64 ie = blockIdx.x; ie < ne; ie += gridDim.x) {
-        const i64 e = elist ? (i64)elist[ie] : ie;
-        const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
-        if (b - a > (i64)cap) continue;
-        const i32 L = len[e];
-        for (int t = lane; t < T; t += kWave) {
-            tkey[t] = -1;
-            thead[t] = -1;
-        }
-        __syncthreads();
-        // e's row parts with their counts first (distinct parts)
-        for (i32 r0 = 0; r0 < L; r0 += kInseqU * kWave) {
-            i32 pp[kInseqU];
-            u32 cc[kInseqU];
+    const i64 stride = gridDim.x;
+    for (int t = lane; t < T; t += kWave) {
+        tkey[t] = -1;
+        thead[t] = -1;
+    }
+    wave_sync();
+    auto edge_at = [&](i64 ie) -> i64 { return ie < ne ? (elist ? (i64)elist[ie] : ie) : 0; };
+    i64 ie = blockIdx.x;
+    i64 e_nn = edge_at(ie + stride);  // two ahead after the first step
+    i64 e_n = edge_at(ie);
+    i64 a_n = he_off[e_n], b_n = he_off[e_n + 1];
+    i32 ns_n = he_nsrc[e_n], L_n = len[e_n];
+    for (; ie < ne; ie += stride) {
+        const i64 a = a_n, b = b_n, d0 = a + ns_n;
+        const i32 L = L_n;
+        const i32 card = (i32)(b - a);
+        const bool skip = (card <= 0) | (card > cap);
+        // row entries and pins, then the pins' sequence positions
+        i32 pp[kInseqU], mm[kInseqU], qq[kInseqU];
+        u32 cc[kInseqU];
+        if (!skip) {
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i32 r = r0 + u * kWave + lane;
-                const int in = (int)(r < L);
-                pp[u] = in ? part[a + r] : -1;
-                cc[u] = in ? ((u32)cnt[a + r] | ((u32)cin[a + r] << 16)) : 0u;  // both <= |e| <= 4096
+                const i32 r = u * kWave + lane;
+                const i64 ri = a + (r < L ? r : 0);
+                pp[u] = part[ri];
+                cc[u] = (u32)cnt[ri] | ((u32)cin[ri] << 16);  // both <= |e| <= 4096
+                mm[u] = pins[a + (r < card ? r : 0)];
             }
 #pragma unroll
-            for (int u = 0; u < kInseqU; ++u) {
-                if (pp[u] >= 0) {
-                    int ins;
-                    const i32 t = part_slot(tkey, tbits, pp[u], ins);
-                    tcnt[t] = cc[u];
-                }
+            for (int u = 0; u < kInseqU; ++u) qq[u] = posn[mm[u]];
+        }
+        // prefetch, behind this h-edge's loads: the next h-edge's offsets and
+        // the id of the one after
+        e_n = e_nn;
+        e_nn = edge_at(ie + 2 * stride);
+        a_n = he_off[e_n];
+        b_n = he_off[e_n + 1];
+        ns_n = he_nsrc[e_n];
+        L_n = len[e_n];
+        if (skip) continue;
+        // e's row parts with their counts (distinct parts)
+#pragma unroll
+        for (int u = 0; u < kInseqU; ++u) {
+            const i32 r = u * kWave + lane;
+            if (r < L) {
+                int ins;
+                const i32 t = part_slot(tkey, tbits, pp[u], ins);
+                tcnt[t] = cc[u];
+                rslot[r] = t;
             }
         }
-        __syncthreads();
-        // Movers: index by ballot, table slots of their parts (a source part
-        // is in the row; a destination part may be new, with no pins in e),
-        // and their two events, pushed on the parts' lists.
+        // movers, indexed by ballot
         int k = 0;
-        for (i64 base = a; base < b; base += kInseqU * kWave) {
-            i32 mm[kInseqU], qq[kInseqU], ps[kInseqU], pd[kInseqU];
+#pragma unroll
+        for (int u = 0; u < kInseqU; ++u) {
+            const i32 j = u * kWave + lane;
+            const int is_mv = (int)(j < card) & (int)(qq[u] < M);
+            const u64 mask = __ballot(is_mv);
+            if (is_mv) {
+                const i32 i = k + __popcll(mask & lt_mask);
+                mq[i] = qq[u];
+                mnode[i] = mm[u];
+                mpk[i] = (u32)j << 20 | ((u32)(a + j >= d0) << 30);
+            }
+            k += __popcll(mask);
+        }
+        wave_sync();
+        if (k > 0) {
+            // the movers' partitions, one lane per mover, then their table
+            // slots (a source part is in the row; a destination part may be
+            // new, with no pins in e) and their two events on the parts' lists
+            i32 ps[kInseqU], pd[kInseqU];
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i64 j = base + u * kWave + lane;
-                mm[u] = j < b ? pins[j] : -1;
+                const i32 i = u * kWave + lane;
+                const i32 nd = mnode[i < k ? i : 0];
+                ps[u] = rho[nd];
+                pd[u] = move_dst[nd];
             }
 #pragma unroll
-            for (int u = 0; u < kInseqU; ++u) qq[u] = mm[u] >= 0 ? posn[mm[u]] : M;
-#pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const int mvr = (int)(qq[u] < M);
-                ps[u] = mvr ? rho[mm[u]] : 0;
-                pd[u] = mvr ? move_dst[mm[u]] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kInseqU; ++u) {
-                const i64 j = base + u * kWave + lane;
-                const int is_mv = (int)(qq[u] < M);
-                const u64 mask = __ballot(is_mv);
-                if (is_mv) {
-                    const i32 i = k + __popcll(mask & lt_mask);
+                const i32 i = u * kWave + lane;
+                if (i < k) {
                     int ins_s, ins_d;
                     const i32 ts = part_slot(tkey, tbits, ps[u], ins_s);
                     const i32 td = part_slot(tkey, tbits, pd[u], ins_d);
                     if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
                     if (ins_d) tcnt[td] = 0u;
-                    const i32 dj = (i32)(j >= d0);
+                    const u32 pk = mpk[i];
+                    const i32 dj = (i32)((pk >> 30) & 1u);
                     const i32 ns = atomicExch(&thead[ts], 2 * i);
                     const i32 nd = atomicExch(&thead[td], 2 * i + 1);
                     ev[2 * i] = ((ns + 1) << 1) | dj;
                     ev[2 * i + 1] = ((nd + 1) << 1) | dj;
-                    mq[i] = qq[u];
-                    mpk[i] = (u32)ts | ((u32)td << 10) | ((u32)(j - a) << 20) | ((u32)dj << 30);
+                    mpk[i] = pk | (u32)ts | ((u32)td << 10);
                 }
-                k += __popcll(mask);
+            }
+            wave_sync();
+            for (int i = lane; i < k; i += kWave) {
+                const i32 q = mq[i];
+                const u32 pk = mpk[i];
+                const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
+                i32 x[2], xi[2];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    i32 acc = 0, acci = 0;
+                    i32 idx = thead[side ? td : ts];
+                    while (idx >= 0) {
+                        const i32 lk = ev[idx];
+                        const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
+                        acc += sg;
+                        acci += sg * (lk & 1);
+                        idx = (lk >> 1) - 1;
+                    }
+                    x[side] = acc;
+                    xi[side] = acci;
+                }
+                const u32 c0s = tcnt[ts], c0d = tcnt[td];
+                const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
+                const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
+                const i32 cis = (i32)(c0s >> 16) + xi[0];
+                const i32 cid = (i32)(c0d >> 16) + xi[1];
+                const i32 di = (i32)((pk >> 30) & 1u);
+                const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
+                                 ((u32)(di & (int)(cid == 0)) << 3);
+                code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
             }
         }
-        __syncthreads();
+        acc_bytes += inseq_edge_bytes(card, L, k);
+        wave_sync();
+        // reset the slots this h-edge used: its row parts and its movers' parts
+#pragma unroll
+        for (int u = 0; u < kInseqU; ++u) {
+            const i32 r = u * kWave + lane;
+            if (r < L) {
+                tkey[rslot[r]] = -1;
+                thead[rslot[r]] = -1;
+            }
+        }
         for (int i = lane; i < k; i += kWave) {
-            const i32 q = mq[i];
             const u32 pk = mpk[i];
             const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
-            i32 x[2], xi[2];
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                i32 acc = 0, acci = 0;
-                i32 idx = thead[side ? td : ts];
-                while (idx >= 0) {
-                    const i32 lk = ev[idx];
-                    const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
-                    acc += sg;
-                    acci += sg * (lk & 1);
-                    idx = (lk >> 1) - 1;
-                }
-                x[side] = acc;
-                xi[side] = acci;
-            }
-            const u32 c0s = tcnt[ts], c0d = tcnt[td];
-            const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
-            const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
-            const i32 cis = (i32)(c0s >> 16) + xi[0];
-            const i32 cid = (i32)(c0d >> 16) + xi[1];
-            const i32 di = (i32)((pk >> 30) & 1u);
-            const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
-                             ((u32)(di & (int)(cid == 0)) << 3);
-            code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
+            tkey[ts] = -1;
+            thead[ts] = -1;
+            tkey[td] = -1;
+            thead[td] = -1;
         }
-        acc_bytes += inseq_edge_bytes(b - a, L, k);
-        __syncthreads();
+        wave_sync();
     }
     if ((bytes != nullptr) & (lane == 0) & (acc_bytes != 0)) atomicAdd(bytes, (unsigned long long)acc_bytes);
 }
 
 // In-sequence gains, mover side: one wave per sequence position q sums the
-// outcome bytes over the mover's incidence list.
+// outcome bytes over the mover's incidence list.  Loads are issued for four
+// entries per lane at once, out-of-range lanes reading the list's first entry;
+// the next position's node is read two positions ahead and its offsets one
+// ahead.
 __global__ __launch_bounds__(256) void k_inseq_movers(i32 M, const i32* __restrict__ seqn,
                                                       const i64* __restrict__ inc_off, const i32* __restrict__ inc,
                                                       const i32* __restrict__ inc_pos, const i32* __restrict__ hw,
@@ -1411,26 +1460,42 @@ __global__ __launch_bounds__(256) void k_inseq_movers(i32 M, const i32* __restri
                                                       i32* ddd, unsigned long long* bytes) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
+    const i64 stride = (i64)gridDim.x * wpb;
     u64 acc = 0;
-    for (i64 q = (i64)blockIdx.x * wpb + wave_id(); q < M; q += (i64)gridDim.x * wpb) {
-        const i32 n = seqn[q];
-        const i64 s = inc_off[n], t = inc_off[n + 1];
+    i64 q = (i64)blockIdx.x * wpb + wave_id();
+    if (q >= M) return;
+    i32 n_nn = seqn[q + stride < M ? q + stride : q];
+    const i32 n0 = seqn[q];
+    i64 s_n = inc_off[n0], t_n = inc_off[n0 + 1];
+    for (; q < M; q += stride) {
+        const i64 s = s_n, t = t_n;
+        const i32 n1 = n_nn;
+        n_nn = seqn[q + 2 * stride < M ? q + 2 * stride : q];
+        s_n = inc_off[n1];
+        t_n = inc_off[n1 + 1];
         i64 g = 0;
         i32 ls = 0, gd = 0;
         for (i64 i0 = s; i0 < t; i0 += 4 * kWave) {
-            i32 cc[4], ww[4];
+            i32 pos[4], hh[4], cc[4], ww[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const i64 i = i0 + u * kWave + lane;
-                const int in = (int)(i < t);
-                cc[u] = in ? (i32)code[inc_pos[i]] : 0;
-                ww[u] = in ? hw[inc[i]] : 0;
+                const i64 ii = i < t ? i : s;
+                pos[u] = inc_pos[ii];
+                hh[u] = inc[ii];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                g += (i64)ww[u] * (i64)((cc[u] & 1) - ((cc[u] >> 1) & 1));
-                ls += (cc[u] >> 2) & 1;
-                gd += (cc[u] >> 3) & 1;
+                cc[u] = (i32)code[pos[u]];
+                ww[u] = hw[hh[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int in = (int)(i0 + u * kWave + lane < t);
+                const i32 c = in ? cc[u] : 0;
+                g += (i64)(in ? ww[u] : 0) * (i64)((c & 1) - ((c >> 1) & 1));
+                ls += (c >> 2) & 1;
+                gd += (c >> 3) & 1;
             }
         }
         g = wave_sum(g);
@@ -1916,7 +1981,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         const int capl = std::min(cap, kInseqListMax);
         int tbits = 1;
         while ((1 << tbits) < 2 * capl) ++tbits;
-        const size_t lds_l = (size_t)16 * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
+        const size_t lds_l = (size_t)24 * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
         LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, lds_l, L.E,
                (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl,
                tbits, (const i32*)elist2, (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));

@@ -7,8 +7,8 @@ def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "tuning.json")
     assert autotune.tuned_options("conv-6.9m", path=path, name="dev") == autotune.DEFAULT
     autotune.save({"dev": {"conv-6.9m": {"hash_log2": 11, "list_gate": 8, "ms": {"x": 1.0}},
-                           "job-stream": {"workers": 12}}}, path)
+                           autotune.stream_key(256, 262144): {"workers": 12}}}, path)
     got = autotune.tuned_options("conv-6.9m", path=path, name="dev")
     assert got == {"hash_log2": 11, "list_gate": 8, "workers": 8}
-    assert autotune.tuned_options("job-stream", path=path, name="dev")["workers"] == 12
+    assert autotune.tuned_options(autotune.stream_key(256, 262144), path=path, name="dev")["workers"] == 12
     assert autotune.tuned_options("conv-6.9m", path=path, name="other") == autotune.DEFAULT
