@@ -149,6 +149,22 @@ __global__ void k_inc_offsets(i32 N, i64 P, const u32* __restrict__ skeys, i64* 
     }
 }
 
+// H-edges of at most kSmallEdge pins are handled one lane each, their keys
+// sorted in registers by an odd-even transposition network (ascending).
+constexpr int kSmallEdge = 8;
+
+template <int S>
+__device__ __forceinline__ void reg_sort(u32 (&k)[S]) {
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int i = r & 1; i + 1 < S; i += 2) {
+            const u32 x = k[i], y = k[i + 1];
+            k[i] = x < y ? x : y;
+            k[i + 1] = x < y ? y : x;
+        }
+}
+
 // Coarse pins of one h-edge per block (Sec. V-E): map pins through gamma,
 // sort (id, is_source) in shared memory, keep each coarse id once; an id seen
 // among destinations is a destination, otherwise a source.  Written at the
@@ -160,11 +176,24 @@ __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __rest
                                                         unsigned long long* bytes) {
     extern __shared__ u32 keys[];
     __shared__ i32 red[16];
+    __shared__ i32 s_list[256];
+    __shared__ int s_n;
     u64 acc = 0;  // algorithmic bytes of the h-edges this block handled
-    for (i64 e = blockIdx.x; e < E; e += gridDim.x) {
+    // h-edges blockDim.x at a time; those of more than skip_le pins are listed
+    // in shared memory and handled one after another
+    for (i64 base = (i64)blockIdx.x * blockDim.x; base < E; base += (i64)gridDim.x * blockDim.x) {
+      if (threadIdx.x == 0) s_n = 0;
+      __syncthreads();
+      {
+        const i64 el = base + threadIdx.x;
+        if ((el < E) && (he_off[el + 1] - he_off[el] > (i64)skip_le)) s_list[atomicAdd(&s_n, 1)] = (i32)el;
+      }
+      __syncthreads();
+      const int nl = s_n;
+      for (int li = 0; li < nl; ++li) {
+        const i64 e = s_list[li];
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
-        if (card <= skip_le) continue;  // taken by the wave kernel
         const int npad = next_pow2(card);
         for (int i = threadIdx.x; i < npad; i += blockDim.x)
             keys[i] = i < card ? (((u32)gamma[pins[a + i]] << 1) | (i < ns ? 1u : 0u)) : 0xFFFFFFFFu;
@@ -202,23 +231,45 @@ __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __rest
         // coarse pins and the two counts written
         acc += 20 + 8 * (u64)card + 4 * (u64)(run_s + run_d);
         __syncthreads();
+      }
     }
     if ((bytes != nullptr) & (threadIdx.x == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
 // Compacts per-h-edge segments written at old offsets into the new layout.
+// Each wave takes 64 h-edges: segments of at most kSmallEdge pins are copied
+// one lane each, longer ones by the whole wave (kept by ballot).
 __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict__ old_off,
                                                     const i64* __restrict__ new_off, const i32* __restrict__ tmp,
                                                     i32* out, unsigned long long* bytes) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
     u64 acc = 0;
-    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
-        const i64 a = old_off[e], o = new_off[e], n = new_off[e + 1] - o;
-        for (i64 j = lane; j < n; j += kWave) out[o + j] = tmp[a + j];
-        acc += 16 + 8 * (u64)n;  // both offsets; each pin read once and written once
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < E; base += (i64)gridDim.x * wpb * kWave) {
+        const i64 el = base + lane;
+        const int in = (int)(el < E);
+        const i64 ec = in ? el : 0;
+        const i64 al = old_off[ec], ol = new_off[ec];
+        const i64 nl = in ? new_off[ec + 1] - ol : 0;
+        if (nl <= kSmallEdge) {
+            i32 v[kSmallEdge];
+#pragma unroll
+            for (int j = 0; j < kSmallEdge; ++j) v[j] = j < nl ? tmp[al + j] : 0;
+#pragma unroll
+            for (int j = 0; j < kSmallEdge; ++j)
+                if (j < nl) out[ol + j] = v[j];
+        }
+        acc += in ? 16 + 8 * (u64)nl : 0;  // both offsets; each pin read once and written once
+        u64 todo = __ballot((int)(nl > kSmallEdge));
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const i64 a = __shfl(al, src, kWave), o = __shfl(ol, src, kWave), n = __shfl(nl, src, kWave);
+            for (i64 j = lane; j < n; j += kWave) out[o + j] = tmp[a + j];
+        }
     }
-    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+    const u64 tot = bytes != nullptr ? (u64)wave_sum((i64)acc) : 0;
+    if ((bytes != nullptr) & (lane == 0) & (tot != 0)) atomicAdd(bytes, (unsigned long long)tot);
 }
 
 // Algorithmic bytes of one h-edge's rows: offsets, |src| and lambda (16), its
@@ -244,13 +295,28 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
                                              unsigned long long* bytes) {
     extern __shared__ u32 sm[];
     __shared__ i32 red[16];
+    __shared__ i32 s_list[256];
+    __shared__ int s_n;
     u64 acc = 0;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    for (i64 i = blockIdx.x; i < ne; i += gridDim.x) {
-        const i64 e = elist ? (i64)elist[i] : i;
+    // list entries blockDim.x at a time; h-edges of more than skip_le pins are
+    // listed in shared memory and handled one after another
+    for (i64 base = (i64)blockIdx.x * blockDim.x; base < ne; base += (i64)gridDim.x * blockDim.x) {
+      if (threadIdx.x == 0) s_n = 0;
+      __syncthreads();
+      {
+        const i64 il = base + threadIdx.x;
+        if (il < ne) {
+            const i64 el = elist ? (i64)elist[il] : il;
+            if (he_off[el + 1] - he_off[el] > (i64)skip_le) s_list[atomicAdd(&s_n, 1)] = (i32)el;
+        }
+      }
+      __syncthreads();
+      const int nl = s_n;
+      for (int li = 0; li < nl; ++li) {
+        const i64 e = s_list[li];
         const i64 a = he_off[e];
         const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
-        if (card <= skip_le) continue;  // taken by the wave kernel
         const int npad = next_pow2(card);
         u32* keys = sm;
         i32* c_all = (i32*)(sm + npad);
@@ -310,6 +376,7 @@ __global__ __launch_bounds__(256) void k_phi(i32 E, const i64* __restrict__ he_o
         if (threadIdx.x == 0) len[e] = rows;
         acc += phi_edge_bytes(card, rows, single != nullptr, part16 != nullptr);
         __syncthreads();
+      }
     }
     if ((bytes != nullptr) & (threadIdx.x == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
@@ -374,24 +441,89 @@ __global__ __launch_bounds__(256) void k_contract_edges_wave(i32 E, const i64* _
                                                              const i32* __restrict__ gamma, i32* tmp, i32* card_out,
                                                              i32* nsrc_out, unsigned long long* bytes) {
     const int wpb = blockDim.x / kWave;
+    const int lane = lane_id();
     u64 acc = 0;
-    for (i64 e = (i64)blockIdx.x * wpb + wave_id(); e < E; e += (i64)gridDim.x * wpb) {
-        const i64 a = he_off[e];
-        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
-        if (card > kWaveEdgeMax) continue;  // taken by the block kernel
+    // 64 h-edges at a time; those of kSmallEdge < |e| <= kWaveEdgeMax pins are
+    // kept by ballot (smaller ones: k_contract_small, larger: the block kernel)
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < E; base += (i64)gridDim.x * wpb * kWave) {
+      const i64 el = base + lane;
+      const i64 ec = el < E ? el : 0;
+      const i64 al = he_off[ec];
+      const int cl = (int)(he_off[ec + 1] - al), nsl = he_nsrc[ec];
+      u64 todo = __ballot((int)(el < E) & (int)(cl > kSmallEdge) & (int)(cl <= kWaveEdgeMax));
+      while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const i64 e = base + src;
+        const i64 a = __shfl(al, src, kWave);
+        const int card = __shfl(cl, src, kWave), ns = __shfl(nsl, src, kWave);
         i32 nc, nsv;
         if (card <= 64) contract_edge_wave<1>(a, card, ns, pins, gamma, tmp, nc, nsv);
         else if (card <= 128) contract_edge_wave<2>(a, card, ns, pins, gamma, tmp, nc, nsv);
         else contract_edge_wave<4>(a, card, ns, pins, gamma, tmp, nc, nsv);
-        if (lane_id() == 0) {
+        if (lane == 0) {
             card_out[e] = nc;
             nsrc_out[e] = nsv;
         }
         // offsets and |src| read, pins and their cluster ids read, the
         // coarse pins and the two counts written
         acc += 20 + 8 * (u64)card + 4 * (u64)nc;
+      }
     }
-    if ((bytes != nullptr) & (lane_id() == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+}
+
+// Coarse pins of h-edges of at most kSmallEdge pins, one lane per h-edge: the
+// keys (cluster << 1 | source flag) sorted in registers, each cluster kept
+// once, sources first; the same result as contract_edge_wave.
+__global__ __launch_bounds__(256) void k_contract_small(i32 E, const i64* __restrict__ he_off,
+                                                        const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+                                                        const i32* __restrict__ gamma, i32* tmp, i32* card_out,
+                                                        i32* nsrc_out, unsigned long long* bytes) {
+    constexpr int S = kSmallEdge;
+    u64 acc = 0;
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (i64)gridDim.x * blockDim.x) {
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a);
+        if (card > S) continue;
+        if (card <= 0) {
+            card_out[e] = 0;
+            nsrc_out[e] = 0;
+            acc += 20;
+            continue;
+        }
+        const int ns = he_nsrc[e];
+        i32 m[S];
+        u32 k[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) m[j] = pins[a + (j < card ? j : 0)];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const u32 g = (u32)gamma[m[j]];
+            k[j] = j < card ? ((g << 1) | (j < ns ? 1u : 0u)) : 0xFFFFFFFFu;
+        }
+        reg_sort<S>(k);
+        int ts = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int head = (int)(j < card) & ((int)(j == 0) | (int)((k[j] >> 1) != (k[j > 0 ? j - 1 : 0] >> 1)));
+            ts += head & (int)((k[j] & 1u) != 0);
+        }
+        int os = 0, od = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int head = (int)(j < card) & ((int)(j == 0) | (int)((k[j] >> 1) != (k[j > 0 ? j - 1 : 0] >> 1)));
+            if (head) {
+                if (k[j] & 1u) tmp[a + os++] = (i32)(k[j] >> 1);
+                else tmp[a + ts + od++] = (i32)(k[j] >> 1);
+            }
+        }
+        card_out[e] = os + od;
+        nsrc_out[e] = os;
+        acc += 20 + 8 * (u64)card + 4 * (u64)(os + od);
+    }
+    const u64 tot = bytes != nullptr ? (u64)wave_sum((i64)acc) : 0;
+    if ((bytes != nullptr) & (lane_id() == 0) & (tot != 0)) atomicAdd(bytes, (unsigned long long)tot);
 }
 
 // Phi rows of one h-edge in one wave.  Shared memory per wave: the sorted
@@ -481,22 +613,105 @@ __global__ __launch_bounds__(256) void k_phi_wave(i32 E, const i64* __restrict__
                                                   unsigned long long* bytes) {
     __shared__ PhiWaveShared sh[4];
     const int wpb = blockDim.x / kWave;
+    const int lane = lane_id();
     PhiWaveShared& my = sh[wave_id()];
     u64 acc = 0;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    for (i64 i = (i64)blockIdx.x * wpb + wave_id(); i < ne; i += (i64)gridDim.x * wpb) {
-        const i64 e = elist ? (i64)elist[i] : i;
-        const i64 a = he_off[e];
-        const int card = (int)(he_off[e + 1] - a), ns = he_nsrc[e];
-        if (card > kWaveEdgeMax) continue;  // taken by the block kernel
+    // 64 list entries at a time; h-edges of kSmallEdge < |e| <= kWaveEdgeMax
+    // pins are kept by ballot (smaller ones: k_phi_small, larger: k_phi)
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < ne; base += (i64)gridDim.x * wpb * kWave) {
+      const i64 il = base + lane;
+      const i64 el = il < ne ? (elist ? (i64)elist[il] : il) : 0;
+      const i64 al = he_off[el];
+      const int cl = (int)(he_off[el + 1] - al), nsl = he_nsrc[el];
+      u64 todo = __ballot((int)(il < ne) & (int)(cl > kSmallEdge) & (int)(cl <= kWaveEdgeMax));
+      while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const i64 e = __shfl(el, src, kWave);
+        const i64 a = __shfl(al, src, kWave);
+        const int card = __shfl(cl, src, kWave), ns = __shfl(nsl, src, kWave);
         i32 rows;
         if (card <= 64) phi_edge_wave<1>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, part16, rows);
         else if (card <= 128) phi_edge_wave<2>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, part16, rows);
         else phi_edge_wave<4>(my, a, card, ns, pins, rho, part, cnt, cnt_in, single, part16, rows);
-        if (lane_id() == 0) len[e] = rows;
+        if (lane == 0) len[e] = rows;
+        acc += phi_edge_bytes(card, rows, single != nullptr, part16 != nullptr);
+      }
+    }
+    if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+}
+
+// Phi rows of h-edges of at most kSmallEdge pins, one lane per h-edge: the
+// keys (partition << 1 | destination flag) sorted in registers and
+// run-length counted; the same rows as phi_edge_wave.
+__global__ __launch_bounds__(256) void k_phi_small(i32 E, const i64* __restrict__ he_off,
+                                                   const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+                                                   const i32* __restrict__ rho, i32* part, i32* cnt, i32* cnt_in,
+                                                   i32* len, unsigned char* single, unsigned short* part16,
+                                                   const i32* __restrict__ elist, const u32* __restrict__ ecount,
+                                                   unsigned long long* bytes) {
+    constexpr int S = kSmallEdge;
+    u64 acc = 0;
+    const i64 ne = elist ? (i64)*ecount : (i64)E;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (i64)gridDim.x * blockDim.x) {
+        const i64 e = elist ? (i64)elist[i] : i;
+        const i64 a = he_off[e];
+        const int card = (int)(he_off[e + 1] - a);
+        if (card > S) continue;
+        if (card <= 0) {
+            len[e] = 0;
+            acc += phi_edge_bytes(0, 0, single != nullptr, part16 != nullptr);
+            continue;
+        }
+        const int ns = he_nsrc[e];
+        i32 m[S];
+        u32 k[S], orig[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) m[j] = pins[a + (j < card ? j : 0)];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const u32 pr = (u32)rho[m[j]];
+            k[j] = j < card ? ((pr << 1) | (j >= ns ? 1u : 0u)) : 0xFFFFFFFFu;
+            orig[j] = k[j];
+        }
+        reg_sort<S>(k);
+        int rows = 0;
+        i32 ca = 0, ci = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (j < card) {
+                ca += 1;
+                ci += (int)(k[j] & 1u);
+                const int last = (int)(j + 1 == card) | (int)(j + 1 < S && (k[j + 1 < S ? j + 1 : j] >> 1) != (k[j] >> 1));
+                if (last) {
+                    part[a + rows] = (i32)(k[j] >> 1);
+                    cnt[a + rows] = ca;
+                    cnt_in[a + rows] = ci;
+                    // 16-bit copy for the gains sweep: partition id, top bit where pins(p,e) = 1
+                    if (part16) part16[a + rows] = (unsigned short)((k[j] >> 1) | (ca == 1 ? 0x8000u : 0u));
+                    ++rows;
+                    ca = 0;
+                    ci = 0;
+                }
+            }
+        }
+        len[e] = rows;
+        if (single) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (j < card) {
+                    int same = 0;
+#pragma unroll
+                    for (int o = 0; o < S; ++o) same += (int)(o < card) & (int)((orig[o] >> 1) == (orig[j] >> 1));
+                    single[a + j] = (unsigned char)(same == 1 ? 1 : 0);
+                }
+            }
+        }
         acc += phi_edge_bytes(card, rows, single != nullptr, part16 != nullptr);
     }
-    if ((bytes != nullptr) & (lane_id() == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
+    const u64 tot = bytes != nullptr ? (u64)wave_sum((i64)acc) : 0;
+    if ((bytes != nullptr) & (lane_id() == 0) & (tot != 0)) atomicAdd(bytes, (unsigned long long)tot);
 }
 
 int bits_for(u64 v) {
@@ -556,10 +771,14 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
     if (E > 0) {
         // the input's largest h-edge bounds every level (|e'| <= |e|)
         const int npad = next_pow2(c->max_card);
-        LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges_wave, grid_for(E, 4, c->num_cu * 16), 256, 0, E, L.he_off(),
+        LAUNCH(c, KF_CONTRACT_EDGES, k_contract_small, grid_for(E, 256, c->num_cu * 8), 256, 0, E, L.he_off(),
                L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(), prof_bytes(c, KF_CONTRACT_EDGES));
+        if (c->max_card > kSmallEdge)
+            LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges_wave, grid_for(ceil_div((i64)E, (i64)kWave), 4,
+                   c->num_cu * 16), 256, 0, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(),
+                   prof_bytes(c, KF_CONTRACT_EDGES));
         if (c->max_card > kWaveEdgeMax)
-            LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges, grid_for(E, 1, c->num_cu * 16), 256,
+            LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges, grid_for(E, 256, c->num_cu * 16), 256,
                    sizeof(u32) * npad, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(),
                    kWaveEdgeMax, prof_bytes(c, KF_CONTRACT_EDGES));
     }
@@ -569,7 +788,8 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
     out.P = P2;
     out.b_pins = c->alloc(sizeof(i32) * (size_t)(P2 > 0 ? P2 : 1));
     if (E > 0)
-        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(E, 4, c->num_cu * 16), 256, 0, E, L.he_off(),
+        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(ceil_div((i64)E, (i64)kWave), 4, c->num_cu * 16), 256, 0, E,
+               L.he_off(),
                (const i64*)out.he_off(), (const i32*)tmp, out.pins(), prof_bytes(c, KF_PACK));
 }
 
@@ -620,10 +840,16 @@ void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32*
                unsigned char* single, unsigned short* part16, const i32* elist, const u32* ecount) {
     if (L.E == 0) return;
     const int npad = next_pow2(c->max_card);
-    LAUNCH(c, KF_PHI, k_phi_wave, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(), L.pins(),
-           rho, part, cnt, cnt_in, len, single, part16, elist, ecount, prof_bytes(c, KF_PHI));
+    // h-edges of at most kSmallEdge pins one lane each, up to kWaveEdgeMax one
+    // wave each, larger ones one block each
+    LAUNCH(c, KF_PHI, k_phi_small, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, L.he_off(), L.he_nsrc(),
+           L.pins(), rho, part, cnt, cnt_in, len, single, part16, elist, ecount, prof_bytes(c, KF_PHI));
+    if (c->max_card > kSmallEdge)
+        LAUNCH(c, KF_PHI, k_phi_wave, grid_for(ceil_div((i64)L.E, (i64)kWave), 4, c->num_cu * 16), 256, 0, L.E,
+               L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, part16, elist, ecount,
+               prof_bytes(c, KF_PHI));
     if (c->max_card > kWaveEdgeMax)
-        LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 1, c->num_cu * 16), 256, sizeof(u32) * (single ? 6 : 4) * npad, L.E,
+        LAUNCH(c, KF_PHI, k_phi, grid_for(L.E, 256, c->num_cu * 16), 256, sizeof(u32) * (single ? 6 : 4) * npad, L.E,
                L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, part16, elist, ecount, npad,
                kWaveEdgeMax, prof_bytes(c, KF_PHI));
 }

@@ -520,6 +520,25 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
 constexpr i32 kGainsWaveParts = 4096;  // 64 KiB of bins for the 4 waves of a block
 constexpr i64 kGainsWaveDeg = 256;
 
+// Nodes of at most kGainsFlatChunks * 64 incident h-edges whose rows hold at
+// most kGainsFlatRow entries are swept with all their loads issued together.
+constexpr int kGainsFlatChunks = 4;
+constexpr int kGainsFlatRow = 4;
+
+// One 64-h-edge batch of a node (per-lane row base, length and weight).
+__device__ __forceinline__ void gains_chunk(i32 avg, int nb, int lane, i32 ps, i32 nparts,
+                                            const unsigned short* __restrict__ partf, i64 r0, i32 L, i32 w,
+                                            i64& saving, u32* bins, Touched tt) {
+    if (avg <= 64)
+        gains_group<16, 1, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+    else if (avg <= 128)
+        gains_group<8, 2, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+    else if (avg <= 192)
+        gains_group<6, 3, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+    else
+        gains_group<4, 4, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+}
+
 __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
     const unsigned short* __restrict__ partf, const i32* __restrict__ len, const i32* __restrict__ hw,
@@ -535,13 +554,93 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     const Touched tt{t_bits[wv]};
     wave_sync();
     const i64 stride = (i64)gridDim.x * nwv;
-    u64 visits = 0;  // row entries this wave read (work counter when profiling)
-    for (i64 n = (i64)blockIdx.x * nwv + wv; n < N; n += stride) {
-        const i32 ps = rho[n];
-        const i64 a = inc_off[n], b = inc_off[n + 1];
+    u64 visits = 0;  // row entries this lane read (work counter when profiling)
+    i64 n = (i64)blockIdx.x * nwv + wv;
+    // the node's partition, incidence offsets and size, one node ahead
+    i32 ps_n = 0;
+    i64 a_n = 0, b_n = 0, nw_nn = 0;
+    if (n < N) {
+        ps_n = rho[n];
+        a_n = inc_off[n];
+        b_n = inc_off[n + 1];
+        nw_nn = nw[n];
+    }
+    for (; n < N; n += stride) {
+        const i32 ps = ps_n;
+        const i64 a = a_n, b = b_n;
+        const i64 nw_n = nw_nn;
         i64 saving = 0, wi = 0;
-        const i64 nw_n = nw[n];
-        for (i64 kb = a; kb < b; kb += kWave) {
+        const i64 deg = b - a;
+        const bool flat = (deg > 0) & (deg <= kGainsFlatChunks * kWave);
+        if (flat) {
+            // All of the node's h-edges at once: incidence, then offsets,
+            // lengths and weights, then (rows of at most kGainsFlatRow entries)
+            // every row entry; three rounds of loads in all.
+            i32 ee[kGainsFlatChunks], LL[kGainsFlatChunks], ww[kGainsFlatChunks];
+            i64 rr[kGainsFlatChunks];
+#pragma unroll
+            for (int u = 0; u < kGainsFlatChunks; ++u) {
+                const i64 k = a + u * kWave + lane;
+                ee[u] = inc[k < b ? k : a];
+            }
+            const i64 n2 = n + stride;  // prefetch behind the incidence loads
+            if (n2 < N) {
+                ps_n = rho[n2];
+                a_n = inc_off[n2];
+                b_n = inc_off[n2 + 1];
+                nw_nn = nw[n2];
+            }
+#pragma unroll
+            for (int u = 0; u < kGainsFlatChunks; ++u) {
+                rr[u] = he_off[ee[u]];
+                LL[u] = len[ee[u]];
+                ww[u] = hw[ee[u]];
+            }
+            i32 lmax = 0;
+#pragma unroll
+            for (int u = 0; u < kGainsFlatChunks; ++u) {
+                const int in = (int)(a + u * kWave + lane < b);
+                LL[u] = in ? LL[u] : 0;
+                ww[u] = in ? ww[u] : 0;
+                wi += ww[u];
+                lmax = max(lmax, LL[u]);
+            }
+            lmax = wave_max(lmax);
+            if (lmax <= kGainsFlatRow) {
+                u32 pp[kGainsFlatChunks][kGainsFlatRow];
+#pragma unroll
+                for (int u = 0; u < kGainsFlatChunks; ++u)
+#pragma unroll
+                    for (int v = 0; v < kGainsFlatRow; ++v)
+                        pp[u][v] = v < LL[u] ? (u32)partf[rr[u] + v] : 0xFFFFFFFFu;
+#pragma unroll
+                for (int u = 0; u < kGainsFlatChunks; ++u) {
+                    visits += (u64)LL[u];
+#pragma unroll
+                    for (int v = 0; v < kGainsFlatRow; ++v)
+                        gains_entry<true, true>(pp[u][v], (u32)ww[u], 0, ps, 0, nparts, saving, bins, tt);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kGainsFlatChunks; ++u) {
+                    const int nb = (int)min((i64)kWave, b - (a + u * kWave));
+                    if (nb > 0) {
+                        const i32 tot = wave_sum(LL[u]);
+                        visits += (u64)LL[u];
+                        gains_chunk(tot / nb, nb, lane, ps, nparts, partf, rr[u], LL[u], ww[u], saving, bins, tt);
+                    }
+                }
+            }
+        } else {
+            const i64 n2 = n + stride;
+            if (n2 < N) {
+                ps_n = rho[n2];
+                a_n = inc_off[n2];
+                b_n = inc_off[n2 + 1];
+                nw_nn = nw[n2];
+            }
+        }
+        for (i64 kb = flat ? b : a; kb < b; kb += kWave) {
             const int nb = (int)min((i64)kWave, b - kb);
             const int valid = (int)(lane < nb);
             const i32 e = inc[valid ? kb + lane : kb];
@@ -551,16 +650,8 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
             const i32 w = valid ? we : 0;
             wi += w;
             const i32 tot = wave_sum(L);
-            visits += (u64)tot;
-            const i32 avg = tot / max(nb, 1);
-            if (avg <= 64)
-                gains_group<16, 1, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
-            else if (avg <= 128)
-                gains_group<8, 2, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
-            else if (avg <= 192)
-                gains_group<6, 3, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
-            else
-                gains_group<4, 4, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+            visits += (u64)L;
+            gains_chunk(tot / max(nb, 1), nb, lane, ps, nparts, partf, r0, L, w, saving, bins, tt);
         }
         saving = wave_sum(saving);
         wi = wave_sum(wi);
@@ -602,7 +693,9 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
             move_gain_sa[n] = bp2 >= 0 ? bg2 : 0;
         }
     }
-    if ((work != nullptr) & (lane == 0) & (visits != 0)) atomicAdd(work, (unsigned long long)visits);
+    // per-lane counts: one reduction per wave, one device atomic per wave
+    const i64 vis = work != nullptr ? wave_sum((i64)visits) : 0;
+    if ((work != nullptr) & (lane == 0) & (vis != 0)) atomicAdd(work, (unsigned long long)vis);
 }
 
 // Lists once each h-edge incident to the nodes nodes[0..cnt): one wave per
@@ -1175,11 +1268,20 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     u64 acc = 0;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    for (i64 ie = blockIdx.x; ie < ne; ie += gridDim.x) {
-        const i64 e = elist ? (i64)elist[ie] : ie;
-        const i64 a = he_off[e], b = he_off[e + 1], d0 = a + he_nsrc[e];
-        if (b - a <= (i64)skip_le) continue;
-        const i32 L = len[e];
+    // h-edges 64 list entries at a time; those of more than skip_le pins are
+    // kept by ballot and handled one after another
+    for (i64 base = (i64)blockIdx.x * kWave; base < ne; base += (i64)gridDim.x * kWave) {
+      const i64 il = base + lane;
+      const i64 el = il < ne ? (elist ? (i64)elist[il] : il) : 0;
+      const i64 al = he_off[el], bl = he_off[el + 1];
+      const i32 nsl = he_nsrc[el], Ll = len[el];
+      u64 todo = __ballot((int)(il < ne) & (int)(bl - al > (i64)skip_le));
+      while (todo) {
+        const int src = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const i64 a = __shfl(al, src, kWave), b = __shfl(bl, src, kWave);
+        const i64 d0 = a + __shfl(nsl, src, kWave);
+        const i32 L = __shfl(Ll, src, kWave);
         for (i32 r = lane; r < L; r += kWave) {
             rp[r] = part[a + r];
             rc[r] = (u32)cnt[a + r] | ((u32)cin[a + r] << 16);  // both <= |e| <= 4096
@@ -1227,6 +1329,7 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
         }
         acc += inseq_edge_bytes(b - a, L, k);
         __syncthreads();
+      }
     }
     if ((bytes != nullptr) & (lane == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
@@ -1269,17 +1372,19 @@ __device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inser
 // 2i + 1 enters its destination part.  20 bytes per mover slot and 12 per
 // table slot.
 //
-// Latency: every global load of an h-edge is issued unconditionally, with
-// out-of-range lanes reading entry 0 of the same h-edge (cards are >= 1 here),
-// so each dependent step (row and pins, positions, the movers' partitions) is
-// one round trip.  The next h-edge's id is read two h-edges ahead and its
-// offsets one ahead.  The table is cleared once; each h-edge resets the slots
-// it used.  One wave per block, so wave-level fences order shared memory.
+// Latency: the wave takes its h-edges 64 list entries at a time, reading their
+// offsets, source counts and row lengths one per lane and keeping (by ballot)
+// those of more than `small` and at most cap pins; the smaller ones belong to
+// k_inseq_small.  Per kept h-edge every global load is issued unconditionally,
+// out-of-range lanes reading entry 0 of the same h-edge, so each dependent
+// step (row and pins, positions, the movers' partitions) is one round trip.
+// The table is cleared once; each h-edge resets the slots it used.  One wave
+// per block, so wave-level fences order shared memory.
 __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
-    const i32* __restrict__ len, unsigned char* code, int cap, int tbits, const i32* __restrict__ elist,
+    const i32* __restrict__ len, unsigned char* code, int cap, int tbits, int small, const i32* __restrict__ elist,
     const u32* __restrict__ ecount, unsigned long long* bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = 1 << tbits;
@@ -1295,27 +1400,28 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
     const int lane = threadIdx.x;
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    const i64 stride = gridDim.x;
     for (int t = lane; t < T; t += kWave) {
         tkey[t] = -1;
         thead[t] = -1;
     }
     wave_sync();
-    auto edge_at = [&](i64 ie) -> i64 { return ie < ne ? (elist ? (i64)elist[ie] : ie) : 0; };
-    i64 ie = blockIdx.x;
-    i64 e_nn = edge_at(ie + stride);  // two ahead after the first step
-    i64 e_n = edge_at(ie);
-    i64 a_n = he_off[e_n], b_n = he_off[e_n + 1];
-    i32 ns_n = he_nsrc[e_n], L_n = len[e_n];
-    for (; ie < ne; ie += stride) {
-        const i64 a = a_n, b = b_n, d0 = a + ns_n;
-        const i32 L = L_n;
-        const i32 card = (i32)(b - a);
-        const bool skip = (card <= 0) | (card > cap);
-        // row entries and pins, then the pins' sequence positions
-        i32 pp[kInseqU], mm[kInseqU], qq[kInseqU];
-        u32 cc[kInseqU];
-        if (!skip) {
+    for (i64 base = (i64)blockIdx.x * kWave; base < ne; base += (i64)gridDim.x * kWave) {
+        const i64 il = base + lane;
+        const i64 el = il < ne ? (elist ? (i64)elist[il] : il) : 0;
+        const i64 al = he_off[el], bl = he_off[el + 1];
+        const i32 nsl = he_nsrc[el], Ll = len[el];
+        const i32 cardl = (i32)(bl - al);
+        u64 todo = __ballot((int)(il < ne) & (int)(cardl > small) & (int)(cardl <= cap));
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const i64 a = __shfl(al, src, kWave);
+            const i32 card = __shfl(cardl, src, kWave);
+            const i64 d0 = a + __shfl(nsl, src, kWave);
+            const i32 L = __shfl(Ll, src, kWave);
+            // row entries and pins, then the pins' sequence positions
+            i32 pp[kInseqU], mm[kInseqU], qq[kInseqU];
+            u32 cc[kInseqU];
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
                 const i32 r = u * kWave + lane;
@@ -1326,126 +1432,202 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
             }
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) qq[u] = posn[mm[u]];
-        }
-        // prefetch, behind this h-edge's loads: the next h-edge's offsets and
-        // the id of the one after
-        e_n = e_nn;
-        e_nn = edge_at(ie + 2 * stride);
-        a_n = he_off[e_n];
-        b_n = he_off[e_n + 1];
-        ns_n = he_nsrc[e_n];
-        L_n = len[e_n];
-        if (skip) continue;
-        // e's row parts with their counts (distinct parts)
-#pragma unroll
-        for (int u = 0; u < kInseqU; ++u) {
-            const i32 r = u * kWave + lane;
-            if (r < L) {
-                int ins;
-                const i32 t = part_slot(tkey, tbits, pp[u], ins);
-                tcnt[t] = cc[u];
-                rslot[r] = t;
-            }
-        }
-        // movers, indexed by ballot
-        int k = 0;
-#pragma unroll
-        for (int u = 0; u < kInseqU; ++u) {
-            const i32 j = u * kWave + lane;
-            const int is_mv = (int)(j < card) & (int)(qq[u] < M);
-            const u64 mask = __ballot(is_mv);
-            if (is_mv) {
-                const i32 i = k + __popcll(mask & lt_mask);
-                mq[i] = qq[u];
-                mnode[i] = mm[u];
-                mpk[i] = (u32)j << 20 | ((u32)(a + j >= d0) << 30);
-            }
-            k += __popcll(mask);
-        }
-        wave_sync();
-        if (k > 0) {
-            // the movers' partitions, one lane per mover, then their table
-            // slots (a source part is in the row; a destination part may be
-            // new, with no pins in e) and their two events on the parts' lists
-            i32 ps[kInseqU], pd[kInseqU];
+            // e's row parts with their counts (distinct parts)
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i32 i = u * kWave + lane;
-                const i32 nd = mnode[i < k ? i : 0];
-                ps[u] = rho[nd];
-                pd[u] = move_dst[nd];
-            }
-#pragma unroll
-            for (int u = 0; u < kInseqU; ++u) {
-                const i32 i = u * kWave + lane;
-                if (i < k) {
-                    int ins_s, ins_d;
-                    const i32 ts = part_slot(tkey, tbits, ps[u], ins_s);
-                    const i32 td = part_slot(tkey, tbits, pd[u], ins_d);
-                    if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
-                    if (ins_d) tcnt[td] = 0u;
-                    const u32 pk = mpk[i];
-                    const i32 dj = (i32)((pk >> 30) & 1u);
-                    const i32 ns = atomicExch(&thead[ts], 2 * i);
-                    const i32 nd = atomicExch(&thead[td], 2 * i + 1);
-                    ev[2 * i] = ((ns + 1) << 1) | dj;
-                    ev[2 * i + 1] = ((nd + 1) << 1) | dj;
-                    mpk[i] = pk | (u32)ts | ((u32)td << 10);
+                const i32 r = u * kWave + lane;
+                if (r < L) {
+                    int ins;
+                    const i32 t = part_slot(tkey, tbits, pp[u], ins);
+                    tcnt[t] = cc[u];
+                    rslot[r] = t;
                 }
+            }
+            // movers, indexed by ballot
+            int k = 0;
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                const i32 j = u * kWave + lane;
+                const int is_mv = (int)(j < card) & (int)(qq[u] < M);
+                const u64 mask = __ballot(is_mv);
+                if (is_mv) {
+                    const i32 i = k + __popcll(mask & lt_mask);
+                    mq[i] = qq[u];
+                    mnode[i] = mm[u];
+                    mpk[i] = (u32)j << 20 | ((u32)(a + j >= d0) << 30);
+                }
+                k += __popcll(mask);
             }
             wave_sync();
+            if (k > 0) {
+                // the movers' partitions, one lane per mover, then their table
+                // slots (a source part is in the row; a destination part may be
+                // new, with no pins in e) and their two events on the parts' lists
+                i32 ps[kInseqU], pd[kInseqU];
+#pragma unroll
+                for (int u = 0; u < kInseqU; ++u) {
+                    const i32 i = u * kWave + lane;
+                    const i32 nd = mnode[i < k ? i : 0];
+                    ps[u] = rho[nd];
+                    pd[u] = move_dst[nd];
+                }
+#pragma unroll
+                for (int u = 0; u < kInseqU; ++u) {
+                    const i32 i = u * kWave + lane;
+                    if (i < k) {
+                        int ins_s, ins_d;
+                        const i32 ts = part_slot(tkey, tbits, ps[u], ins_s);
+                        const i32 td = part_slot(tkey, tbits, pd[u], ins_d);
+                        if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
+                        if (ins_d) tcnt[td] = 0u;
+                        const u32 pk = mpk[i];
+                        const i32 dj = (i32)((pk >> 30) & 1u);
+                        const i32 hs = atomicExch(&thead[ts], 2 * i);
+                        const i32 hd = atomicExch(&thead[td], 2 * i + 1);
+                        ev[2 * i] = ((hs + 1) << 1) | dj;
+                        ev[2 * i + 1] = ((hd + 1) << 1) | dj;
+                        mpk[i] = pk | (u32)ts | ((u32)td << 10);
+                    }
+                }
+                wave_sync();
+                for (int i = lane; i < k; i += kWave) {
+                    const i32 q = mq[i];
+                    const u32 pk = mpk[i];
+                    const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
+                    i32 x[2], xi[2];
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        i32 acc = 0, acci = 0;
+                        i32 idx = thead[side ? td : ts];
+                        while (idx >= 0) {
+                            const i32 lk = ev[idx];
+                            const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
+                            acc += sg;
+                            acci += sg * (lk & 1);
+                            idx = (lk >> 1) - 1;
+                        }
+                        x[side] = acc;
+                        xi[side] = acci;
+                    }
+                    const u32 c0s = tcnt[ts], c0d = tcnt[td];
+                    const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
+                    const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
+                    const i32 cis = (i32)(c0s >> 16) + xi[0];
+                    const i32 cid = (i32)(c0d >> 16) + xi[1];
+                    const i32 di = (i32)((pk >> 30) & 1u);
+                    const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) |
+                                     ((u32)(di & (int)(cis == 1)) << 2) | ((u32)(di & (int)(cid == 0)) << 3);
+                    code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
+                }
+            }
+            acc_bytes += inseq_edge_bytes(card, L, k);
+            wave_sync();
+            // reset the slots this h-edge used: its row parts and its movers' parts
+#pragma unroll
+            for (int u = 0; u < kInseqU; ++u) {
+                const i32 r = u * kWave + lane;
+                if (r < L) {
+                    tkey[rslot[r]] = -1;
+                    thead[rslot[r]] = -1;
+                }
+            }
             for (int i = lane; i < k; i += kWave) {
-                const i32 q = mq[i];
                 const u32 pk = mpk[i];
                 const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
-                i32 x[2], xi[2];
-#pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    i32 acc = 0, acci = 0;
-                    i32 idx = thead[side ? td : ts];
-                    while (idx >= 0) {
-                        const i32 lk = ev[idx];
-                        const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
-                        acc += sg;
-                        acci += sg * (lk & 1);
-                        idx = (lk >> 1) - 1;
-                    }
-                    x[side] = acc;
-                    xi[side] = acci;
-                }
-                const u32 c0s = tcnt[ts], c0d = tcnt[td];
-                const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
-                const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
-                const i32 cis = (i32)(c0s >> 16) + xi[0];
-                const i32 cid = (i32)(c0d >> 16) + xi[1];
-                const i32 di = (i32)((pk >> 30) & 1u);
-                const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
-                                 ((u32)(di & (int)(cid == 0)) << 3);
-                code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
+                tkey[ts] = -1;
+                thead[ts] = -1;
+                tkey[td] = -1;
+                thead[td] = -1;
             }
+            wave_sync();
         }
-        acc_bytes += inseq_edge_bytes(card, L, k);
-        wave_sync();
-        // reset the slots this h-edge used: its row parts and its movers' parts
-#pragma unroll
-        for (int u = 0; u < kInseqU; ++u) {
-            const i32 r = u * kWave + lane;
-            if (r < L) {
-                tkey[rslot[r]] = -1;
-                thead[rslot[r]] = -1;
-            }
-        }
-        for (int i = lane; i < k; i += kWave) {
-            const u32 pk = mpk[i];
-            const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
-            tkey[ts] = -1;
-            thead[ts] = -1;
-            tkey[td] = -1;
-            thead[td] = -1;
-        }
-        wave_sync();
     }
     if ((bytes != nullptr) & (lane == 0) & (acc_bytes != 0)) atomicAdd(bytes, (unsigned long long)acc_bytes);
+}
+
+// The same outcome bytes for h-edges of at most kInseqSmall pins, one lane per
+// h-edge, everything in registers: a mover's counts of p_s and p_d just before
+// it moves are the row counts plus the moves of the h-edge's earlier movers,
+// compared all pairs (at most kInseqSmall^2 per h-edge).
+constexpr int kInseqSmall = 8;
+
+__global__ __launch_bounds__(256) void k_inseq_small(
+    i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
+    const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
+    const i32* __restrict__ len, unsigned char* code, const i32* __restrict__ elist, const u32* __restrict__ ecount,
+    unsigned long long* bytes) {
+    constexpr int S = kInseqSmall;
+    const i64 ne = elist ? (i64)*ecount : (i64)E;
+    u64 acc = 0;
+    for (i64 ie = (i64)blockIdx.x * blockDim.x + threadIdx.x; ie < ne; ie += (i64)gridDim.x * blockDim.x) {
+        const i64 e = elist ? (i64)elist[ie] : ie;
+        const i64 a = he_off[e], b = he_off[e + 1];
+        const i32 card = (i32)(b - a);
+        if ((card <= 0) | (card > S)) continue;
+        const i64 d0 = a + he_nsrc[e];
+        const i32 L = len[e];
+        i32 m[S], q[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) m[j] = pins[a + (j < card ? j : 0)];
+#pragma unroll
+        for (int j = 0; j < S; ++j) q[j] = j < card ? posn[m[j]] : 0x7FFFFFFF;
+        int nmv = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) nmv += (int)(q[j] < M);
+        if (nmv > 0) {
+            i32 ps[S], pd[S], rp[S];
+            u32 rc[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const int mv = (int)(q[j] < M);
+                ps[j] = mv ? rho[m[j]] : -1;
+                pd[j] = mv ? move_dst[m[j]] : -1;
+            }
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                const i64 ri = a + (r < L ? r : 0);
+                const i32 pr = part[ri];
+                const u32 cr = (u32)cnt[ri] | ((u32)cin[ri] << 16);
+                rp[r] = r < L ? pr : -1;
+                rc[r] = r < L ? cr : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (q[j] < M) {
+                    i32 xs = 0, xd = 0, xis = 0, xid = 0;
+#pragma unroll
+                    for (int o = 0; o < S; ++o) {
+                        const i32 before = (i32)(q[o] < q[j]);
+                        const i32 dj = (i32)(a + o >= d0);
+                        const i32 es = before * ((i32)(pd[o] == ps[j]) - (i32)(ps[o] == ps[j]));
+                        const i32 ed = before * ((i32)(pd[o] == pd[j]) - (i32)(ps[o] == pd[j]));
+                        xs += es;
+                        xd += ed;
+                        xis += dj * es;
+                        xid += dj * ed;
+                    }
+                    u32 c0s = 0, c0d = 0;
+#pragma unroll
+                    for (int r = 0; r < S; ++r) {
+                        c0s = rp[r] == ps[j] ? rc[r] : c0s;
+                        c0d = rp[r] == pd[j] ? rc[r] : c0d;
+                    }
+                    const i32 cs = (i32)(c0s & 0xFFFFu) + xs;
+                    const i32 cd = (i32)(c0d & 0xFFFFu) + xd;
+                    const i32 cis = (i32)(c0s >> 16) + xis;
+                    const i32 cid = (i32)(c0d >> 16) + xid;
+                    const i32 di = (i32)(a + j >= d0);
+                    const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
+                                     ((u32)(di & (int)(cid == 0)) << 3);
+                    code[a + j] = (unsigned char)bits;
+                }
+            }
+        }
+        acc += inseq_edge_bytes(card, nmv ? L : 0, nmv);
+    }
+    const u64 tot = bytes != nullptr ? (u64)wave_sum((i64)acc) : 0;
+    if ((bytes != nullptr) & (lane_id() == 0) & (tot != 0)) atomicAdd(bytes, (unsigned long long)tot);
 }
 
 // In-sequence gains, mover side: one wave per sequence position q sums the
@@ -1982,11 +2164,16 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         int tbits = 1;
         while ((1 << tbits) < 2 * capl) ++tbits;
         const size_t lds_l = (size_t)24 * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
-        LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave, lds_l, L.E,
-               (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl,
-               tbits, (const i32*)elist2, (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
+        LAUNCH(c, KF_INSEQ, k_inseq_small, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, (i32)M, L.he_off(),
+               L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, (const i32*)elist2,
+               (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
+        if (cap > kInseqSmall)
+            LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32),
+                   kWave, lds_l, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt,
+                   f.cin, f.len, code, capl, tbits, kInseqSmall, (const i32*)elist2, (const u32*)(ecount + 1),
+                   prof_bytes(c, KF_INSEQ));
         if (cap > capl)
-            LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(L.E, (i64)c->num_cu * 32), kWave,
+            LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32), kWave,
                    (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn,
                    rho, mdst, f.part, f.cnt, f.cin, f.len, code, cap, (i32)capl, (const i32*)elist2,
                    (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
