@@ -642,11 +642,11 @@ __global__ __launch_bounds__(256) void k_propose_hash(
                     const i32 avg = tot / max(nb, 1);
                     const u32 bm = (u32)(B - 1), ps = (u32)pass;
                     if (avg <= 64)
-                        hash_group<16, 1>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
+                        hash_group<8, 1>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
                     else if (avg <= 128)
-                        hash_group<8, 2>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
+                        hash_group<4, 2>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
                     else
-                        hash_group<4, 4>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
+                        hash_group<2, 4>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
                 }
                 if (Q.count > 0) miss_drain(Q, Q.count, T);  // the rest of the wave's misses
                 __syncthreads();
@@ -1092,13 +1092,21 @@ void launch_propose_hash(Ctx* c, const Level& L, int Pi, const unsigned long lon
                          u64* score) {
     const int C = 1 << (c->opt.tune[0] ? c->opt.tune[0] : 12);  // slots; shared memory = C * (8 + sizeof(BIN)) B
     const size_t lds = (size_t)C * (8 + sizeof(BIN));
-    // as many blocks as are resident at once (shared memory, at most 4 per CU
-    // by registers): a second, partial round of blocks would leave most of the
-    // chip idle while it runs
-    // (registers hold the kernel to 3 waves per SIMD with 32-bit bins, 2 with 64-bit)
-    const int per_cu = std::max(1, std::min(sizeof(BIN) == 4 ? 3 : 2,
-                                            (int)(160 * 1024 / (lds + (sizeof(BIN) == 4 ? 5 : 7) * 1024))));
-    const int grid = std::min<i64>(L.N, (i64)c->num_cu * per_cu);
+    // as many blocks as are resident at once (registers and shared memory, as
+    // the runtime's occupancy query gives them): a second, partial round of
+    // blocks would leave most of the chip idle while it runs
+    int per_cu = 0;
+#define HGP_PROPH_OCC(PIV)                                                                                         \
+    case PIV:                                                                                                      \
+        HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propose_hash<BIN, PIV>, 256, lds));          \
+        break;
+    switch (Pi) {
+        HGP_PROPH_OCC(1) HGP_PROPH_OCC(2) HGP_PROPH_OCC(3) HGP_PROPH_OCC(4) HGP_PROPH_OCC(5) HGP_PROPH_OCC(6)
+        HGP_PROPH_OCC(7) HGP_PROPH_OCC(8)
+        default: fail(HGP_E_INVALID, "pi must be in 1..8");
+    }
+#undef HGP_PROPH_OCC
+    const int grid = std::min<i64>(L.N, (i64)c->num_cu * std::max(1, per_cu));
 #define HGP_PROPH(PIV)                                                                                             \
     case PIV:                                                                                                      \
         LAUNCH(c, KF_PROPOSE, (k_propose_hash<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(),          \

@@ -539,6 +539,76 @@ __device__ __forceinline__ void gains_chunk(i32 avg, int nb, int lane, i32 ps, i
         gains_group<4, 4, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
 }
 
+// A node of at most CH * 64 incident h-edges with all its loads issued
+// together: incidence, then offsets, lengths and weights, then (rows of at
+// most kGainsFlatRow entries) every row entry, three rounds in all; the next
+// node's scalars are prefetched behind the incidence loads.  Longer rows go
+// through gains_chunk per 64 h-edges.
+template <int CH>
+__device__ __forceinline__ void gains_flat(i64 a, i64 b, int lane, i32 ps, i32 nparts, const i32* __restrict__ inc,
+                                           const i64* __restrict__ he_off, const unsigned short* __restrict__ partf,
+                                           const i32* __restrict__ len, const i32* __restrict__ hw, i64& saving,
+                                           i64& wi, u64& visits, u32* bins, Touched tt, i64 n2, i32 N,
+                                           const i32* __restrict__ rho, const i64* __restrict__ inc_off,
+                                           const i32* __restrict__ nw, i32& ps_n, i64& a_n, i64& b_n, i64& nw_nn) {
+    i32 ee[CH], LL[CH], ww[CH];
+    i64 rr[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const i64 k = a + u * kWave + lane;
+        ee[u] = inc[k < b ? k : a];
+    }
+    if (n2 < N) {
+        ps_n = rho[n2];
+        a_n = inc_off[n2];
+        b_n = inc_off[n2 + 1];
+        nw_nn = nw[n2];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        rr[u] = he_off[ee[u]];
+        LL[u] = len[ee[u]];
+        ww[u] = hw[ee[u]];
+    }
+    i32 lmax = 0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int in = (int)(a + u * kWave + lane < b);
+        LL[u] = in ? LL[u] : 0;
+        ww[u] = in ? ww[u] : 0;
+        wi += ww[u];
+        lmax = max(lmax, LL[u]);
+    }
+    lmax = wave_max(lmax);
+    if (lmax <= kGainsFlatRow) {
+        // every lane loads; entries past a row read its first entry (a row of
+        // an h-edge holding n is never empty) and are dropped at use
+        u32 pp[CH][kGainsFlatRow];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int v = 0; v < kGainsFlatRow; ++v) pp[u][v] = (u32)partf[rr[u] + (v < LL[u] ? v : 0)];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            visits += (u64)LL[u];
+#pragma unroll
+            for (int v = 0; v < kGainsFlatRow; ++v)
+                gains_entry<true, true>(v < LL[u] ? pp[u][v] : 0xFFFFFFFFu, (u32)ww[u], 0, ps, 0, nparts, saving,
+                                        bins, tt);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int nb = (int)min((i64)kWave, b - (a + u * kWave));
+            if (nb > 0) {
+                const i32 tot = wave_sum(LL[u]);
+                visits += (u64)LL[u];
+                gains_chunk(tot / nb, nb, lane, ps, nparts, partf, rr[u], LL[u], ww[u], saving, bins, tt);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     i32 N, i32 nparts, const i64* __restrict__ inc_off, const i32* __restrict__ inc, const i64* __restrict__ he_off,
     const unsigned short* __restrict__ partf, const i32* __restrict__ len, const i32* __restrict__ hw,
@@ -572,73 +642,19 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
         i64 saving = 0, wi = 0;
         const i64 deg = b - a;
         const bool flat = (deg > 0) & (deg <= kGainsFlatChunks * kWave);
+        const i64 n2 = n + stride;  // the next node's scalars, behind this node's first loads
         if (flat) {
-            // All of the node's h-edges at once: incidence, then offsets,
-            // lengths and weights, then (rows of at most kGainsFlatRow entries)
-            // every row entry; three rounds of loads in all.
-            i32 ee[kGainsFlatChunks], LL[kGainsFlatChunks], ww[kGainsFlatChunks];
-            i64 rr[kGainsFlatChunks];
-#pragma unroll
-            for (int u = 0; u < kGainsFlatChunks; ++u) {
-                const i64 k = a + u * kWave + lane;
-                ee[u] = inc[k < b ? k : a];
-            }
-            const i64 n2 = n + stride;  // prefetch behind the incidence loads
-            if (n2 < N) {
-                ps_n = rho[n2];
-                a_n = inc_off[n2];
-                b_n = inc_off[n2 + 1];
-                nw_nn = nw[n2];
-            }
-#pragma unroll
-            for (int u = 0; u < kGainsFlatChunks; ++u) {
-                rr[u] = he_off[ee[u]];
-                LL[u] = len[ee[u]];
-                ww[u] = hw[ee[u]];
-            }
-            i32 lmax = 0;
-#pragma unroll
-            for (int u = 0; u < kGainsFlatChunks; ++u) {
-                const int in = (int)(a + u * kWave + lane < b);
-                LL[u] = in ? LL[u] : 0;
-                ww[u] = in ? ww[u] : 0;
-                wi += ww[u];
-                lmax = max(lmax, LL[u]);
-            }
-            lmax = wave_max(lmax);
-            if (lmax <= kGainsFlatRow) {
-                u32 pp[kGainsFlatChunks][kGainsFlatRow];
-#pragma unroll
-                for (int u = 0; u < kGainsFlatChunks; ++u)
-#pragma unroll
-                    for (int v = 0; v < kGainsFlatRow; ++v)
-                        pp[u][v] = v < LL[u] ? (u32)partf[rr[u] + v] : 0xFFFFFFFFu;
-#pragma unroll
-                for (int u = 0; u < kGainsFlatChunks; ++u) {
-                    visits += (u64)LL[u];
-#pragma unroll
-                    for (int v = 0; v < kGainsFlatRow; ++v)
-                        gains_entry<true, true>(pp[u][v], (u32)ww[u], 0, ps, 0, nparts, saving, bins, tt);
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < kGainsFlatChunks; ++u) {
-                    const int nb = (int)min((i64)kWave, b - (a + u * kWave));
-                    if (nb > 0) {
-                        const i32 tot = wave_sum(LL[u]);
-                        visits += (u64)LL[u];
-                        gains_chunk(tot / nb, nb, lane, ps, nparts, partf, rr[u], LL[u], ww[u], saving, bins, tt);
-                    }
-                }
-            }
-        } else {
-            const i64 n2 = n + stride;
-            if (n2 < N) {
-                ps_n = rho[n2];
-                a_n = inc_off[n2];
-                b_n = inc_off[n2 + 1];
-                nw_nn = nw[n2];
-            }
+            if (deg <= 2 * kWave)
+                gains_flat<2>(a, b, lane, ps, nparts, inc, he_off, partf, len, hw, saving, wi, visits, bins, tt, n2,
+                              N, rho, inc_off, nw, ps_n, a_n, b_n, nw_nn);
+            else
+                gains_flat<kGainsFlatChunks>(a, b, lane, ps, nparts, inc, he_off, partf, len, hw, saving, wi, visits,
+                                             bins, tt, n2, N, rho, inc_off, nw, ps_n, a_n, b_n, nw_nn);
+        } else if (n2 < N) {
+            ps_n = rho[n2];
+            a_n = inc_off[n2];
+            b_n = inc_off[n2 + 1];
+            nw_nn = nw[n2];
         }
         for (i64 kb = flat ? b : a; kb < b; kb += kWave) {
             const int nb = (int)min((i64)kWave, b - kb);
