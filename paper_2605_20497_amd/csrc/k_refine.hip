@@ -1241,6 +1241,7 @@ struct MoverRec {
     i32 q, ps, pd, slot;  // slot = (pin offset in e) << 1 | destination flag
 };
 constexpr int kInseqListMax = 256;  // largest h-edge of the event-list kernel
+constexpr int kInseqGroup = 64;     // largest h-edge of its 16-lane groups
 constexpr int kInseqU = 4;          // row entries / pins per lane loaded together
 
 __device__ __forceinline__ i32 lds_row(const i32* __restrict__ rp, const u32* __restrict__ rc, i32 L, i32 p,
@@ -1380,43 +1381,49 @@ __device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inser
     return -1;  // unreachable: the table has a slot for every part of 2 * cap movers
 }
 
-// Shared memory of the wave: per mover its sequence position, node and
-// packed (source slot | destination slot << 10 | pin slot << 20 | destination
-// pin << 30); per row entry its table slot; the table (keys, list heads,
-// packed row counts); one 32-bit link per event: ((next event + 1) << 1) |
-// destination-pin flag, where event 2i leaves mover i's source part and
-// 2i + 1 enters its destination part.  20 bytes per mover slot and 12 per
-// table slot.
+// Shared memory of a lane group (GW lanes, one h-edge at a time): per mover
+// its sequence position, node and packed (source slot | destination slot << 10
+// | pin slot << 20 | destination pin << 30); per row entry its table slot; the
+// table (keys, list heads, packed row counts); one 32-bit link per event:
+// ((next event + 1) << 1) | destination-pin flag, where event 2i leaves mover
+// i's source part and 2i + 1 enters its destination part.  24 bytes per mover
+// slot and 12 per table slot.
 //
-// Latency: the wave takes its h-edges 64 list entries at a time, reading their
-// offsets, source counts and row lengths one per lane and keeping (by ballot)
-// those of more than `small` and at most cap pins; the smaller ones belong to
-// k_inseq_small.  Per kept h-edge every global load is issued unconditionally,
-// out-of-range lanes reading entry 0 of the same h-edge, so each dependent
-// step (row and pins, positions, the movers' partitions) is one round trip.
-// The table is cleared once; each h-edge resets the slots it used.  One wave
-// per block, so wave-level fences order shared memory.
-__global__ __launch_bounds__(64) void k_inseq_edges_lists(
+// A wave takes its h-edges 64 list entries at a time, reading their offsets,
+// source counts and row lengths one per lane and keeping (by ballot) those of
+// more than `lo` and at most cap pins; its 64 / GW lane groups then handle
+// them GW at a time, each group its own h-edge with its own shared memory.
+// Every global load of an h-edge is issued unconditionally (out-of-range lanes
+// read entry 0 of the same h-edge, an idle group the first pin slot), so each
+// dependent step (row and pins, positions, the movers' partitions) is one
+// round trip.  The table is cleared once; each h-edge resets the slots it
+// used.  One wave per block, so wave-level fences order shared memory.
+template <int GW>
+__global__ __launch_bounds__(64) void k_inseq_lists(
     i32 E, i32 M, const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ posn, const i32* __restrict__ rho, const i32* __restrict__ move_dst,
     const i32* __restrict__ part, const i32* __restrict__ cnt, const i32* __restrict__ cin,
-    const i32* __restrict__ len, unsigned char* code, int cap, int tbits, int small, const i32* __restrict__ elist,
+    const i32* __restrict__ len, unsigned char* code, int cap, int tbits, int lo, const i32* __restrict__ elist,
     const u32* __restrict__ ecount, unsigned long long* bytes) {
+    constexpr int NG = kWave / GW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ i32 s_list[kWave];
     const int T = 1 << tbits;
-    u64 acc_bytes = 0;
-    i32* mq = (i32*)smem_raw;          // cap
-    i32* mnode = mq + cap;             // cap
-    u32* mpk = (u32*)(mnode + cap);    // cap
-    i32* rslot = (i32*)(mpk + cap);    // cap
-    i32* tkey = rslot + cap;           // T
-    i32* thead = tkey + T;             // T
-    u32* tcnt = (u32*)(thead + T);     // T
-    i32* ev = (i32*)(tcnt + T);        // 2 * cap
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x, g = lane / GW, gl = lane % GW;
+    const u64 gmask = GW == kWave ? ~0ull : (((1ull << GW) - 1ull) << (g * GW));
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const u64 glt = lt_mask & gmask;
+    i32* mq = (i32*)smem_raw + (size_t)g * (6 * cap + 3 * T);  // cap
+    i32* mnode = mq + cap;                                       // cap
+    u32* mpk = (u32*)(mnode + cap);                              // cap
+    i32* rslot = (i32*)(mpk + cap);                              // cap
+    i32* tkey = rslot + cap;                                     // T
+    i32* thead = tkey + T;                                       // T
+    u32* tcnt = (u32*)(thead + T);                               // T
+    i32* ev = (i32*)(tcnt + T);                                  // 2 * cap
+    u64 acc_bytes = 0;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    for (int t = lane; t < T; t += kWave) {
+    for (int t = gl; t < T; t += GW) {
         tkey[t] = -1;
         thead[t] = -1;
     }
@@ -1427,20 +1434,30 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
         const i64 al = he_off[el], bl = he_off[el + 1];
         const i32 nsl = he_nsrc[el], Ll = len[el];
         const i32 cardl = (i32)(bl - al);
-        u64 todo = __ballot((int)(il < ne) & (int)(cardl > small) & (int)(cardl <= cap));
-        while (todo) {
-            const int src = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const i64 a = __shfl(al, src, kWave);
-            const i32 card = __shfl(cardl, src, kWave);
-            const i64 d0 = a + __shfl(nsl, src, kWave);
-            const i32 L = __shfl(Ll, src, kWave);
+        const int mine = (int)(il < ne) & (int)(cardl > lo) & (int)(cardl <= cap);
+        const u64 todo = __ballot(mine);
+        const int nt = __popcll(todo);
+        if (mine) s_list[__popcll(todo & lt_mask)] = lane;
+        wave_sync();
+        for (int r0 = 0; r0 < nt; r0 += NG) {
+            const int act = (int)(r0 + g < nt);
+            const int src = s_list[act ? r0 + g : 0];
+            // the shuffles run on every lane (a lane left out of a shuffle
+            // cannot serve as another group's source), then idle groups
+            // take an empty h-edge at pin slot 0
+            const i64 a_s = __shfl(al, src, kWave);
+            const i32 card_s = __shfl(cardl, src, kWave), ns_s = __shfl(nsl, src, kWave);
+            const i32 L_s = __shfl(Ll, src, kWave);
+            const i64 a = act ? a_s : 0;
+            const i32 card = act ? card_s : 0;
+            const i64 d0 = a + ns_s;
+            const i32 L = act ? L_s : 0;
             // row entries and pins, then the pins' sequence positions
             i32 pp[kInseqU], mm[kInseqU], qq[kInseqU];
             u32 cc[kInseqU];
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i32 r = u * kWave + lane;
+                const i32 r = u * GW + gl;
                 const i64 ri = a + (r < L ? r : 0);
                 pp[u] = part[ri];
                 cc[u] = (u32)cnt[ri] | ((u32)cin[ri] << 16);  // both <= |e| <= 4096
@@ -1451,7 +1468,7 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
             // e's row parts with their counts (distinct parts)
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i32 r = u * kWave + lane;
+                const i32 r = u * GW + gl;
                 if (r < L) {
                     int ins;
                     const i32 t = part_slot(tkey, tbits, pp[u], ins);
@@ -1459,15 +1476,15 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
                     rslot[r] = t;
                 }
             }
-            // movers, indexed by ballot
+            // movers, indexed by the group's ballot bits
             int k = 0;
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i32 j = u * kWave + lane;
+                const i32 j = u * GW + gl;
                 const int is_mv = (int)(j < card) & (int)(qq[u] < M);
-                const u64 mask = __ballot(is_mv);
+                const u64 mask = __ballot(is_mv) & gmask;
                 if (is_mv) {
-                    const i32 i = k + __popcll(mask & lt_mask);
+                    const i32 i = k + __popcll(mask & glt);
                     mq[i] = qq[u];
                     mnode[i] = mm[u];
                     mpk[i] = (u32)j << 20 | ((u32)(a + j >= d0) << 30);
@@ -1475,79 +1492,78 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
                 k += __popcll(mask);
             }
             wave_sync();
-            if (k > 0) {
-                // the movers' partitions, one lane per mover, then their table
-                // slots (a source part is in the row; a destination part may be
-                // new, with no pins in e) and their two events on the parts' lists
-                i32 ps[kInseqU], pd[kInseqU];
+            // the movers' partitions, one lane per mover, then their table
+            // slots (a source part is in the row; a destination part may be
+            // new, with no pins in e) and their two events on the parts' lists
+            i32 ps[kInseqU], pd[kInseqU];
 #pragma unroll
-                for (int u = 0; u < kInseqU; ++u) {
-                    const i32 i = u * kWave + lane;
-                    const i32 nd = mnode[i < k ? i : 0];
-                    ps[u] = rho[nd];
-                    pd[u] = move_dst[nd];
-                }
+            for (int u = 0; u < kInseqU; ++u) {
+                const i32 i = u * GW + gl;
+                const i32 nd0 = mnode[i < k ? i : 0];
+                const i32 nd = k > 0 ? nd0 : 0;  // node 0 when the group has no mover
+                ps[u] = rho[nd];
+                pd[u] = move_dst[nd];
+            }
 #pragma unroll
-                for (int u = 0; u < kInseqU; ++u) {
-                    const i32 i = u * kWave + lane;
-                    if (i < k) {
-                        int ins_s, ins_d;
-                        const i32 ts = part_slot(tkey, tbits, ps[u], ins_s);
-                        const i32 td = part_slot(tkey, tbits, pd[u], ins_d);
-                        if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
-                        if (ins_d) tcnt[td] = 0u;
-                        const u32 pk = mpk[i];
-                        const i32 dj = (i32)((pk >> 30) & 1u);
-                        const i32 hs = atomicExch(&thead[ts], 2 * i);
-                        const i32 hd = atomicExch(&thead[td], 2 * i + 1);
-                        ev[2 * i] = ((hs + 1) << 1) | dj;
-                        ev[2 * i + 1] = ((hd + 1) << 1) | dj;
-                        mpk[i] = pk | (u32)ts | ((u32)td << 10);
-                    }
-                }
-                wave_sync();
-                for (int i = lane; i < k; i += kWave) {
-                    const i32 q = mq[i];
+            for (int u = 0; u < kInseqU; ++u) {
+                const i32 i = u * GW + gl;
+                if (i < k) {
+                    int ins_s, ins_d;
+                    const i32 ts = part_slot(tkey, tbits, ps[u], ins_s);
+                    const i32 td = part_slot(tkey, tbits, pd[u], ins_d);
+                    if (ins_s) tcnt[ts] = 0u;  // not reached: p_s has a pin of e in the row
+                    if (ins_d) tcnt[td] = 0u;
                     const u32 pk = mpk[i];
-                    const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
-                    i32 x[2], xi[2];
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        i32 acc = 0, acci = 0;
-                        i32 idx = thead[side ? td : ts];
-                        while (idx >= 0) {
-                            const i32 lk = ev[idx];
-                            const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
-                            acc += sg;
-                            acci += sg * (lk & 1);
-                            idx = (lk >> 1) - 1;
-                        }
-                        x[side] = acc;
-                        xi[side] = acci;
-                    }
-                    const u32 c0s = tcnt[ts], c0d = tcnt[td];
-                    const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
-                    const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
-                    const i32 cis = (i32)(c0s >> 16) + xi[0];
-                    const i32 cid = (i32)(c0d >> 16) + xi[1];
-                    const i32 di = (i32)((pk >> 30) & 1u);
-                    const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) |
-                                     ((u32)(di & (int)(cis == 1)) << 2) | ((u32)(di & (int)(cid == 0)) << 3);
-                    code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
+                    const i32 dj = (i32)((pk >> 30) & 1u);
+                    const i32 hs = atomicExch(&thead[ts], 2 * i);
+                    const i32 hd = atomicExch(&thead[td], 2 * i + 1);
+                    ev[2 * i] = ((hs + 1) << 1) | dj;
+                    ev[2 * i + 1] = ((hd + 1) << 1) | dj;
+                    mpk[i] = pk | (u32)ts | ((u32)td << 10);
                 }
             }
-            acc_bytes += inseq_edge_bytes(card, L, k);
+            wave_sync();
+            for (int i = gl; i < k; i += GW) {
+                const i32 q = mq[i];
+                const u32 pk = mpk[i];
+                const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
+                i32 x[2], xi[2];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    i32 sacc = 0, sacci = 0;
+                    i32 idx = thead[side ? td : ts];
+                    while (idx >= 0) {
+                        const i32 lk = ev[idx];
+                        const i32 sg = (i32)(mq[idx >> 1] < q) * ((idx & 1) ? 1 : -1);
+                        sacc += sg;
+                        sacci += sg * (lk & 1);
+                        idx = (lk >> 1) - 1;
+                    }
+                    x[side] = sacc;
+                    xi[side] = sacci;
+                }
+                const u32 c0s = tcnt[ts], c0d = tcnt[td];
+                const i32 cs = (i32)(c0s & 0xFFFFu) + x[0];
+                const i32 cd = (i32)(c0d & 0xFFFFu) + x[1];
+                const i32 cis = (i32)(c0s >> 16) + xi[0];
+                const i32 cid = (i32)(c0d >> 16) + xi[1];
+                const i32 di = (i32)((pk >> 30) & 1u);
+                const u32 bits = (u32)(cs == 1) | ((u32)(cd == 0) << 1) | ((u32)(di & (int)(cis == 1)) << 2) |
+                                 ((u32)(di & (int)(cid == 0)) << 3);
+                code[a + ((pk >> 20) & 1023u)] = (unsigned char)bits;
+            }
+            if ((gl == 0) & act) acc_bytes += inseq_edge_bytes(card, L, k);
             wave_sync();
             // reset the slots this h-edge used: its row parts and its movers' parts
 #pragma unroll
             for (int u = 0; u < kInseqU; ++u) {
-                const i32 r = u * kWave + lane;
+                const i32 r = u * GW + gl;
                 if (r < L) {
                     tkey[rslot[r]] = -1;
                     thead[rslot[r]] = -1;
                 }
             }
-            for (int i = lane; i < k; i += kWave) {
+            for (int i = gl; i < k; i += GW) {
                 const u32 pk = mpk[i];
                 const i32 ts = (i32)(pk & 1023u), td = (i32)((pk >> 10) & 1023u);
                 tkey[ts] = -1;
@@ -1558,7 +1574,8 @@ __global__ __launch_bounds__(64) void k_inseq_edges_lists(
             wave_sync();
         }
     }
-    if ((bytes != nullptr) & (lane == 0) & (acc_bytes != 0)) atomicAdd(bytes, (unsigned long long)acc_bytes);
+    const u64 tot = bytes != nullptr ? (u64)wave_sum((i64)acc_bytes) : 0;
+    if ((bytes != nullptr) & (lane == 0) & (tot != 0)) atomicAdd(bytes, (unsigned long long)tot);
 }
 
 // The same outcome bytes for h-edges of at most kInseqSmall pins, one lane per
@@ -2174,20 +2191,34 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
             LAUNCH(c, KF_INSEQ, k_mark_edges, grid_for(M, 4, c->num_cu * 16), 256, 0, (i32)M, (const i32*)seqn,
                    L.inc_off(), L.inc(), emark, 2u, elist2, ecount + 1);
         }
-        // Event lists for h-edges of up to kInseqListMax pins, all pairs beyond.
+        // H-edges of at most kInseqSmall pins one lane each; event lists for
+        // up to kInseqGroup pins in 16-lane groups, up to kInseqListMax in whole
+        // waves; all pairs beyond.
         const int cap = std::max(1, c->max_card);
         const int capl = std::min(cap, kInseqListMax);
-        int tbits = 1;
-        while ((1 << tbits) < 2 * capl) ++tbits;
-        const size_t lds_l = (size_t)24 * capl + (size_t)3 * sizeof(i32) * ((size_t)1 << tbits);
+        auto table_bits = [](int pins_max) {
+            int tb = 1;
+            while ((1 << tb) < 2 * pins_max) ++tb;
+            return tb;
+        };
         LAUNCH(c, KF_INSEQ, k_inseq_small, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, (i32)M, L.he_off(),
                L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, (const i32*)elist2,
                (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
-        if (cap > kInseqSmall)
-            LAUNCH(c, KF_INSEQ, k_inseq_edges_lists, std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32),
-                   kWave, lds_l, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt,
-                   f.cin, f.len, code, capl, tbits, kInseqSmall, (const i32*)elist2, (const u32*)(ecount + 1),
-                   prof_bytes(c, KF_INSEQ));
+        const int nbw = (int)std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32);
+        if (cap > kInseqSmall) {
+            const int capg = std::min(cap, kInseqGroup), tbg = table_bits(capg);
+            const size_t lds_g = (size_t)(kWave / 16) * ((size_t)24 * capg + (size_t)12 * ((size_t)1 << tbg));
+            LAUNCH(c, KF_INSEQ, k_inseq_lists<16>, nbw, kWave, lds_g, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(),
+                   posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capg, tbg, kInseqSmall, (const i32*)elist2,
+                   (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
+        }
+        if (cap > kInseqGroup) {
+            const int tbl = table_bits(capl);
+            const size_t lds_l = (size_t)24 * capl + (size_t)12 * ((size_t)1 << tbl);
+            LAUNCH(c, KF_INSEQ, k_inseq_lists<64>, nbw, kWave, lds_l, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(),
+                   posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, capl, tbl, kInseqGroup, (const i32*)elist2,
+                   (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
+        }
         if (cap > capl)
             LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32), kWave,
                    (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn,

@@ -52,6 +52,33 @@ GAINS_VARIANTS = {
 }
 
 
+def mixed_size_hypergraph(n, e, seed):
+    """e h-edges over n nodes with sizes cycling through 2-8, 9-64, 65-256
+    and 257-400 pins in a seeded random order, so that each size class of the
+    in-sequence kernels meets windows of 64 h-edges where it holds only a few
+    (and lane groups that stay idle in a window's last round).  One or two
+    sources per h-edge."""
+    rng = np.random.default_rng(seed)
+    bounds = [(2, 8), (9, 64), (65, 256), (257, 400)]
+    weights = np.array([0.55, 0.3, 0.12, 0.03])
+    cls = rng.choice(4, size=e, p=weights)
+    srcs, dsts = [], []
+    for c in cls:
+        lo, hi = bounds[c]
+        card = int(rng.integers(lo, hi + 1))
+        ids = rng.choice(n, size=card, replace=False)
+        ns = 1 + int(rng.integers(0, 2))
+        srcs.append(ids[:ns])
+        dsts.append(ids[ns:])
+    return W._assemble(n, srcs, dsts)
+
+
+def mixed_size_case(seed):
+    hg = _weighted(mixed_size_hypergraph(3000, 6000, 40 + seed), seed)
+    rho = random_partition(hg.n_nodes, 64, seed)
+    return hg, rho, 64
+
+
 def gains_variant(name):
     build, nparts, pseed, weighted = GAINS_VARIANTS[name]
     hg = build()

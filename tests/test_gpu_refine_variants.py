@@ -57,6 +57,34 @@ def test_gains_kernel_variants(name, rep):
     g.close()
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_inseq_size_classes_against_oracle(seed):
+    """H-edges of every in-sequence size class (one lane each up to 8 pins,
+    16-lane groups up to 64, whole waves up to 256, all pairs beyond) mixed in
+    one input, so that windows hold a few h-edges of a class and lane groups
+    stay idle: the repetition matches the oracle, and two runs of it on the
+    device match each other."""
+    from paper_2605_20497_amd import Partitioner
+    hg, rho, P = RC.mixed_size_case(seed)
+    og = oracle.Graph(hg)
+    ev = og.evaluate(rho, P)
+    omega = int(ev["max_size"]) + 2
+    delta = int(ev["max_inbound"]) + 1
+    print("case mixed seed", seed, "N", hg.n_nodes, "P", hg.n_pins, "omega", omega, "delta", delta, flush=True)
+    g = Partitioner()
+    g.load(hg)
+    g.hgp_set_limits(omega, delta, 0)
+    orho, od = og.refine_rep(rho, P, 0, 16, omega, delta)
+    runs = [g.hgp_refine_rep(rho, P, 0) for _ in range(2)]
+    for grho, gd in runs:
+        assert gd["moves"] == od["M"] and gd["kstar"] == od["kstar"]
+        for key in ("seq", "seq_pd", "gseq", "C", "V"):
+            assert np.array_equal(gd[key], od[key]), key
+        assert np.array_equal(grho, orho)
+    assert od["M"] > 100
+    g.close()
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("name", sorted(RC.FULL))
 def test_full_size_refine_rep_against_oracle_digests(name):
