@@ -5,9 +5,14 @@
 // trips.  Here several worker threads each own a context with its own HIP
 // stream and run whole jobs; the streams overlap on the device.  Jobs are
 // admitted in arrival order, when a worker is free and their estimated device
-// footprint fits the budget next to the jobs in flight.  One worker gives the
-// plain one-at-a-time baseline with the same code path.  Each job's result is
-// that of a lone run (the method is deterministic; contexts share nothing).
+// footprint fits the budget next to the jobs in flight.  The footprint is an
+// estimate: a hierarchy's depth is known only once it is built, and a deep one
+// (hundreds of levels) can outgrow it.  A job that runs out of device memory
+// while other jobs are in flight is put back and run again alone, once every
+// other job has finished; only a job that fails alone reports HGP_E_NOMEM.
+// One worker gives the plain one-at-a-time baseline with the same code path.
+// Each job's result is that of a lone run (the method is deterministic;
+// contexts share nothing).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -84,6 +89,8 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
     std::condition_variable cv;
     int64_t next = 0, inflight = 0;
     int running = 0;
+    bool exclusive = false;         // a job put back for lack of memory is running alone
+    std::vector<int64_t> put_back;  // such jobs, waiting for the device to empty
     hgp_status setup = HGP_OK;
     const auto t0 = std::chrono::steady_clock::now();
 
@@ -98,9 +105,23 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
         }
         for (;;) {
             int64_t i;
+            int concurrent = 0;  // jobs in progress, this one included, when it started
+            bool alone = false;  // this run is a put-back job's lone rerun
             {
                 std::unique_lock<std::mutex> lk(mu);
                 for (;;) {
+                    if (exclusive) {  // a lone rerun holds the device
+                        cv.wait(lk);
+                        continue;
+                    }
+                    if (!put_back.empty()) {
+                        if (running > 0) {
+                            cv.wait(lk);
+                            continue;
+                        }
+                        alone = true;
+                        break;
+                    }
                     if (next >= n_jobs) break;
                     const hgp_job& j = jobs[next];
                     const auto due = t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
@@ -115,19 +136,46 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
                     }
                     break;
                 }
-                if (next >= n_jobs) break;
-                i = next++;
+                if (alone) {
+                    i = put_back.back();
+                    put_back.pop_back();
+                    exclusive = true;
+                } else {
+                    if (next >= n_jobs) break;
+                    i = next++;
+                    jobs[i].start_s = seconds_since(t0);  // under the lock: starts follow admission order
+                }
                 ++running;
                 inflight += jobs[i].footprint;
+                concurrent = running;
             }
             hgp_job& j = jobs[i];
-            j.start_s = seconds_since(t0);
             j.status = run_one(ctx, j);
             j.end_s = seconds_since(t0);
+            // Out of memory beside other jobs: free what this job holds and
+            // put it back for a lone rerun (running > 1 at its start or end).
+            bool again = false;
             {
                 std::lock_guard<std::mutex> lk(mu);
+                if (j.status == HGP_E_NOMEM && !alone && (concurrent > 1 || running > 1)) {
+                    put_back.push_back(i);
+                    again = true;
+                }
                 --running;
                 inflight -= j.footprint;
+                if (alone) exclusive = false;
+            }
+            if (again) {
+                // a fresh context: the partial hierarchy and the workspace go
+                hgp_destroy(ctx);
+                ctx = nullptr;
+                const hgp_status rs = hgp_create(&ctx, &o);
+                if (rs != HGP_OK) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    setup = rs;
+                    cv.notify_all();
+                    return;
+                }
             }
             cv.notify_all();
         }

@@ -71,16 +71,29 @@ constexpr int kScanSingleMax = 1 << 16;
 template <typename Tin, typename Tacc, typename Tout>
 __global__ __launch_bounds__(1024) void k_scan_single(const Tin* __restrict__ in, i64 n, Tout* out) {
     __shared__ Tacc red[16];
-    Tacc carry = 0;
-    for (i64 base0 = 0; base0 < n; base0 += 1024 * kScanItems) {
+    constexpr i64 kTile = 1024 * kScanItems;
+    // the next tile's items are loaded before the current tile is scanned;
+    // indices past the end read the last element (n >= 1) and count as 0
+    auto load = [&](i64 base0, Tacc (&v)[kScanItems]) {
         const i64 base = base0 + (i64)threadIdx.x * kScanItems;
-        Tacc v[kScanItems];
-        Tacc s = 0;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            v[k] = (base + k < n) ? (Tacc)in[base + k] : 0;
-            s += v[k];
+            const Tacc x = (Tacc)in[min(base + k, n - 1)];
+            v[k] = base + k < n ? x : (Tacc)0;
         }
+    };
+    Tacc nx[kScanItems];
+    load(0, nx);
+    Tacc carry = 0;
+    for (i64 base0 = 0; base0 < n; base0 += kTile) {
+        Tacc v[kScanItems];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = nx[k];
+        if (base0 + kTile < n) load(base0 + kTile, nx);
+        const i64 base = base0 + (i64)threadIdx.x * kScanItems;
+        Tacc s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) s += v[k];
         Tacc tot;
         Tacc run = carry + block_excl_scan(s, red, &tot);
 #pragma unroll

@@ -82,6 +82,58 @@ __global__ __launch_bounds__(256) void k_part_sizes(i32 N, const i32* __restrict
     if ((bytes != nullptr) & (lane_id() == 0) & (acc != 0)) atomicAdd(bytes, (unsigned long long)acc);
 }
 
+// Partition sizes after the previous repetition applied the first k moves of
+// its sequence: each applied move takes its node's weight from p_s to p_d.
+// Signed counts per block in shared memory when the partition ids fit.
+__global__ __launch_bounds__(256) void k_sizes_moved(i64 k, const i32* __restrict__ seqn,
+                                                     const i32* __restrict__ seqs, const i32* __restrict__ seqd,
+                                                     const i32* __restrict__ nw, i64* psize, int nbins) {
+    extern __shared__ i32 shist[];
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) shist[i] = 0;
+    __syncthreads();
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < k; q += (i64)gridDim.x * blockDim.x) {
+        const i32 w = nw[seqn[q]], ps = seqs[q], pd = seqd[q];
+        if (nbins > 0) {
+            atomicAdd(&shist[ps], -w);
+            atomicAdd(&shist[pd], w);
+        } else {
+            atomicAdd((unsigned long long*)&psize[ps], (unsigned long long)(-(i64)w));
+            atomicAdd((unsigned long long*)&psize[pd], (unsigned long long)(i64)w);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        if (shist[i]) atomicAdd((unsigned long long*)&psize[i], (unsigned long long)(i64)shist[i]);
+}
+
+// sign * |{listed e : pins_in(p,e) > 0}| added to D(p): with the listed
+// h-edges' old rows before they are rebuilt (sign -1) and their new rows after
+// (sign +1), D follows the rebuild without a pass over every row.
+__global__ __launch_bounds__(256) void k_inbound_listed(const i32* __restrict__ elist, const u32* __restrict__ ecount,
+                                                        const i64* __restrict__ he_off, const i32* __restrict__ part,
+                                                        const i32* __restrict__ cin, const i32* __restrict__ len,
+                                                        i64* pD, int nbins, int sign) {
+    extern __shared__ i32 shist[];
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) shist[i] = 0;
+    __syncthreads();
+    const i64 ne = (i64)*ecount;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (i64)gridDim.x * blockDim.x) {
+        const i64 e = elist[i];
+        const i64 a = he_off[e];
+        const i32 L = len[e];
+        for (i32 r = 0; r < L; ++r) {
+            if (cin[a + r] > 0) {
+                const i32 p = part[a + r];
+                if (nbins > 0) atomicAdd(&shist[p], sign);
+                else atomicAdd((unsigned long long*)&pD[p], (unsigned long long)(i64)sign);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        if (shist[i]) atomicAdd((unsigned long long*)&pD[i], (unsigned long long)(i64)shist[i]);
+}
+
 // D(p) = |{e : pins_in(p,e) > 0}| from the rows.  Each wave takes 64 h-edges,
 // one per lane, and walks the concatenation of their rows 64 entries at a
 // time (kRowU loads per lane in flight), so every lane is busy whatever the
@@ -580,6 +632,15 @@ __device__ __forceinline__ void gains_flat(i64 a, i64 b, int lane, i32 ps, i32 n
         lmax = max(lmax, LL[u]);
     }
     lmax = wave_max(lmax);
+    // Every incident h-edge lies in one partition (its row is p_s alone): no
+    // other partition meets n, so n has no move whatever its saving, which is
+    // the outcome of sweeping the rows; they are not read (the work counter
+    // still counts the method's row visits).
+    if (lmax <= 1) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u) visits += (u64)LL[u];
+        return;
+    }
     if (lmax <= kGainsFlatRow) {
         // every lane loads; entries past a row read its first entry (a row of
         // an h-edge holding n is never empty) and are dropped at use
@@ -716,12 +777,30 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
 
 // Lists once each h-edge incident to the nodes nodes[0..cnt): one wave per
 // node over its incidence entries; emark[e] takes `stamp` and the lane that
-// changed it appends e (wave-aggregated appends, order immaterial).
+// changed it appends e (order immaterial).  Appends gather in a per-wave
+// buffer in shared memory and go out kMarkBuf - 64 or more at a time, one
+// atomic on the shared list count per batch: one per 64 entries put the
+// whole device's waves in line on that one address.
+constexpr u32 kMarkBuf = 512;
+
 __global__ __launch_bounds__(256) void k_mark_edges(i32 cnt, const i32* __restrict__ nodes,
                                                     const i64* __restrict__ inc_off, const i32* __restrict__ inc,
                                                     u32* emark, u32 stamp, i32* elist, u32* ecount) {
+    __shared__ i32 buf[4][kMarkBuf];
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
+    i32* wb = buf[wave_id()];
+    const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    u32 nb = 0;  // buffered entries (wave-uniform)
+    auto flush = [&]() {
+        u32 base = 0;
+        if (lane == 0) base = atomicAdd(ecount, nb);
+        base = (u32)__shfl((int)base, 0, kWave);
+        wave_sync();  // the buffer's writes are visible to every lane
+        for (u32 i = lane; i < nb; i += kWave) elist[base + i] = wb[i];
+        wave_sync();  // read out before it is refilled
+        nb = 0;
+    };
     for (i64 j = (i64)blockIdx.x * wpb + wave_id(); j < cnt; j += (i64)gridDim.x * wpb) {
         const i32 n = nodes[j];
         const i64 a = inc_off[n], b = inc_off[n + 1];
@@ -732,12 +811,12 @@ __global__ __launch_bounds__(256) void k_mark_edges(i32 cnt, const i32* __restri
             if (e >= 0) old = atomicExch(&emark[e], stamp);
             const int first = (int)(old != stamp);
             const u64 bal = __ballot(first);
-            u32 base = 0;
-            if (lane == 0 && bal) base = atomicAdd(ecount, (u32)__popcll(bal));
-            base = (u32)__shfl((int)base, 0, kWave);
-            if (first) elist[base + (u32)__popcll(bal & (lane ? (~0ull >> (64 - lane)) : 0ull))] = e;
+            if (first) wb[nb + (u32)__popcll(bal & lt_mask)] = e;
+            nb += (u32)__popcll(bal);
+            if (nb > kMarkBuf - kWave) flush();
         }
     }
+    if (nb > 0) flush();
 }
 
 __global__ void k_move_flags(i32 N, const i32* __restrict__ move_dst, i32* flag) {
@@ -1922,8 +2001,11 @@ PhiBufs phi_bufs(Ctx* c, const Level& L, i32 nparts) {
 // sizes and D(p).  With elist, only the listed h-edges' rows are rebuilt: the
 // others are those of the previous repetition, whose moves left them as they
 // were.
+// With elist, moved_k > 0 moves of the previous repetition were applied (its
+// sequence buffers still hold them): the sizes and D of that repetition are
+// updated from those moves and the listed rows instead of recomputed.
 PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsigned char* single = nullptr,
-                      const i32* elist = nullptr, const u32* ecount = nullptr) {
+                      const i32* elist = nullptr, const u32* ecount = nullptr, i64 moved_k = 0) {
     PhiBufs f;
     f.part = wsp<i32>(c, WS_PHI_PART, (size_t)L.P + 1);
     f.cnt = wsp<i32>(c, WS_PHI_CNT, (size_t)L.P + 1);
@@ -1933,6 +2015,23 @@ PhiBufs phi_and_parts(Ctx* c, const Level& L, const i32* rho, i32 nparts, unsign
     f.pD = wsp<i64>(c, WS_PD, nparts);
     f.part16 = (nparts <= kGainsFlagParts && L.P > 0) ? wsp<unsigned short>(c, WS_PHI_PART16, (size_t)L.P + 1)
                                                        : nullptr;
+    if (elist && moved_k > 0) {
+        const int nbins = nparts <= 16384 ? nparts : 0;  // 64 KiB of shared memory at most
+        const size_t lds = sizeof(i32) * (size_t)nbins;
+        const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 4096))));
+        const int grid = grid_for(L.E, 256, c->num_cu * per_cu);
+        LAUNCH(c, KF_PART_STATS, k_inbound_listed, grid, 256, lds, elist, ecount, L.he_off(), f.part, f.cin, f.len,
+               f.pD, nbins, -1);
+        build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len, single, f.part16, elist, ecount);
+        LAUNCH(c, KF_PART_STATS, k_inbound_listed, grid, 256, lds, elist, ecount, L.he_off(), f.part, f.cin, f.len,
+               f.pD, nbins, 1);
+        const i32* seqn = wsp<i32>(c, WS_SEQN, (size_t)moved_k);
+        const i32* seqs = wsp<i32>(c, WS_SEQS, (size_t)moved_k);
+        const i32* seqd = wsp<i32>(c, WS_SEQD, (size_t)moved_k);
+        LAUNCH(c, KF_PART_STATS, k_sizes_moved, grid_for(moved_k, 256, c->num_cu * per_cu), 256, lds, moved_k, seqn,
+               seqs, seqd, L.nw(), f.psize, nbins);
+        return f;
+    }
     build_phi(c, L, rho, f.part, f.cnt, f.cin, f.len, single, f.part16, elist, ecount);
     fill_many(c, {{f.psize, 2 * (i64)nparts, 0u}, {f.pD, 2 * (i64)nparts, 0u}});
     part_stats(c, L, rho, nparts, f.part, f.cin, f.len, f.psize, f.pD);
@@ -1976,7 +2075,8 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     const bool dense_gains = !reuse && use_dense_gains(c, L, nparts);
     unsigned char* single = dense_gains ? wsp<unsigned char>(c, WS_SINGLE, (size_t)(L.P > 0 ? L.P : 1)) : nullptr;
     PhiBufs f = reuse ? phi_bufs(c, L, nparts)
-                      : phi_and_parts(c, L, rho, nparts, single, incremental ? elist : nullptr, ecount);
+                      : phi_and_parts(c, L, rho, nparts, single, incremental ? elist : nullptr, ecount,
+                                      incremental ? incr_k : 0);
     unsigned long long* rs = wsp<unsigned long long>(c, WS_RSTATS, 8);
     HIPC(hipMemsetAsync(rs, 0, 8 * sizeof(u64), c->stream));
     LAUNCH(c, KF_PART_STATS, k_initial_violations, grid_for(nparts, 256, c->num_cu * 4), 256, 0, nparts, f.psize,

@@ -3,8 +3,10 @@
 // AddressSanitizer.  Each context copies its inputs like the library does,
 // spends time in proportion to the job's pins, and returns a result that is a
 // fixed function of the input (rho[n] = (n * 7 + P) % 13, conn = P), so the
-// driver can check every job's outputs.  Contexts share no state except a
-// counter of live contexts.
+// driver can check every job's outputs.  A job whose delta is kOomDelta runs
+// out of device memory in coarsening when another job was in progress at its
+// load or is at that moment, as a deep hierarchy can beside other jobs.  Contexts share no
+// state except the counters of live contexts and of jobs in progress.
 #include <atomic>
 #include <chrono>
 #include <cstring>
@@ -14,6 +16,9 @@
 #include "../../include/hgp.h"
 
 std::atomic<int> g_live_contexts{0};
+std::atomic<int> g_in_job{0};  // contexts between load and the end of their job
+std::atomic<int> g_oom_returns{0};
+constexpr int64_t kOomDelta = (1 << 20) + 1;
 
 struct hgp_ctx {
     hgp_options opt;
@@ -22,7 +27,8 @@ struct hgp_ctx {
     int32_t N = 0, E = 0;
     int64_t omega = 0, delta = 0;
     int32_t k = 0;
-    bool loaded = false, limited = false, coarsened = false, refined = false;
+    bool loaded = false, limited = false, coarsened = false, refined = false, in_job = false;
+    bool crowded = false;  // another job was in progress when this one was loaded
     std::vector<int32_t> rho;
 };
 
@@ -44,6 +50,7 @@ hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt) {
 
 void hgp_destroy(hgp_ctx* c) {
     if (!c) return;
+    if (c->in_job) g_in_job--;
     g_live_contexts--;
     delete c;
 }
@@ -60,6 +67,8 @@ hgp_status hgp_load_csr(hgp_ctx* c, int32_t n, int32_t e, const int64_t* he_off,
     c->nw = node_w ? std::vector<int32_t>(node_w, node_w + n) : std::vector<int32_t>(n, 1);
     c->loaded = true;
     c->limited = c->coarsened = c->refined = false;
+    if (!c->in_job) c->crowded = ++g_in_job > 1;
+    c->in_job = true;
     return HGP_OK;
 }
 
@@ -76,6 +85,12 @@ hgp_status hgp_set_limits(hgp_ctx* c, int64_t omega, int64_t delta, int32_t k) {
 hgp_status hgp_coarsen(hgp_ctx* c, int32_t* nl) {
     if (!c->limited) return HGP_E_STATE;
     std::this_thread::sleep_for(std::chrono::microseconds(c->pins.size() / 64));
+    if (c->delta == kOomDelta && (c->crowded || g_in_job.load() > 1)) {
+        c->in_job = false;
+        g_in_job--;
+        g_oom_returns++;
+        return HGP_E_NOMEM;
+    }
     *nl = 3;
     c->coarsened = true;
     return HGP_OK;
@@ -104,6 +119,8 @@ hgp_status hgp_evaluate(hgp_ctx* c, const int32_t* rho, int32_t, hgp_eval* out) 
     std::memset(out, 0, sizeof(*out));
     out->conn = (int64_t)c->pins.size();
     out->n_parts = 13;
+    if (c->in_job) g_in_job--;
+    c->in_job = false;
     return HGP_OK;
 }
 

@@ -42,6 +42,7 @@ def test_batch_scheduler_tsan(tmp_path, workers):
     out = _build_run(tmp_path, "batch_tsan", BATCH, ["-fsanitize=thread"], (300, workers),
                      env={"TSAN_OPTIONS": "halt_on_error=1"})
     assert "bad 0" in out
+    assert "put back 0 " not in out  # the put-back path ran
 
 
 def test_batch_scheduler_asan_ubsan(tmp_path):
