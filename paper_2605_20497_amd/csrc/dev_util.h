@@ -77,6 +77,17 @@ __device__ __forceinline__ unsigned long bcast(unsigned long v, int src) {
 
 // Orders shared-memory writes of one wave before later reads of other lanes of
 // the same wave.
+// Work item of round r for workgroup b of a persistent grid of G workgroups.
+// Workgroups go to the 8 XCDs round robin (b to XCD b % 8), so item b of each
+// round would put consecutive items, which share most of their inputs (a
+// node's neighbours, an h-edge's rows), on eight different L2 caches.  Here
+// each XCD takes a contiguous run of G / 8 items per round.  A bijection on
+// each round's G items; grids not a multiple of 8 keep the plain order.
+__device__ __forceinline__ i64 xcd_item(i64 r, int b, int G) {
+    if (G & 7) return r * G + b;
+    return r * G + (i64)(b & 7) * (G >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -283,7 +283,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_propose(
     const int nalloc4 = propose_bins_alloc(R) / kBinsPerVec;
     for (int i = threadIdx.x; i < nalloc4; i += blockDim.x) bins4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+    for (i64 r = 0;; ++r) {
+        const i64 nx = xcd_item(r, blockIdx.x, gridDim.x);  // neighbouring nodes on one XCD
+        if (nx >= N) break;
+        const i32 n = (i32)nx;
         TopList<PI> top;
         top.clear();
         const i64 a = inc_off[n], b = inc_off[n + 1];
@@ -603,7 +606,10 @@ __global__ __launch_bounds__(256) void k_propose_hash(
     }
     __syncthreads();
     u64 Bhint = 1;  // passes the block's previous node needed
-    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+    for (i64 r = 0;; ++r) {
+        const i64 nx = xcd_item(r, blockIdx.x, gridDim.x);  // neighbouring nodes on one XCD
+        if (nx >= N) break;
+        const i32 n = (i32)nx;
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i32 nin_n = inc_nin[n];
         const i64 nw_n = nw[n];

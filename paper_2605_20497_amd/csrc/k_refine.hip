@@ -246,7 +246,10 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains(
     const int npass = (int)((nparts + R - 1) / R);
     for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
     __syncthreads();
-    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+    for (i64 r = 0;; ++r) {
+        const i64 nx = xcd_item(r, blockIdx.x, gridDim.x);  // neighbouring nodes on one XCD
+        if (nx >= N) break;
+        const i32 n = (i32)nx;
         const i32 ps = rho[n];
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i64 deg = b - a;
@@ -467,7 +470,10 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16(
     for (int i = threadIdx.x; i < R; i += blockDim.x) bins[i] = 0;
     __syncthreads();
     u64 visits = 0;  // row entries this wave read (work counter when profiling)
-    for (i32 n = blockIdx.x; n < N; n += gridDim.x) {
+    for (i64 r = 0;; ++r) {
+        const i64 nx = xcd_item(r, blockIdx.x, gridDim.x);  // neighbouring nodes on one XCD
+        if (nx >= N) break;
+        const i32 n = (i32)nx;
         const i32 ps = rho[n];
         const i64 a = inc_off[n], b = inc_off[n + 1];
         const i64 deg = b - a;
@@ -684,9 +690,12 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     for (int i = lane; i < kGainsWaveParts / 32; i += kWave) t_bits[wv][i] = 0;
     const Touched tt{t_bits[wv]};
     wave_sync();
-    const i64 stride = (i64)gridDim.x * nwv;
     u64 visits = 0;  // row entries this lane read (work counter when profiling)
-    i64 n = (i64)blockIdx.x * nwv + wv;
+    // node of round r for this wave: each block takes nwv consecutive nodes
+    // per round, blocks of one XCD adjacent runs of them
+    auto node_of = [&](i64 r) { return xcd_item(r, blockIdx.x, gridDim.x) * nwv + wv; };
+    i64 rr = 0;
+    i64 n = node_of(0);
     // the node's partition, incidence offsets and size, one node ahead
     i32 ps_n = 0;
     i64 a_n = 0, b_n = 0, nw_nn = 0;
@@ -696,14 +705,14 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
         b_n = inc_off[n + 1];
         nw_nn = nw[n];
     }
-    for (; n < N; n += stride) {
+    for (; n < N; n = node_of(++rr)) {
         const i32 ps = ps_n;
         const i64 a = a_n, b = b_n;
         const i64 nw_n = nw_nn;
         i64 saving = 0, wi = 0;
         const i64 deg = b - a;
         const bool flat = (deg > 0) & (deg <= kGainsFlatChunks * kWave);
-        const i64 n2 = n + stride;  // the next node's scalars, behind this node's first loads
+        const i64 n2 = node_of(rr + 1);  // the next node's scalars, behind this node's first loads
         if (flat) {
             if (deg <= 2 * kWave)
                 gains_flat<2>(a, b, lane, ps, nparts, inc, he_off, partf, len, hw, saving, wi, visits, bins, tt, n2,
