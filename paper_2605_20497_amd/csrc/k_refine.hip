@@ -588,13 +588,11 @@ __device__ __forceinline__ void gains_chunk(i32 avg, int nb, int lane, i32 ps, i
                                             const unsigned short* __restrict__ partf, i64 r0, i32 L, i32 w,
                                             i64& saving, u32* bins, Touched tt) {
     if (avg <= 64)
-        gains_group<16, 1, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+        gains_group<8, 1, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
     else if (avg <= 128)
-        gains_group<8, 2, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
-    else if (avg <= 192)
-        gains_group<6, 3, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+        gains_group<4, 2, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
     else
-        gains_group<4, 4, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
+        gains_group<2, 4, true, true>(nb, lane, 0, ps, 0, nparts, partf, r0, L, w, saving, bins, tt);
 }
 
 // A node of at most CH * 64 incident h-edges with all its loads issued
