@@ -4,6 +4,8 @@
 // and the coarse hypergraph.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "dev_util.h"
 #include "top_select.h"
 
@@ -561,7 +563,7 @@ __device__ __forceinline__ void hash_group(int nb, int lane, i32 n, u32 bmask, u
 }
 
 template <typename BIN, int PI>
-__global__ __launch_bounds__(256) void k_propose_hash(
+__device__ __forceinline__ void propose_hash_body(
     i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
     const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
     const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
@@ -693,6 +695,31 @@ __global__ __launch_bounds__(256) void k_propose_hash(
         Bhint = (most <= (u32)C / 4 && B > 1) ? B / 2 : B;
         sel_merge(top, red_s, red_m, cand + (i64)n * PI, score + (i64)n * PI);
     }
+}
+
+// The kernel for 32-bit bins asks for five waves per SIMD (at most 102 VGPRs;
+// the register allocator spills a handful of cold values to scratch): a fifth
+// more waves to hide the pin loads' latency measured 857 -> 809 ms per
+// partitioning of config 3(b).  With 64-bit bins the same request spilled
+// 30-99 registers, so that kernel keeps the compiler's choice.
+template <typename BIN, int PI>
+__global__ __launch_bounds__(256) void k_propose_hash(
+    i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
+    const unsigned long long* __restrict__ stats, int ib, i32* cand, u64* score, int C) {
+    propose_hash_body<BIN, PI>(N, inc_off, inc_nin, inc, he_off, he_nsrc, pins, hw, nw, omega, delta, seed, stats,
+                               ib, cand, score, C);
+}
+
+template <int PI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_propose_hash32(
+    i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
+    const i64* __restrict__ he_off, const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+    const i32* __restrict__ hw, const i32* __restrict__ nw, i64 omega, i64 delta, u64 seed,
+    const unsigned long long* __restrict__ stats, int ib, i32* cand, u64* score, int C) {
+    propose_hash_body<u32, PI>(N, inc_off, inc_nin, inc, he_off, he_nsrc, pins, hw, nw, omega, delta, seed, stats,
+                               ib, cand, score, C);
 }
 
 // For each h-edge: offsets (from the h-edge start) where the destination
@@ -1104,7 +1131,11 @@ void launch_propose_hash(Ctx* c, const Level& L, int Pi, const unsigned long lon
     int per_cu = 0;
 #define HGP_PROPH_OCC(PIV)                                                                                         \
     case PIV:                                                                                                      \
-        HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propose_hash<BIN, PIV>, 256, lds));          \
+        if constexpr (std::is_same<BIN, u32>::value) {                                                             \
+            HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propose_hash32<PIV>, 256, lds));         \
+        } else {                                                                                                   \
+            HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propose_hash<BIN, PIV>, 256, lds));      \
+        }                                                                                                          \
         break;
     switch (Pi) {
         HGP_PROPH_OCC(1) HGP_PROPH_OCC(2) HGP_PROPH_OCC(3) HGP_PROPH_OCC(4) HGP_PROPH_OCC(5) HGP_PROPH_OCC(6)
@@ -1115,9 +1146,15 @@ void launch_propose_hash(Ctx* c, const Level& L, int Pi, const unsigned long lon
     const int grid = std::min<i64>(L.N, (i64)c->num_cu * std::max(1, per_cu));
 #define HGP_PROPH(PIV)                                                                                             \
     case PIV:                                                                                                      \
-        LAUNCH(c, KF_PROPOSE, (k_propose_hash<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(),          \
-               L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed,       \
-               stats, ib, cand, score, C);                                                                         \
+        if constexpr (std::is_same<BIN, u32>::value) {                                                             \
+            LAUNCH(c, KF_PROPOSE, (k_propose_hash32<PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(),          \
+                   L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed,   \
+                   stats, ib, cand, score, C);                                                                     \
+        } else {                                                                                                   \
+            LAUNCH(c, KF_PROPOSE, (k_propose_hash<BIN, PIV>), grid, 256, lds, L.N, L.inc_off(), L.inc_nin(),      \
+                   L.inc(), L.he_off(), L.he_nsrc(), L.pins(), c->hw(), L.nw(), c->omega, c->delta, c->opt.seed,   \
+                   stats, ib, cand, score, C);                                                                     \
+        }                                                                                                          \
         break;
     switch (Pi) {
         HGP_PROPH(1) HGP_PROPH(2) HGP_PROPH(3) HGP_PROPH(4) HGP_PROPH(5) HGP_PROPH(6) HGP_PROPH(7) HGP_PROPH(8)
