@@ -562,6 +562,64 @@ __device__ __forceinline__ void hash_group(int nb, int lane, i32 n, u32 bmask, u
     }
 }
 
+// Short segments (averaging under kLongSegment pins, as at the coarser levels
+// of the convolutional graph: ~200 h-edges of ~5 pins per node): the wave's
+// batch is one flat index space [0, tot), lane l's h-edge at [start_l, start_l
+// + len_l) with its sources first and its pins contiguous from e0_l, swept
+// 64 * kHashFlatU entries at a time with every lane busy.  An entry's h-edge
+// is found by a binary search over the lanes' starts with whole-wave
+// shuffles; the updates are those of group_apply_hash.
+constexpr int kHashFlatU = 4;
+
+template <typename BIN>
+__device__ __forceinline__ void hash_flat(int lane, i32 n, u32 bmask, u32 pass, const i32* __restrict__ pins, i64 e0,
+                                          i32 cs, i32 len, BIN add, BIN add_in, const HashTab<BIN>& T,
+                                          MissQueue<BIN>& Q) {
+    const i32 incl = wave_incl_scan(len);
+    const i32 start = incl - len;
+    const i32 tot = __shfl(incl, kWave - 1, kWave);
+    const volatile int* ovf = T.overflow;
+    for (i32 j0 = 0; j0 < tot; j0 += kHashFlatU * kWave) {
+        i32 mm[kHashFlatU];
+        BIN ad[kHashFlatU];
+        u32 live = 0;
+#pragma unroll
+        for (int u = 0; u < kHashFlatU; ++u) {
+            const i32 j = j0 + u * kWave + lane;
+            int o = 0;  // the last lane whose segment starts at or before j
+#pragma unroll
+            for (int step = kWave / 2; step >= 1; step >>= 1) {
+                const int cand = o + step;
+                const i32 sc = __shfl(start, cand, kWave);
+                o = sc <= j ? cand : o;
+            }
+            const i32 st = __shfl(start, o, kWave), ns = __shfl(cs, o, kWave);
+            const i64 base = __shfl(e0, o, kWave);
+            const BIN a1 = __shfl(add, o, kWave), a2 = __shfl(add_in, o, kWave);
+            const int in = (int)(j < tot);
+            live |= (u32)in << u;
+            mm[u] = pins[in ? base + (j - st) : 0];  // past the end: the first pin slot, dropped below
+            ad[u] = j - st < ns ? a1 : a2;
+        }
+        u32 home[kHashFlatU], seen[kHashFlatU];
+#pragma unroll
+        for (int u = 0; u < kHashFlatU; ++u) {
+            const u32 m = ((live >> u) & 1u) ? (u32)mm[u] : (u32)n;
+            home[u] = slot_hash(m) & T.cmask;
+            seen[u] = T.keys[home[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kHashFlatU; ++u) {
+            const i32 m = ((live >> u) & 1u) ? mm[u] : n;
+            const int mine = (int)(m != n) & (int)((pass_hash((u32)m) & bmask) == pass);
+            const int hit = mine & (int)(seen[u] == (u32)m);
+            if (hit) atomicAdd(&T.vals[home[u]], ad[u]);
+            miss_push(Q, mine & !hit, m, ad[u], T);
+        }
+        if (*ovf) break;
+    }
+}
+
 template <typename BIN, int PI>
 __device__ __forceinline__ void propose_hash_body(
     i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
@@ -649,7 +707,9 @@ __device__ __forceinline__ void propose_hash_body(
                     const int nb = __popcll(__ballot(valid));
                     const i32 avg = tot / max(nb, 1);
                     const u32 bm = (u32)(B - 1), ps = (u32)pass;
-                    if (avg <= 64)
+                    if (tot < kLongSegment * nb)
+                        hash_flat(lane, n, bm, ps, pins, e0, cs, cs + cd, add, add_in, T, Q);
+                    else if (avg <= 64)
                         hash_group<8, 1>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
                     else if (avg <= 128)
                         hash_group<4, 2>(nb, lane, n, bm, ps, pins, e0, cs, cd, add, add_in, T, Q);
