@@ -49,10 +49,9 @@ TRAFFIC_SOURCES = {
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
-    ("k_propose", "d67cc2b673d2efe632ec33285bccf0026b910079dcb412744d199253a4567321"): 6492284725,
-    ("k_gains16", "9add569fcb1bf581861266e7849e1af19a3f3d782b5d58384d9954aa51b6b435"): 5173471137,
-    ("k_dense_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 1777133399,
-    ("k_conn_gemm", "7650765301f3707763fbf1a94aa603699eb4970c383675851ebedd006ab0ec68"): 556130590,
+    # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
+    ("k_propose", "2deeecb15e993344f25b5cfb52beb068933dafd31cc49ded741f81b67c598709"): 11791731983,
+    ("k_gains16", "4a8d37592c3cafeb834f1537cbc98cf1df3241fea91088b82e5fc726c75e7f0e"): 4306995247,
 }
 
 
