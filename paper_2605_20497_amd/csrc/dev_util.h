@@ -75,8 +75,6 @@ __device__ __forceinline__ unsigned long bcast(unsigned long v, int src) {
     return (unsigned long)bcast((long long)v, src);
 }
 
-// Orders shared-memory writes of one wave before later reads of other lanes of
-// the same wave.
 // Work item of round r for workgroup b of a persistent grid of G workgroups.
 // Workgroups go to the 8 XCDs round robin (b to XCD b % 8), so item b of each
 // round would put consecutive items, which share most of their inputs (a
@@ -88,6 +86,19 @@ __device__ __forceinline__ i64 xcd_item(i64 r, int b, int G) {
     return r * G + (i64)(b & 7) * (G >> 3) + (b >> 3);
 }
 
+// List entries one wave takes at a time in the windowed kernels (one per lane,
+// kept by ballot): the list of n entries spread evenly over the grid's waves,
+// at most kWave.  Long lists use full windows; a short one (a coarse level)
+// gets narrow windows, so it still reaches every wave of the grid instead of
+// leaving most of the chip idle.  Host grids are sized for kWindowMin.
+constexpr int kWindowMin = 8;
+__device__ __forceinline__ i64 wave_window(i64 n, i64 waves) {
+    const i64 w = (n + waves - 1) / waves;
+    return w < 1 ? 1 : (w > kWave ? kWave : w);
+}
+
+// Orders shared-memory writes of one wave before later reads of other lanes of
+// the same wave.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

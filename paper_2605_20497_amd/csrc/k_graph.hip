@@ -237,17 +237,18 @@ __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __rest
 }
 
 // Compacts per-h-edge segments written at old offsets into the new layout.
-// Each wave takes 64 h-edges: segments of at most kSmallEdge pins are copied
+// Each wave takes a window of up to 64 h-edges: segments of at most kSmallEdge pins are copied
 // one lane each, longer ones by the whole wave (kept by ballot).
 __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict__ old_off,
                                                     const i64* __restrict__ new_off, const i32* __restrict__ tmp,
                                                     i32* out, unsigned long long* bytes) {
     const int lane = lane_id();
     const int wpb = blockDim.x / kWave;
+    const i64 nw = (i64)gridDim.x * wpb, win = wave_window(E, nw);
     u64 acc = 0;
-    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < E; base += (i64)gridDim.x * wpb * kWave) {
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * win; base < E; base += nw * win) {
         const i64 el = base + lane;
-        const int in = (int)(el < E);
+        const int in = (int)(lane < win) & (int)(el < E);
         const i64 ec = in ? el : 0;
         const i64 al = old_off[ec], ol = new_off[ec];
         const i64 nl = in ? new_off[ec + 1] - ol : 0;
@@ -442,15 +443,18 @@ __global__ __launch_bounds__(256) void k_contract_edges_wave(i32 E, const i64* _
                                                              i32* nsrc_out, unsigned long long* bytes) {
     const int wpb = blockDim.x / kWave;
     const int lane = lane_id();
+    const i64 nw = (i64)gridDim.x * wpb, win = wave_window(E, nw);
     u64 acc = 0;
-    // 64 h-edges at a time; those of kSmallEdge < |e| <= kWaveEdgeMax pins are
-    // kept by ballot (smaller ones: k_contract_small, larger: the block kernel)
-    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < E; base += (i64)gridDim.x * wpb * kWave) {
+    // a window of h-edges at a time; those of kSmallEdge < |e| <= kWaveEdgeMax
+    // pins are kept by ballot (smaller ones: k_contract_small, larger: the
+    // block kernel)
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * win; base < E; base += nw * win) {
       const i64 el = base + lane;
-      const i64 ec = el < E ? el : 0;
+      const int in = (int)(lane < win) & (int)(el < E);
+      const i64 ec = in ? el : 0;
       const i64 al = he_off[ec];
       const int cl = (int)(he_off[ec + 1] - al), nsl = he_nsrc[ec];
-      u64 todo = __ballot((int)(el < E) & (int)(cl > kSmallEdge) & (int)(cl <= kWaveEdgeMax));
+      u64 todo = __ballot(in & (int)(cl > kSmallEdge) & (int)(cl <= kWaveEdgeMax));
       while (todo) {
         const int src = __builtin_ctzll(todo);
         todo &= todo - 1;
@@ -617,14 +621,17 @@ __global__ __launch_bounds__(256) void k_phi_wave(i32 E, const i64* __restrict__
     PhiWaveShared& my = sh[wave_id()];
     u64 acc = 0;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    // 64 list entries at a time; h-edges of kSmallEdge < |e| <= kWaveEdgeMax
-    // pins are kept by ballot (smaller ones: k_phi_small, larger: k_phi)
-    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < ne; base += (i64)gridDim.x * wpb * kWave) {
+    const i64 nw = (i64)gridDim.x * wpb, win = wave_window(ne, nw);
+    // a window of list entries at a time; h-edges of kSmallEdge < |e| <=
+    // kWaveEdgeMax pins are kept by ballot (smaller ones: k_phi_small, larger:
+    // k_phi)
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * win; base < ne; base += nw * win) {
       const i64 il = base + lane;
-      const i64 el = il < ne ? (elist ? (i64)elist[il] : il) : 0;
+      const int in = (int)(lane < win) & (int)(il < ne);
+      const i64 el = in ? (elist ? (i64)elist[il] : il) : 0;
       const i64 al = he_off[el];
       const int cl = (int)(he_off[el + 1] - al), nsl = he_nsrc[el];
-      u64 todo = __ballot((int)(il < ne) & (int)(cl > kSmallEdge) & (int)(cl <= kWaveEdgeMax));
+      u64 todo = __ballot(in & (int)(cl > kSmallEdge) & (int)(cl <= kWaveEdgeMax));
       while (todo) {
         const int src = __builtin_ctzll(todo);
         todo &= todo - 1;
@@ -774,7 +781,7 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
         LAUNCH(c, KF_CONTRACT_EDGES, k_contract_small, grid_for(E, 256, c->num_cu * 8), 256, 0, E, L.he_off(),
                L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(), prof_bytes(c, KF_CONTRACT_EDGES));
         if (c->max_card > kSmallEdge)
-            LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges_wave, grid_for(ceil_div((i64)E, (i64)kWave), 4,
+            LAUNCH(c, KF_CONTRACT_EDGES, k_contract_edges_wave, grid_for(ceil_div((i64)E, (i64)kWindowMin), 4,
                    c->num_cu * 16), 256, 0, E, L.he_off(), L.he_nsrc(), L.pins(), gamma, tmp, card, out.he_nsrc(),
                    prof_bytes(c, KF_CONTRACT_EDGES));
         if (c->max_card > kWaveEdgeMax)
@@ -788,7 +795,7 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
     out.P = P2;
     out.b_pins = c->alloc(sizeof(i32) * (size_t)(P2 > 0 ? P2 : 1));
     if (E > 0)
-        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(ceil_div((i64)E, (i64)kWave), 4, c->num_cu * 16), 256, 0, E,
+        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(ceil_div((i64)E, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0, E,
                L.he_off(),
                (const i64*)out.he_off(), (const i32*)tmp, out.pins(), prof_bytes(c, KF_PACK));
 }
@@ -845,7 +852,7 @@ void build_phi(Ctx* c, const Level& L, const i32* rho, i32* part, i32* cnt, i32*
     LAUNCH(c, KF_PHI, k_phi_small, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, L.he_off(), L.he_nsrc(),
            L.pins(), rho, part, cnt, cnt_in, len, single, part16, elist, ecount, prof_bytes(c, KF_PHI));
     if (c->max_card > kSmallEdge)
-        LAUNCH(c, KF_PHI, k_phi_wave, grid_for(ceil_div((i64)L.E, (i64)kWave), 4, c->num_cu * 16), 256, 0, L.E,
+        LAUNCH(c, KF_PHI, k_phi_wave, grid_for(ceil_div((i64)L.E, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0, L.E,
                L.he_off(), L.he_nsrc(), L.pins(), rho, part, cnt, cnt_in, len, single, part16, elist, ecount,
                prof_bytes(c, KF_PHI));
     if (c->max_card > kWaveEdgeMax)

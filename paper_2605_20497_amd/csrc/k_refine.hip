@@ -1371,14 +1371,16 @@ __global__ __launch_bounds__(64) void k_inseq_edges(
     const u64 lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     u64 acc = 0;
     const i64 ne = elist ? (i64)*ecount : (i64)E;
-    // h-edges 64 list entries at a time; those of more than skip_le pins are
-    // kept by ballot and handled one after another
-    for (i64 base = (i64)blockIdx.x * kWave; base < ne; base += (i64)gridDim.x * kWave) {
+    const i64 win = wave_window(ne, gridDim.x);
+    // h-edges a window of list entries at a time; those of more than skip_le
+    // pins are kept by ballot and handled one after another
+    for (i64 base = (i64)blockIdx.x * win; base < ne; base += (i64)gridDim.x * win) {
       const i64 il = base + lane;
-      const i64 el = il < ne ? (elist ? (i64)elist[il] : il) : 0;
+      const int in = (int)(lane < win) & (int)(il < ne);
+      const i64 el = in ? (elist ? (i64)elist[il] : il) : 0;
       const i64 al = he_off[el], bl = he_off[el + 1];
       const i32 nsl = he_nsrc[el], Ll = len[el];
-      u64 todo = __ballot((int)(il < ne) & (int)(bl - al > (i64)skip_le));
+      u64 todo = __ballot(in & (int)(bl - al > (i64)skip_le));
       while (todo) {
         const int src = __builtin_ctzll(todo);
         todo &= todo - 1;
@@ -1475,7 +1477,8 @@ __device__ __forceinline__ i32 part_slot(i32* tkey, int tbits, i32 p, int& inser
 // i's source part and 2i + 1 enters its destination part.  24 bytes per mover
 // slot and 12 per table slot.
 //
-// A wave takes its h-edges 64 list entries at a time, reading their offsets,
+// A wave takes its h-edges a window of list entries at a time (up to 64, fewer
+// when the list is short for the grid), reading their offsets,
 // source counts and row lengths one per lane and keeping (by ballot) those of
 // more than `lo` and at most cap pins; its 64 / GW lane groups then handle
 // them GW at a time, each group its own h-edge with its own shared memory.
@@ -1514,13 +1517,15 @@ __global__ __launch_bounds__(64) void k_inseq_lists(
         thead[t] = -1;
     }
     wave_sync();
-    for (i64 base = (i64)blockIdx.x * kWave; base < ne; base += (i64)gridDim.x * kWave) {
+    const i64 win = wave_window(ne, gridDim.x);
+    for (i64 base = (i64)blockIdx.x * win; base < ne; base += (i64)gridDim.x * win) {
         const i64 il = base + lane;
-        const i64 el = il < ne ? (elist ? (i64)elist[il] : il) : 0;
+        const int in = (int)(lane < win) & (int)(il < ne);
+        const i64 el = in ? (elist ? (i64)elist[il] : il) : 0;
         const i64 al = he_off[el], bl = he_off[el + 1];
         const i32 nsl = he_nsrc[el], Ll = len[el];
         const i32 cardl = (i32)(bl - al);
-        const int mine = (int)(il < ne) & (int)(cardl > lo) & (int)(cardl <= cap);
+        const int mine = in & (int)(cardl > lo) & (int)(cardl <= cap);
         const u64 todo = __ballot(mine);
         const int nt = __popcll(todo);
         if (mine) s_list[__popcll(todo & lt_mask)] = lane;
@@ -2311,7 +2316,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         LAUNCH(c, KF_INSEQ, k_inseq_small, grid_for(L.E, 256, c->num_cu * 8), 256, 0, L.E, (i32)M, L.he_off(),
                L.he_nsrc(), L.pins(), posn, rho, mdst, f.part, f.cnt, f.cin, f.len, code, (const i32*)elist2,
                (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
-        const int nbw = (int)std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32);
+        const int nbw = (int)std::min<i64>(ceil_div(L.E, (i64)kWindowMin), (i64)c->num_cu * 32);
         if (cap > kInseqSmall) {
             const int capg = std::min(cap, kInseqGroup), tbg = table_bits(capg);
             const size_t lds_g = (size_t)(kWave / 16) * ((size_t)24 * capg + (size_t)12 * ((size_t)1 << tbg));
@@ -2327,7 +2332,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
                    (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
         }
         if (cap > capl)
-            LAUNCH(c, KF_INSEQ, k_inseq_edges, std::min<i64>(ceil_div(L.E, (i64)kWave), (i64)c->num_cu * 32), kWave,
+            LAUNCH(c, KF_INSEQ, k_inseq_edges, nbw, kWave,
                    (sizeof(MoverRec) + 2 * sizeof(i32)) * cap, L.E, (i32)M, L.he_off(), L.he_nsrc(), L.pins(), posn,
                    rho, mdst, f.part, f.cnt, f.cin, f.len, code, cap, (i32)capl, (const i32*)elist2,
                    (const u32*)(ecount + 1), prof_bytes(c, KF_INSEQ));
