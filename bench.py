@@ -216,7 +216,9 @@ def batched_leg(args):
            "plain_closed_jobs_per_s": round(len(jobs) / span, 2),
            "batched_closed_jobs_per_s": round(len(jobs) / span_b, 2), "arrival_rate_per_s": round(rate, 2),
            "plain": summary(plain, 1), "batched": summary(batched, args.batch_workers),
-           "status_counts": status, "bit_exact_vs_plain": bool(ok), "differing_jobs": differ[:16]}
+           "status_counts": status,
+           "reruns": {k: int(sum(r["reruns"] for r in v)) for k, v in runs.items()},
+           "bit_exact_vs_plain": bool(ok), "differing_jobs": differ[:16]}
     gold = os.path.join(ROOT, "tests", "golden", "job_stream_%d.json" % len(jobs))
     if os.path.exists(gold):
         with open(gold) as f:

@@ -107,6 +107,17 @@ hgp_status hgp_create(hgp_ctx** out, const hgp_options* opt);
 /* Destroys the context and frees its device memory.  NULL is a no-op. */
 void hgp_destroy(hgp_ctx* ctx);
 
+/*
+ * Frees the device memory of the loaded job: the input hypergraph, the
+ * coarsening hierarchy and the partition; with workspace_too != 0 also the
+ * scratch buffers that the context otherwise keeps for its next job.  The
+ * context stays valid and needs hgp_load_csr before any other call that
+ * reads a job.  Returns HGP_E_INVALID for a NULL context.  For callers that
+ * keep idle contexts (a pool of workers) and want the memory back between
+ * jobs; a context that is loaded again frees the previous job anyway.
+ */
+hgp_status hgp_release(hgp_ctx* ctx, int32_t workspace_too);
+
 /* Message describing the last error on this context ("" if none). */
 const char* hgp_last_error(const hgp_ctx* ctx);
 
@@ -319,6 +330,8 @@ typedef struct hgp_job {
     double end_s;         /* out: completion time (partition on the host) */
     int64_t footprint;    /* out: the device-memory estimate used for admission, bytes */
     hgp_status status;    /* out: HGP_OK, or the error of the job's first failing call */
+    int32_t reruns;       /* out: 1 if the job ran out of device memory beside other jobs and was run
+                             again alone (start_s is then its first admission), else 0 */
 } hgp_job;
 
 /*

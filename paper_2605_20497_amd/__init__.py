@@ -44,7 +44,8 @@ class hgp_job(C.Structure):
                 ("pins", C.c_void_p), ("hedge_w", C.c_void_p), ("node_w", C.c_void_p), ("omega", C.c_int64),
                 ("delta", C.c_int64), ("k", C.c_int32), ("arrival_s", C.c_double), ("rho", C.c_void_p),
                 ("n_parts", C.c_int32), ("n_levels", C.c_int32), ("conn", C.c_int64), ("violations", C.c_int64),
-                ("start_s", C.c_double), ("end_s", C.c_double), ("footprint", C.c_int64), ("status", C.c_int)]
+                ("start_s", C.c_double), ("end_s", C.c_double), ("footprint", C.c_int64), ("status", C.c_int),
+                ("reruns", C.c_int32)]
 
 
 class HgpError(RuntimeError):
@@ -76,6 +77,7 @@ def lib():
             "hgp_default_options": (None, [C.POINTER(hgp_options)]),
             "hgp_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(hgp_options)]),
             "hgp_destroy": (None, [P]),
+            "hgp_release": (C.c_int, [P, i32]),
             "hgp_last_error": (C.c_char_p, [P]),
             "hgp_load_csr": (C.c_int, [P, i32, i32, P, P, P, P, P, C.c_int]),
             "hgp_set_limits": (C.c_int, [P, i64, i64, i32]),
@@ -112,7 +114,7 @@ KERNEL_FAMILIES = ["validate", "transpose", "radix_sort", "scan", "level_stats",
                    "inseq", "events", "select", "apply", "project", "eval", "misc", "propose_dense", "dense_gemm",
                    "gains_gemm"]
 
-EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_last_error", "hgp_load_csr",
+EXPORTED = ["hgp_default_options", "hgp_create", "hgp_destroy", "hgp_release", "hgp_last_error", "hgp_load_csr",
             "hgp_set_limits", "hgp_set_kway_limits", "hgp_coarsen", "hgp_refine", "hgp_get_levels", "hgp_get_cluster_map",
             "hgp_get_proposal", "hgp_get_level_graph", "hgp_get_partition", "hgp_get_phi", "hgp_evaluate",
             "hgp_evaluate_noalloc",
@@ -127,7 +129,7 @@ def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16,
     delta and k) as jobs on `workers` concurrent contexts; `arrivals` are the
     seconds after the start at which each may be admitted (sorted; default
     all 0).  Returns one dict per job: rho, n_parts, n_levels, conn,
-    violations, start_s, end_s, footprint, status."""
+    violations, start_s, end_s, footprint, status, reruns."""
     n = len(graphs)
     arr = [0.0] * n if arrivals is None else [float(a) for a in arrivals]
     jobs = (hgp_job * max(n, 1))()
@@ -158,7 +160,7 @@ def hgp_run_jobs(graphs, workers=1, arrivals=None, hbm_budget=0, pi=4, theta=16,
         j = jobs[i]
         out.append({"rho": rhos[i], "n_parts": j.n_parts, "n_levels": j.n_levels, "conn": j.conn,
                     "violations": j.violations, "start_s": j.start_s, "end_s": j.end_s,
-                    "footprint": j.footprint, "status": j.status})
+                    "footprint": j.footprint, "status": j.status, "reruns": j.reruns})
     return out
 
 
@@ -244,6 +246,10 @@ class Partitioner:
             raise HgpError(st, lib().hgp_last_error(self.h).decode())
 
     # -- calls with the C ABI's names --------------------------------------
+    def hgp_release(self, workspace_too=False):
+        self._chk(lib().hgp_release(self.h, 1 if workspace_too else 0))
+        self.N = self.E = self.P = 0
+
     def hgp_load_csr(self, n_nodes, he_off, he_nsrc, pins, hedge_w=None, node_w=None):
         he_off = np.ascontiguousarray(he_off, np.int64)
         he_nsrc = np.ascontiguousarray(he_nsrc, np.int32)

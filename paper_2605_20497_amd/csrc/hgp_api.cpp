@@ -365,6 +365,20 @@ void hgp_destroy(hgp_ctx* h) {
     delete h;
 }
 
+hgp_status hgp_release(hgp_ctx* h, int32_t workspace_too) {
+    API_BEGIN(h)
+    HIPC(hipSetDevice(c->device));
+    drop_hierarchy(c);
+    for (auto& L : c->levels) c->free_level(L);
+    c->levels.clear();
+    c->release(c->b_hw);
+    if (workspace_too)
+        for (auto& b : c->ws) c->release(b);
+    c->loaded = c->limits_set = c->coarsened = c->refined = false;
+    c->sync();  // the frees are stream-ordered: done when this returns
+    API_END
+}
+
 const char* hgp_last_error(const hgp_ctx* h) { return h ? h->c.err.c_str() : "null context"; }
 
 hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int64_t* he_off,

@@ -10,6 +10,8 @@
 // (hundreds of levels) can outgrow it.  A job that runs out of device memory
 // while other jobs are in flight is put back and run again alone, once every
 // other job has finished; only a job that fails alone reports HGP_E_NOMEM.
+// A worker frees its job's hierarchy as soon as the results are on the host,
+// so idle workers keep only their scratch buffers.
 // One worker gives the plain one-at-a-time baseline with the same code path.
 // Each job's result is that of a lone run (the method is deterministic;
 // contexts share nothing).
@@ -60,7 +62,9 @@ hgp_status run_one(hgp_ctx* ctx, hgp_job& j) {
     j.n_parts = (int32_t)ev.n_parts;
     j.conn = ev.conn;
     j.violations = ev.violations;
-    return HGP_OK;
+    // an idle worker holds no hierarchy: a deep one can be tens of GB, which
+    // the jobs still running (or a lone rerun) may need
+    return hgp_release(ctx, 0);
 }
 
 }  // namespace
@@ -76,6 +80,7 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
         jobs[i].status = HGP_E_STATE;
         jobs[i].start_s = jobs[i].end_s = -1.0;
         jobs[i].footprint = footprint(jobs[i]);
+        jobs[i].reruns = 0;
         if (i > 0 && jobs[i].arrival_s < jobs[i - 1].arrival_s) return HGP_E_INVALID;
     }
     if (hipSetDevice(o.device) != hipSuccess) return HGP_E_DEVICE;
@@ -88,6 +93,7 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
     std::mutex mu;
     std::condition_variable cv;
     int64_t next = 0, inflight = 0;
+    int64_t admissions = 0;  // jobs started so far, lone reruns included
     int running = 0;
     bool exclusive = false;         // a job put back for lack of memory is running alone
     std::vector<int64_t> put_back;  // such jobs, waiting for the device to empty
@@ -106,6 +112,7 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
         for (;;) {
             int64_t i;
             int concurrent = 0;  // jobs in progress, this one included, when it started
+            int64_t seen = 0;    // admissions, this one included, when it started
             bool alone = false;  // this run is a put-back job's lone rerun
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -148,17 +155,20 @@ extern "C" hgp_status hgp_run_jobs(const hgp_options* opt, hgp_job* jobs, int64_
                 ++running;
                 inflight += jobs[i].footprint;
                 concurrent = running;
+                seen = ++admissions;
             }
             hgp_job& j = jobs[i];
             j.status = run_one(ctx, j);
             j.end_s = seconds_since(t0);
             // Out of memory beside other jobs: free what this job holds and
-            // put it back for a lone rerun (running > 1 at its start or end).
+            // put it back for a lone rerun.  Another job overlapped this one if
+            // it was in progress at this one's start or started since.
             bool again = false;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                if (j.status == HGP_E_NOMEM && !alone && (concurrent > 1 || running > 1)) {
+                if (j.status == HGP_E_NOMEM && !alone && (concurrent > 1 || admissions != seen)) {
                     put_back.push_back(i);
+                    j.reruns = 1;
                     again = true;
                 }
                 --running;

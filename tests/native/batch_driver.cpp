@@ -101,6 +101,13 @@ int main(int argc, char** argv) {
             if (!put_back(q) && jobs[q].start_s <= jobs[i].start_s && jobs[q].end_s > jobs[i].start_s) cnt++;
         if (cnt > workers) { std::printf("more jobs in flight than workers at job %d\n", i); bad++; }
     }
+    // every out-of-memory return beside other jobs is one recorded rerun
+    int reruns = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        reruns += jobs[i].reruns;
+        if (jobs[i].reruns && !put_back(i)) { std::printf("job %d rerun without running out of memory\n", i); bad++; }
+    }
+    if (reruns != g_oom_returns.load()) { std::printf("reruns %d, out-of-memory returns %d\n", reruns, g_oom_returns.load()); bad++; }
     std::printf("jobs %d workers %d budget %lld put back %d bad %d\n", n_jobs, workers, (long long)budget,
                 g_oom_returns.load(), bad);
     return bad ? 1 : 0;

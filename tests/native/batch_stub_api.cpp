@@ -124,4 +124,18 @@ hgp_status hgp_evaluate(hgp_ctx* c, const int32_t* rho, int32_t, hgp_eval* out) 
     return HGP_OK;
 }
 
+hgp_status hgp_release(hgp_ctx* c, int32_t) {
+    if (!c) return HGP_E_INVALID;
+    if (c->in_job) g_in_job--;
+    c->in_job = false;
+    c->he_off.clear();
+    c->he_nsrc.clear();
+    c->pins.clear();
+    c->hw.clear();
+    c->nw.clear();
+    c->rho.clear();
+    c->loaded = c->limited = c->coarsened = c->refined = false;
+    return HGP_OK;
+}
+
 }  // extern "C"

@@ -47,3 +47,24 @@ def test_run_jobs_arguments():
     with pytest.raises(HgpError):
         hgp_run_jobs(jobs, workers=0)
     assert hgp_run_jobs([], workers=2) == []
+
+
+def test_release_then_reload():
+    """hgp_release frees the job's device memory; the context refuses calls
+    that read a job until the next load, and then gives the same result."""
+    import paper_2605_20497_amd as pkg
+    jobs, _ = W.job_stream(2, 4096, 4096, seed=5)
+    p = pkg.Partitioner(device=0)
+    try:
+        first = [p.partition(hg) for hg in jobs]
+        for workspace_too in (False, True):
+            p.hgp_release(workspace_too)
+            with pytest.raises(pkg.HgpError):
+                p.hgp_get_partition()
+            with pytest.raises(pkg.HgpError):
+                p.hgp_coarsen()
+            again = [p.partition(hg) for hg in jobs]
+            for (ra, ka), (rb, kb) in zip(first, again):
+                assert np.array_equal(ra, rb) and ka == kb
+    finally:
+        p.close()
