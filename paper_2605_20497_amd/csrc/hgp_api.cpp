@@ -354,6 +354,7 @@ void hgp_destroy(hgp_ctx* h) {
         c->levels.clear();
         c->release(c->b_hw);
         for (auto& b : c->ws) c->release(b);
+        release_scan_state(c);
         c->release(c->prof.b_work);
         c->release(c->prof.b_lv_bytes);
         (void)hipStreamSynchronize(c->stream);
@@ -372,8 +373,10 @@ hgp_status hgp_release(hgp_ctx* h, int32_t workspace_too) {
     for (auto& L : c->levels) c->free_level(L);
     c->levels.clear();
     c->release(c->b_hw);
-    if (workspace_too)
+    if (workspace_too) {
         for (auto& b : c->ws) c->release(b);
+        release_scan_state(c);
+    }
     c->loaded = c->limits_set = c->coarsened = c->refined = false;
     c->sync();  // the frees are stream-ordered: done when this returns
     API_END
@@ -450,7 +453,7 @@ hgp_status hgp_load_csr(hgp_ctx* h, int32_t n_nodes, int32_t n_hedges, const int
     // what it counts (sources: swap the blocks; any pin: one merged block).
     if (c->opt.delta_mode != HGP_DELTA_INBOUND) retarget_pins(c, L0, c->opt.delta_mode);
     build_incidence(c, L0);
-    c->sync();
+    check_scan_state(c);
     c->loaded = true;
     API_END
 }
@@ -516,7 +519,7 @@ hgp_status hgp_coarsen(hgp_ctx* h, int32_t* n_levels_out) {
         c->level_ev_coarsen.push_back(ev);
         if ((int)c->levels.size() == lv + 1) break;  // no merge
     }
-    c->sync();
+    check_scan_state(c);
     c->coarsened = true;
     if (n_levels_out) *n_levels_out = (int32_t)c->levels.size();
     API_END
@@ -586,6 +589,7 @@ hgp_status hgp_refine(hgp_ctx* h) {
     require(c->coarsened, HGP_E_STATE, "coarsen first");
     HIPC(hipSetDevice(c->device));
     refine_all(c);
+    check_scan_state(c);
     c->refined = true;
     API_END
 }
@@ -729,6 +733,7 @@ hgp_status hgp_refine_rep(hgp_ctx* h, int32_t* rho, int32_t n_parts, int32_t rep
     tr.prefix_gain = prefix_gain;
     tr.prefix_viol = prefix_viol;
     RepInfo ri = refine_rep(c, L, d, n_parts, rep, c->opt.theta, &tr);
+    check_scan_state(c);
     d2h(c, rho, d, (size_t)L.N);
     if (info) {
         info[0] = ri.moves;

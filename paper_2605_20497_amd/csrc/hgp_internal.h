@@ -145,6 +145,15 @@ struct Ctx {
     std::vector<Buf> ws;
     void* ws_get(int slot, size_t bytes);
 
+    // State of the single-pass scan (k_prim.hip): a tile ticket counter, an
+    // error word, and per tile a status word and two values.  Zeroed when
+    // allocated; every scan after that takes a fresh tag and a fresh run of
+    // tickets, so no clearing is needed between scans.
+    Buf b_scan;
+    i64 scan_tiles = 0;   // tiles the state has room for
+    u64 scan_tag = 0;     // tag of the last scan
+    u64 scan_ticket = 0;  // tickets handed out so far
+
     // Pinned host staging for scalars read back by the driver.
     i64* host_scalars = nullptr;
     // Device address of the library's static workspace on this context's
@@ -204,6 +213,10 @@ void iota_i32(Ctx* c, i32* p, i64 n);
 void gather_i32(Ctx* c, const i32* src, const i32* idx, i32* dst, i64 n);  // dst[i] = src[idx[i]]
 // Reads `count` device i64 values into host memory (synchronises the stream).
 void read_back(Ctx* c, const void* dev, i64* host, int count, int elem_bytes);
+// Fails with HGP_E_DEVICE if a scan's look-back wait ran out since the state
+// was allocated (synchronises the stream).
+void check_scan_state(Ctx* c);
+void release_scan_state(Ctx* c);
 
 // ---------------------------------------------------------------------------
 // Hypergraph launchers (k_graph.hip).
