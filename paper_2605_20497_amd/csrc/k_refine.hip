@@ -782,13 +782,18 @@ __global__ __launch_bounds__(kGainsWaves * kWave) void k_gains16w(
     if ((work != nullptr) & (lane == 0) & (vis != 0)) atomicAdd(work, (unsigned long long)vis);
 }
 
-// Lists once each h-edge incident to the nodes nodes[0..cnt): one wave per
-// node over its incidence entries; emark[e] takes `stamp` and the lane that
-// changed it appends e (order immaterial).  Appends gather in a per-wave
-// buffer in shared memory and go out kMarkBuf - 64 or more at a time, one
-// atomic on the shared list count per batch: one per 64 entries put the
-// whole device's waves in line on that one address.
+// Lists once each h-edge incident to the nodes nodes[0..cnt); emark[e] takes
+// `stamp` and the lane that changed it appends e (order immaterial).  Each
+// wave takes a window of listed nodes, one per lane, and walks the window's
+// incidence entries as one flat range, kMarkU * 64 at a time: a lane finds
+// the node of its entry by a binary search over the window's degree sums, so
+// every lane has an entry whatever the degrees, and the loads and exchanges
+// of kMarkU entries per lane are in flight together.  Appends gather in a
+// per-wave buffer in shared memory and go out kMarkBuf - 64 or more at a
+// time, one atomic on the shared list count per batch: one per 64 entries
+// put the whole device's waves in line on that one address.
 constexpr u32 kMarkBuf = 512;
+constexpr int kMarkU = 4;
 
 __global__ __launch_bounds__(256) void k_mark_edges(i32 cnt, const i32* __restrict__ nodes,
                                                     const i64* __restrict__ inc_off, const i32* __restrict__ inc,
@@ -808,19 +813,44 @@ __global__ __launch_bounds__(256) void k_mark_edges(i32 cnt, const i32* __restri
         wave_sync();  // read out before it is refilled
         nb = 0;
     };
-    for (i64 j = (i64)blockIdx.x * wpb + wave_id(); j < cnt; j += (i64)gridDim.x * wpb) {
-        const i32 n = nodes[j];
-        const i64 a = inc_off[n], b = inc_off[n + 1];
-        for (i64 k0 = a; k0 < b; k0 += kWave) {
-            const i64 k = k0 + lane;
-            const i32 e = k < b ? inc[k] : -1;
-            u32 old = stamp;
-            if (e >= 0) old = atomicExch(&emark[e], stamp);
-            const int first = (int)(old != stamp);
-            const u64 bal = __ballot(first);
-            if (first) wb[nb + (u32)__popcll(bal & lt_mask)] = e;
-            nb += (u32)__popcll(bal);
-            if (nb > kMarkBuf - kWave) flush();
+    const i64 nwv = (i64)gridDim.x * wpb, win = wave_window(cnt, nwv);
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * win; base < cnt; base += nwv * win) {
+        const i64 j = base + lane;
+        const int in = (int)(lane < win) & (int)(j < cnt);
+        const i32 n = nodes[in ? j : base];
+        const i64 a = inc_off[n];
+        const i64 d = in ? inc_off[n + 1] - a : 0;
+        const i64 incl = wave_incl_scan(d);
+        const i64 start = incl - d;
+        const i64 tot = bcast((long long)incl, kWave - 1);
+        for (i64 f0 = 0; f0 < tot; f0 += kMarkU * kWave) {
+            i32 e[kMarkU];
+#pragma unroll
+            for (int u = 0; u < kMarkU; ++u) {
+                const i64 f = f0 + u * kWave + lane;
+                int o = 0;  // the last lane whose range starts at or before f
+#pragma unroll
+                for (int step = kWave / 2; step >= 1; step >>= 1) {
+                    const int cand = o + step;
+                    const i64 sc = __shfl(start, cand, kWave);
+                    o = sc <= f ? cand : o;
+                }
+                const i64 ao = __shfl(a, o, kWave), so = __shfl(start, o, kWave);
+                const int ok = (int)(f < tot);
+                const i32 x = inc[ok ? ao + (f - so) : 0];  // past the end: entry 0, dropped
+                e[u] = ok ? x : -1;
+            }
+            u32 old[kMarkU];
+#pragma unroll
+            for (int u = 0; u < kMarkU; ++u) old[u] = e[u] >= 0 ? atomicExch(&emark[e[u]], stamp) : stamp;
+#pragma unroll
+            for (int u = 0; u < kMarkU; ++u) {
+                const int first = (int)(old[u] != stamp);
+                const u64 bal = __ballot(first);
+                if (first) wb[nb + (u32)__popcll(bal & lt_mask)] = e[u];
+                nb += (u32)__popcll(bal);
+                if (nb > kMarkBuf - kWave) flush();
+            }
         }
     }
     if (nb > 0) flush();
@@ -2077,7 +2107,8 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     if (incremental) {
         clear_marks();
         const i32* prev_seq = wsp<i32>(c, WS_SEQN, (size_t)incr_k);
-        LAUNCH(c, KF_PHI, k_mark_edges, grid_for(incr_k, 4, c->num_cu * 16), 256, 0, (i32)incr_k, prev_seq,
+        LAUNCH(c, KF_PHI, k_mark_edges, grid_for(ceil_div(incr_k, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0,
+               (i32)incr_k, prev_seq,
                L.inc_off(), L.inc(), emark, 1u, elist, ecount);
     }
     // With `reuse`, rho is unchanged since the previous repetition (it applied
@@ -2300,7 +2331,8 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         i32* elist2 = listed ? wsp<i32>(c, WS_ELIST2, (size_t)L.E) : nullptr;
         if (listed) {
             clear_marks();
-            LAUNCH(c, KF_INSEQ, k_mark_edges, grid_for(M, 4, c->num_cu * 16), 256, 0, (i32)M, (const i32*)seqn,
+            LAUNCH(c, KF_INSEQ, k_mark_edges, grid_for(ceil_div(M, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0,
+                   (i32)M, (const i32*)seqn,
                    L.inc_off(), L.inc(), emark, 2u, elist2, ecount + 1);
         }
         // H-edges of at most kInseqSmall pins one lane each; event lists for
