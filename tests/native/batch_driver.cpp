@@ -61,8 +61,8 @@ int main(int argc, char** argv) {
         j.rho = x.rho.data();
     }
     // budget: room for about three average jobs at once, by the scheduler's
-    // footprint estimate (8 levels of 14 B per pin, 72 B per node and 12 B per
-    // h-edge, 40 B per pin of scratch, 16 MiB)
+    // footprint estimate (32 level copies of 14 B per pin, 72 B per node and
+    // 12 B per h-edge, 40 B per pin of scratch, 16 MiB)
     hgp_options opt;
     hgp_default_options(&opt);
     int64_t budget = 0;
@@ -70,7 +70,7 @@ int main(int argc, char** argv) {
         int64_t tot = 0;
         for (auto& j : jobs) {
             const int64_t P = j.he_off[j.n_hedges];
-            tot += 8 * (14 * P + 72 * (int64_t)j.n_nodes + 12 * (int64_t)j.n_hedges) + 40 * P + (16 << 20);
+            tot += 32 * (14 * P + 72 * (int64_t)j.n_nodes + 12 * (int64_t)j.n_hedges) + 40 * P + (16 << 20);
         }
         budget = 3 * tot / n_jobs;
     }
