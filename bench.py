@@ -484,6 +484,7 @@ def main():
         "roofline": roof,
         "rooflines": list(roofs.values()),
         "tuning": {k: tune[k] for k in ("hash_log2", "list_gate")},
+        "tuning_device": autotune.device_name(),
         "streams": streams,
         "levels": per_level,
         "kernels": breakdown,

@@ -49,9 +49,24 @@ def save(cache: dict, path: str = CACHE) -> None:
     os.replace(tmp, path)
 
 
+def _device_entry(cache: dict, name: str) -> dict:
+    """The cache's entry for this device name; failing that, one for the same
+    ISA (the marketing name the runtime reports can differ between processes
+    on one machine, e.g. with and without a profiler's library loaded)."""
+    if name in cache:
+        return cache[name]
+    i = name.rfind(" (")
+    if i >= 0 and name.endswith(")"):
+        isa = name[i:]
+        for key in sorted(cache):
+            if key.endswith(isa):
+                return cache[key]
+    return {}
+
+
 def tuned_options(workload: str, device: int = 0, path: str = CACHE, name: str | None = None) -> dict:
     """Choices cached for (device, workload), else the defaults."""
-    entry = load(path).get(name or device_name(device), {}).get(workload, {})
+    entry = _device_entry(load(path), name or device_name(device)).get(workload, {})
     out = dict(DEFAULT)
     out.update({k: v for k, v in entry.items() if k in DEFAULT})
     return out
