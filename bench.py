@@ -50,8 +50,8 @@ TRAFFIC_SOURCES = {
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
-    ("k_propose", "2deeecb15e993344f25b5cfb52beb068933dafd31cc49ded741f81b67c598709"): 11791731983,
-    ("k_gains16", "4a8d37592c3cafeb834f1537cbc98cf1df3241fea91088b82e5fc726c75e7f0e"): 4306995247,
+    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16689785072,
+    ("k_gains16", "f12092d674d99eff16993e17cd29e1a02fca4cf376349e185c77f0a7e7e53742"): 4291872410,
 }
 
 
