@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void k_contract_edges(i32 E, const i64* __rest
 }
 
 // Compacts per-h-edge segments written at old offsets into the new layout.
-// Each wave takes a window of up to 64 h-edges: segments of at most kSmallEdge pins are copied
+// Each wave takes a window of up to 64 h-edges (64 whenever the grid, sized
+// for 64 per wave, is not capped): segments of at most kSmallEdge pins are copied
 // one lane each, longer ones by the whole wave (kept by ballot).
 __global__ __launch_bounds__(256) void k_pack_edges(i32 E, const i64* __restrict__ old_off,
                                                     const i64* __restrict__ new_off, const i32* __restrict__ tmp,
@@ -795,7 +796,7 @@ void contract_edges(Ctx* c, const Level& L, const i32* gamma, Level& out) {
     out.P = P2;
     out.b_pins = c->alloc(sizeof(i32) * (size_t)(P2 > 0 ? P2 : 1));
     if (E > 0)
-        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(ceil_div((i64)E, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0, E,
+        LAUNCH(c, KF_PACK, k_pack_edges, grid_for(ceil_div((i64)E, (i64)kWave), 4, c->num_cu * 16), 256, 0, E,
                L.he_off(),
                (const i64*)out.he_off(), (const i32*)tmp, out.pins(), prof_bytes(c, KF_PACK));
 }

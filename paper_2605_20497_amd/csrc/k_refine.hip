@@ -2014,6 +2014,16 @@ bool few_touched(const Ctx* c, const Level& L, i64 movers) {
     return L.N > 0 && movers * gate < (i64)L.N;
 }
 
+// Blocks of k_mark_edges for `cnt` listed nodes: a wave per about
+// kMarkPerWave incidence entries at the level's mean degree, so that nodes of
+// many h-edges still spread over many waves and nodes of few share one.
+constexpr i64 kMarkPerWave = 512;
+int mark_grid(const Ctx* c, const Level& L, i64 cnt) {
+    const i64 deg = std::max<i64>(1, L.P / std::max<i64>(1, (i64)L.N));
+    const i64 waves = std::max(ceil_div(cnt * deg, kMarkPerWave), ceil_div(cnt, (i64)kWave));
+    return grid_for(waves, 4, c->num_cu * 16);
+}
+
 // Partition sizes and D(p) of rho from its Phi rows; psize and pD start at 0.
 void part_stats(Ctx* c, const Level& L, const i32* rho, i32 nparts, const i32* part, const i32* cin, const i32* len,
                 i64* psize, i64* pD) {
@@ -2107,8 +2117,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
     if (incremental) {
         clear_marks();
         const i32* prev_seq = wsp<i32>(c, WS_SEQN, (size_t)incr_k);
-        LAUNCH(c, KF_PHI, k_mark_edges, grid_for(ceil_div(incr_k, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0,
-               (i32)incr_k, prev_seq,
+        LAUNCH(c, KF_PHI, k_mark_edges, mark_grid(c, L, incr_k), 256, 0, (i32)incr_k, prev_seq,
                L.inc_off(), L.inc(), emark, 1u, elist, ecount);
     }
     // With `reuse`, rho is unchanged since the previous repetition (it applied
@@ -2331,8 +2340,7 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         i32* elist2 = listed ? wsp<i32>(c, WS_ELIST2, (size_t)L.E) : nullptr;
         if (listed) {
             clear_marks();
-            LAUNCH(c, KF_INSEQ, k_mark_edges, grid_for(ceil_div(M, (i64)kWindowMin), 4, c->num_cu * 16), 256, 0,
-                   (i32)M, (const i32*)seqn,
+            LAUNCH(c, KF_INSEQ, k_mark_edges, mark_grid(c, L, M), 256, 0, (i32)M, (const i32*)seqn,
                    L.inc_off(), L.inc(), emark, 2u, elist2, ecount + 1);
         }
         // H-edges of at most kInseqSmall pins one lane each; event lists for
