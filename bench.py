@@ -50,8 +50,8 @@ TRAFFIC_SOURCES = {
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
-    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16719864819,
-    ("k_gains16", "ceffdb832be711caf68a5fe5c639958e96acdf5067b3d3ef070a807cc1905c43"): 4293988698,
+    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16748646686,
+    ("k_gains16", "9ece52777eaa6d84cf212cce263ad091fa131462e40a3ff98d3e5e42d89c8e06"): 4282128455,
 }
 
 

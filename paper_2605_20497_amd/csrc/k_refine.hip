@@ -6,6 +6,7 @@
 #include <mutex>
 
 #include "dev_util.h"
+#include "scan_lb.h"
 
 // Workspace of hgp_evaluate_noalloc, for callers that cannot allocate device
 // memory.  Every device the library runs on holds its own copy until the
@@ -991,15 +992,23 @@ __device__ __forceinline__ int link_elem(i64 i, const i32* __restrict__ prop, co
 
 #define HGP_GRID_LOOP(i, n) for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
 
-__global__ void k_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pred, i32* pl) {
-    if (!rs[0]) return;
-    HGP_GRID_LOOP(i, M) predless_elem(i, pred, pl);
-}
-
-__global__ void k_compact_predless(i32 M, const unsigned long long* __restrict__ rs, const i32* __restrict__ pl,
-                                   const i32* __restrict__ pls, i32* cl, u64* accG, i32* accN) {
-    if (!rs[0]) return;
-    HGP_GRID_LOOP(i, M) compact_elem(i, pl, pls, cl, accG, accN);
+// The first step of a device-wide chain round in one look-back scan: the
+// moves without a predecessor are flagged (as predless_elem does), their flags
+// scanned into pls (with pls[M] their count), listed in cl in move order and
+// the round's accumulators reset (as compact_elem does), in one launch.
+__global__ __launch_bounds__(kLbBlock) void k_predless_compact(i32 M, const unsigned long long* __restrict__ rs,
+                                                                const i32* __restrict__ pred, i32* pls, i32* cl,
+                                                                u64* accG, i32* accN, ScanState st, u64 tag,
+                                                                u64 ticket0, i64 tiles) {
+    lookback_scan_tile(
+        M, st, tag, ticket0, tiles, rs[0] != 0, [&](i64 i) { return (i64)(pred[i] < 0); },
+        [&](i64 i, i64 prefix, i64 flag) {
+            pls[i] = (i32)prefix;
+            if (flag) cl[prefix] = (i32)i;
+            accG[i] = 0;
+            accN[i] = -1;
+        },
+        [&](i64 sum) { pls[M] = (i32)sum; });
 }
 
 __global__ __launch_bounds__(256) void k_chain_propose(i32 M, const unsigned long long* __restrict__ rs,
@@ -2252,9 +2261,11 @@ RepInfo refine_rep(Ctx* c, const Level& L, i32* rho, i32 nparts, int rep, int th
         }
     }
     for (int round = 0; round < rounds && M > kChainSingleMax && !one; ++round) {
-        LAUNCH(c, KF_CHAINS, k_predless, nbM, 256, 0, (i32)M, rs, pred, pl);
-        scan_excl_i32(c, pl, pls, M);
-        LAUNCH(c, KF_CHAINS, k_compact_predless, nbM, 256, 0, (i32)M, rs, pl, pls, cl, accG, accN);
+        {
+            const ScanLaunch sl = scan_launch(c, M);
+            LAUNCH(c, KF_CHAINS, k_predless_compact, (int)sl.tiles, kLbBlock, 0, (i32)M, rs, (const i32*)pred, pls,
+                   cl, accG, accN, sl.st, sl.tag, sl.ticket0, sl.tiles);
+        }
         LAUNCH(c, KF_CHAINS, k_chain_propose, wblocks, 256, 0, (i32)M, rs, succ, spd, segb, sege, pls, cl, sg, snw,
                snin, snode, prop, propG);
         LAUNCH(c, KF_CHAINS, k_chain_accept_a, nbM, 256, 0, (i32)M, rs, prop, propG, accG);
