@@ -44,14 +44,14 @@ INT8_PEAK_TOPS = 5000.0
 _CSRC = "paper_2605_20497_amd/csrc/"
 TRAFFIC_SOURCES = {
     "k_propose": [_CSRC + f for f in ("k_coarsen.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
-    "k_gains16": [_CSRC + f for f in ("k_refine.hip", "dev_util.h", "hgp_internal.h")],
+    "k_gains16": [_CSRC + f for f in ("k_refine.hip", "scan_lb.h", "dev_util.h", "hgp_internal.h")],
     "k_dense_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
     "k_conn_gemm": [_CSRC + f for f in ("k_dense.hip", "top_select.h", "dev_util.h", "hgp_internal.h")],
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
-    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16748646686,
-    ("k_gains16", "9ece52777eaa6d84cf212cce263ad091fa131462e40a3ff98d3e5e42d89c8e06"): 4282128455,
+    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16643042806,
+    ("k_gains16", "b1669d7b1659b8e798f5e16d669674602c40e91f0ae9c14ed998c7fbd72b872f"): 4290220045,
 }
 
 

@@ -53,19 +53,23 @@ void scan_impl(Ctx* c, const Tin* in, Tout* out, i64 n) {
 
 ScanLaunch scan_launch(Ctx* c, i64 n) {
     const i64 tiles = ceil_div(n, kLbTile);
-    if (c->scan_tiles < tiles) {  // (re)allocated zeroed: every status word older than any tag
-        const i64 cap = std::max<i64>({tiles, 2 * c->scan_tiles, 4096});
-        c->release(c->b_scan);
-        const size_t bytes = 16 + (size_t)cap * 24;
-        c->b_scan = c->alloc(bytes);
+    if (c->scan_tiles < tiles || c->scan_tag + 1 >= kLbTagLimit) {
+        // (re)allocated or, once the tags run out, cleared: zero status words
+        // are older than any tag
+        const i64 cap = std::max<i64>({tiles, c->scan_tiles, 4096});
+        const size_t bytes = 16 + (size_t)cap * 32;
+        if (c->scan_tiles < cap) {
+            c->release(c->b_scan);
+            c->b_scan = c->alloc(bytes);
+        }
         HIPC(hipMemsetAsync(c->b_scan.p, 0, bytes, c->stream));
         c->scan_tiles = cap;
         c->scan_ticket = 0;
+        c->scan_tag = 0;
     }
     u64* base = (u64*)c->b_scan.p;
     ScanLaunch sl;
-    sl.st = ScanState{(unsigned long long*)base, base + 1, base + 2, (i64*)(base + 2 + c->scan_tiles),
-                      (i64*)(base + 2 + 2 * c->scan_tiles)};
+    sl.st = ScanState{(unsigned long long*)base, base + 1, base + 2};
     sl.tag = ++c->scan_tag;
     sl.ticket0 = c->scan_ticket;
     sl.tiles = tiles;

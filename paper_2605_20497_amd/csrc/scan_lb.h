@@ -15,27 +15,42 @@ namespace hgp {
 // counter, so every tile with a smaller index belongs to a block already
 // running.  It publishes its aggregate, sums its predecessors' published
 // values 64 tiles at a time (stopping at the nearest tile that has published
-// its inclusive prefix), then publishes its own inclusive prefix.  Status words
-// carry the scan's tag, so values left by earlier scans are never taken as
-// this scan's and nothing is cleared between scans.  A wait that runs out
+// its inclusive prefix), then publishes its own inclusive prefix.
+//
+// Each published value is two status words, one per 32-bit half, each
+// carrying the scan's tag and a ready bit beside its half, so a word read
+// whole is either this scan's final half or not ready, and no ordering between
+// words is needed.  The words are written and read with relaxed device-scope
+// atomics: release and acquire at device scope would write back and
+// invalidate the XCD's whole L2 on every publish and poll.  Tags make values
+// left by earlier scans unreadable, so nothing is cleared between scans (the
+// host zeroes the state when the 31-bit tag wraps).  A wait that runs out
 // (kLbSpinMax polls) sets the error word, which the host checks, instead of
 // waiting for ever.
 constexpr int kLbBlock = 256;
 constexpr int kLbItems = 16;
 constexpr i64 kLbTile = (i64)kLbBlock * kLbItems;
 constexpr u32 kLbSpinMax = 1u << 22;
+constexpr u64 kLbTagLimit = 1ull << 31;
 
 struct ScanState {
     unsigned long long* ticket;
     u64* err;
-    u64* flag;  // (tag << 2) | 1 (aggregate published) or 2 (inclusive prefix published)
-    i64* agg;
-    i64* incl;
+    u64* word;  // per tile: aggregate (low, high half), inclusive prefix (low, high half)
 };
 
-__device__ __forceinline__ void lb_publish(const ScanState& st, i64 t, u64 tag, u64 kind, i64 v) {
-    __hip_atomic_store(kind == 2 ? st.incl + t : st.agg + t, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(st.flag + t, (tag << 2) | kind, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ u64 lb_word(u64 tag, u32 half) { return (tag << 33) | (1ull << 32) | (u64)half; }
+__device__ __forceinline__ bool lb_ready(u64 w, u64 tag) { return (w >> 32) == ((tag << 1) | 1ull); }
+__device__ __forceinline__ i64 lb_join(u64 lo, u64 hi) { return (i64)(((hi & 0xFFFFFFFFull) << 32) | (lo & 0xFFFFFFFFull)); }
+
+__device__ __forceinline__ void lb_publish(const ScanState& st, i64 t, u64 tag, int incl, i64 v) {
+    u64* w = st.word + 4 * t + 2 * incl;
+    __hip_atomic_store(w, lb_word(tag, (u32)(u64)v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, lb_word(tag, (u32)((u64)v >> 32)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ u64 lb_load(const u64* p) {
+    return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sum of the items of tiles 0 .. t-1, on every lane of the calling wave
@@ -45,10 +60,17 @@ __device__ inline i64 lb_look_back(const ScanState& st, i64 t, u64 tag) {
     i64 prefix = 0;
     for (i64 hi = t;; hi -= kWave) {
         const i64 j = hi - 1 - lane;  // lane 0: the nearest tile
-        u64 f = 0;
+        const u64* w = st.word + 4 * (j >= 0 ? j : 0);
+        u64 a0 = 0, a1 = 0, c0 = 0, c1 = 0;
+        int has_incl = 0, has_agg = 0;
         for (u32 spins = 0;; ++spins) {
-            f = j >= 0 ? __hip_atomic_load(st.flag + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0;
-            if (__all((int)(j < 0) | (int)((f >> 2) == tag))) break;
+            a0 = lb_load(w);
+            a1 = lb_load(w + 1);
+            c0 = lb_load(w + 2);
+            c1 = lb_load(w + 3);
+            has_incl = (int)(j >= 0) & (int)lb_ready(c0, tag) & (int)lb_ready(c1, tag);
+            has_agg = (int)(j >= 0) & (int)lb_ready(a0, tag) & (int)lb_ready(a1, tag);
+            if (__all((int)(j < 0) | has_incl | has_agg)) break;
             if (spins == kLbSpinMax) {
                 if (lane == 0) __hip_atomic_store(st.err, (u64)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return prefix;
@@ -56,12 +78,10 @@ __device__ inline i64 lb_look_back(const ScanState& st, i64 t, u64 tag) {
             __builtin_amdgcn_s_sleep(1);
         }
         // the window holds tile 0 (inclusive) whenever some j < 0, so stop < kWave then
-        const u64 im = __ballot((int)(j >= 0) & (int)((f & 3u) == 2u));
+        const u64 im = __ballot(has_incl);
         const int stop = im ? __builtin_ctzll(im) : kWave;
         i64 v = 0;
-        if ((j >= 0) & (lane <= stop))
-            v = __hip_atomic_load(lane == stop ? st.incl + j : st.agg + j, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+        if ((j >= 0) & (lane <= stop)) v = lane == stop ? lb_join(c0, c1) : lb_join(a0, a1);
         prefix += wave_sum(v);
         if (im) return prefix;
     }
@@ -114,11 +134,11 @@ __device__ __forceinline__ void lookback_scan_tile(i64 n, const ScanState& st, u
     if (w == 0) {
         i64 prefix = 0;
         if (t == 0) {
-            if (lane == 0) lb_publish(st, 0, tag, 2, tot);
+            if (lane == 0) lb_publish(st, 0, tag, 1, tot);
         } else {
-            if (lane == 0) lb_publish(st, t, tag, 1, tot);
+            if (lane == 0) lb_publish(st, t, tag, 0, tot);
             prefix = lb_look_back(st, t, tag);
-            if (lane == 0) lb_publish(st, t, tag, 2, prefix + tot);
+            if (lane == 0) lb_publish(st, t, tag, 1, prefix + tot);
         }
         if (lane == 0) s_prefix = prefix;
     }
