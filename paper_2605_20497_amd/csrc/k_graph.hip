@@ -113,6 +113,47 @@ __global__ __launch_bounds__(256) void k_pin_keys(i32 E, const i64* __restrict__
     }
 }
 
+// Mean h-edge size below which the flat key kernel is used.
+constexpr i64 kPinKeysFlatMean = 32;
+
+// The same keys for levels of small h-edges (a few pins on average), where a
+// wave per h-edge leaves most lanes idle: each wave takes 64 consecutive
+// h-edges, whose pins form one contiguous range, and walks that range 64 pins
+// at a time; a lane finds its pin's h-edge by a binary search over the
+// window's start offsets (relative to the window, so 32 bits).
+__global__ __launch_bounds__(256) void k_pin_keys_flat(i32 E, const i64* __restrict__ he_off,
+                                                       const i32* __restrict__ he_nsrc, const i32* __restrict__ pins,
+                                                       u32* keys, u64* vals) {
+    const int lane = lane_id();
+    const int wpb = blockDim.x / kWave;
+    for (i64 base = ((i64)blockIdx.x * wpb + wave_id()) * kWave; base < E; base += (i64)gridDim.x * wpb * kWave) {
+        const i64 e = base + lane;
+        const int in = (int)(e < E);
+        const i64 A = he_off[base];
+        const i64 B = he_off[min(base + kWave, (i64)E)];
+        const i64 a = he_off[in ? e : E];  // lanes past the end start at B and own nothing
+        const i32 rel = (i32)(a - A);
+        const i32 srel = rel + (in ? he_nsrc[e] : 0);  // first destination pin, window-relative
+        for (i64 j0 = A; j0 < B; j0 += kWave) {
+            const i64 j = j0 + lane;
+            const i32 jr = (i32)(j - A);
+            int o = 0;  // the last lane whose h-edge starts at or before pin j
+#pragma unroll
+            for (int step = kWave / 2; step >= 1; step >>= 1) {
+                const int cand = o + step;
+                const i32 sc = __shfl(rel, cand, kWave);
+                o = sc <= jr ? cand : o;
+            }
+            const i32 so = __shfl(srel, o, kWave);
+            if (j < B) {
+                const i32 n = pins[j];
+                keys[j] = ((u32)n << 1) | (jr < so ? 1u : 0u);
+                vals[j] = ((u64)(u32)(base + o) << 32) | (u64)(u32)j;
+            }
+        }
+    }
+}
+
 __global__ void k_pins16(i64 P, const i32* __restrict__ pins, unsigned short* p16) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (i64)gridDim.x * blockDim.x)
         p16[i] = (unsigned short)pins[i];
@@ -751,9 +792,14 @@ void build_incidence(Ctx* c, Level& L) {
     L.b_inc_off = c->alloc(sizeof(i64) * ((size_t)L.N + 1));
     L.b_inc = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
     L.b_inc_pos = c->alloc(sizeof(i32) * (size_t)(P > 0 ? P : 1));
-    if (L.E > 0)
-        LAUNCH(c, KF_TRANSPOSE, k_pin_keys, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(), L.he_nsrc(),
-               L.pins(), keys, vals);
+    if (L.E > 0) {
+        if (P < (i64)kPinKeysFlatMean * L.E)  // a few pins per h-edge: flat over each window's pins
+            LAUNCH(c, KF_TRANSPOSE, k_pin_keys_flat, grid_for(ceil_div((i64)L.E, (i64)kWave), 4, c->num_cu * 16), 256,
+                   0, L.E, L.he_off(), L.he_nsrc(), L.pins(), keys, vals);
+        else
+            LAUNCH(c, KF_TRANSPOSE, k_pin_keys, grid_for(L.E, 4, c->num_cu * 16), 256, 0, L.E, L.he_off(),
+                   L.he_nsrc(), L.pins(), keys, vals);
+    }
     // Stable sort by (node, source flag): per node its inbound h-edges first,
     // each group in ascending h-edge order, since pins are stored by h-edge.
     sort_pairs_u32_u64(c, keys, keys_out, vals, vals_out, P, bits_for(2ull * (u64)L.N));
