@@ -50,8 +50,8 @@ TRAFFIC_SOURCES = {
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
-    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16643042806,
-    ("k_gains16", "b1669d7b1659b8e798f5e16d669674602c40e91f0ae9c14ed998c7fbd72b872f"): 4290220045,
+    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16637355755,
+    ("k_gains16", "b1669d7b1659b8e798f5e16d669674602c40e91f0ae9c14ed998c7fbd72b872f"): 4290207056,
 }
 
 
