@@ -50,7 +50,7 @@ TRAFFIC_SOURCES = {
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
-    ("k_propose", "c0d3fcc07cef62c2e98dfde684b351da6b04e41c90076224f75b645f7a6c809d"): 16637355755,
+    ("k_propose", "ceba8c1d7c5e9987da1de801fab8d003ec1ebc123fc0ae3e26161dcd2f117bd4"): 16637355755,
     ("k_gains16", "b1669d7b1659b8e798f5e16d669674602c40e91f0ae9c14ed998c7fbd72b872f"): 4290207056,
 }
 
@@ -164,8 +164,9 @@ STREAM_FAMILIES = ("phi", "part_stats", "inseq", "contract_edges", "pack")
 
 
 def batched_leg(args):
-    """Job stream (config 5: the five workload families, log-uniform 2,048 to
-    batch_max_nodes nodes, job i seeded with i): the plain one-at-a-time rate
+    """Job stream (batch_jobs jobs, 256 by default, of the five workload
+    families, log-uniform 2,048 to batch_max_nodes nodes, job i seeded with
+    i): the plain one-at-a-time rate
     with every job waiting from the start, the batched rate the same way, then
     Poisson arrivals (seed 12,345) at 1.5x the plain rate served by one worker
     (plain) and by batch_workers concurrent workers (batched).  Latency =
@@ -300,8 +301,7 @@ def _roofline_entry(kernel, bound, achieved, peak, unit, traffic_bytes, **extra)
 def main():
     args = _args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(sharding across GPUs is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: the partitioner runs on one GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.sweep:
         sweep(args)

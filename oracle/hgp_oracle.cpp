@@ -9,7 +9,7 @@
 // HIP sources.
 //
 // Everything is integer.  Where the paper is silent or ambiguous the reading
-// taken is named inline as "Reading Rk"; the design doc lists all of them.
+// taken is named inline as "Reading Rk" and stated where it is applied.
 //
 // Parity status per function (what pins each one; see tests/test_oracle_*.py):
 //   evaluate / phi            pinned: incidence-matrix products, closed forms,

@@ -760,8 +760,9 @@ __device__ __forceinline__ void propose_hash_body(
 // The kernel for 32-bit bins asks for five waves per SIMD (at most 102 VGPRs;
 // the register allocator spills a handful of cold values to scratch): a fifth
 // more waves to hide the pin loads' latency measured 857 -> 809 ms per
-// partitioning of config 3(b).  With 64-bit bins the same request spilled
-// 30-99 registers, so that kernel keeps the compiler's choice.
+// partitioning of the 6.9 M-node convolutional graph.  With 64-bit bins the
+// same request spilled 30-99 registers, so that kernel keeps the compiler's
+// choice.
 template <typename BIN, int PI>
 __global__ __launch_bounds__(256) void k_propose_hash(
     i32 N, const i64* __restrict__ inc_off, const i32* __restrict__ inc_nin, const i32* __restrict__ inc,
