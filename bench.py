@@ -249,7 +249,7 @@ def sweep(args):
     import paper_2605_20497_amd as pkg
     from paper_2605_20497_amd import workloads as W
 
-    hg = W.CONFIGS[args.sweep_workload]()
+    hg = W.WORKLOADS[args.sweep_workload]()
     torch.cuda.set_device(0)
 
     def run(pi, theta, no_chains=False, greedy=False):
@@ -312,7 +312,7 @@ def main():
     import paper_2605_20497_amd as pkg
     from paper_2605_20497_amd import workloads as W
 
-    hg = W.CONFIGS[args.workload]()
+    hg = W.WORKLOADS[args.workload]()
     print("bench: %s generated, %d nodes, %d pins" % (args.workload, hg.n_nodes, hg.n_pins), file=sys.stderr,
           flush=True)
     dev = torch.device("cuda:0")

@@ -93,7 +93,7 @@ def _time_partition(hg, tune, device):
 def tune_partition(workload: str, device: int = 0, path: str = CACHE, log=print) -> dict:
     """Coordinate search over hash_log2, then list_gate, on one workload."""
     from paper_2605_20497_amd import workloads as W
-    hg = W.CONFIGS[workload]()
+    hg = W.WORKLOADS[workload]()
     cur = {"hash_log2": DEFAULT["hash_log2"], "list_gate": DEFAULT["list_gate"]}
     timings = {}
     for key, values in (("hash_log2", HASH_LOG2), ("list_gate", LIST_GATE)):

@@ -137,12 +137,12 @@ def random_snn(n: int, fanout: int, seed: int = 0, omega: int = 0, delta: int = 
     return _assemble_uniform(n, src, dst, omega=omega, delta=delta, name=name)
 
 
-def config1(seed: int = 0) -> Hypergraph:
+def rand_4k_e32(seed: int = 0) -> Hypergraph:
     """4,096 nodes, 4,096 h-edges of size 32 (131,072 pins), Omega=256, Delta=1,024."""
     return random_snn(4096, 31, seed, omega=256, delta=1024, name="rand-4k-e32")
 
 
-def config2(seed: int = 0) -> Hypergraph:
+def rand_64k_e192(seed: int = 0) -> Hypergraph:
     """65,536 nodes, 65,536 h-edges of size 192 (12,582,912 pins), Omega=2^10, Delta=2^12."""
     return random_snn(65536, 191, seed, omega=1 << 10, delta=1 << 12, name="rand-64k-e192")
 
@@ -174,7 +174,7 @@ def layered_snn(layers: int, width: int, fanout: int, window: int, local_frac: f
                              omega=omega, delta=delta, name=name)
 
 
-def config3a(seed: int = 0) -> Hypergraph:
+def layered_256k_e256(seed: int = 0) -> Hypergraph:
     """8 layers x 32,768 nodes, |e|=256 (204 local in a 2,048 window + 51 uniform): 67M pins."""
     return layered_snn(8, 32768, 255, 2048, 0.8, seed, omega=1 << 12, delta=1 << 16,
                        name="layered-256k-e256")
@@ -258,7 +258,7 @@ def conv_snn(layers: int, hw: int, channels: int, mean_fanout: float, seed: int 
                       np.ones(n, np.int32), omega=omega, delta=delta, name=name)
 
 
-def config3b(seed: int = 0, progress=None) -> Hypergraph:
+def conv_6_9m(seed: int = 0, progress=None) -> Hypergraph:
     """7 layers of 176x176x32 (6,938,624 nodes), Poisson(82) fanout: ~577M pins."""
     return conv_snn(7, 176, 32, 82.0, seed, omega=1 << 12, delta=1 << 16, name="conv-6.9m", progress=progress)
 
@@ -327,7 +327,7 @@ def netlist(n: int, n_nets: int, smin: int, smax: int, alpha: float, local: int,
     return _assemble(n, srcs, dsts, node_w=node_w, omega=omega, delta=delta, k=k, name=name)
 
 
-def config4(seed: int = 0) -> Hypergraph:
+def netlist_500k(seed: int = 0) -> Hypergraph:
     """500k cells, 550k nets, sizes ~ s^-2.827 on [2, 2000], weights in [1, 8], k=64, eps=3%."""
     return netlist(500_000, 550_000, 2, 2000, 2.827, 2048, 0.9, 8, seed, k=64,
                    name="netlist-500k")
@@ -424,10 +424,10 @@ def job_stream(n_jobs: int = 256, min_nodes: int = 2048, max_nodes: int = 262144
     return jobs, arrivals
 
 
-CONFIGS = {
-    "rand-4k-e32": config1,
-    "rand-64k-e192": config2,
-    "layered-256k-e256": config3a,
-    "conv-6.9m": config3b,
-    "netlist-500k": config4,
+WORKLOADS = {
+    "rand-4k-e32": rand_4k_e32,
+    "rand-64k-e192": rand_64k_e192,
+    "layered-256k-e256": layered_256k_e256,
+    "conv-6.9m": conv_6_9m,
+    "netlist-500k": netlist_500k,
 }

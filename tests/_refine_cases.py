@@ -93,7 +93,7 @@ def gains_variant(name):
 FULL = {
     # the 65,536-node random SNN workload with a random partition over 2,872
     # parts and a Delta loose enough that refinement commits
-    "rand-64k-e192-rho2872": dict(hg=lambda: W.config2(), nparts=2872, seed=7, delta=1 << 20),
+    "rand-64k-e192-rho2872": dict(hg=lambda: W.rand_64k_e192(), nparts=2872, seed=7, delta=1 << 20),
     # 8,192 nodes in 65,536 h-edges of 64 pins: every node meets ~512 h-edges
     # and the in-isolation moves fit the dense product
     "dense-8k-e65k-rho1024": dict(hg=lambda: many_sources_hypergraph(8192, 65536, 63, 21), nparts=1024, seed=8,

@@ -27,7 +27,7 @@ def digest(a) -> str:
 
 
 def main(name: str, Pi: int = 4, theta: int = 16, seed: int = 0):
-    hg = W.CONFIGS[name]()
+    hg = W.WORKLOADS[name]()
     g = oracle.Graph(hg)
     t0 = time.time()
     res = g.partition(hg.omega, hg.delta, k=hg.k, Pi=Pi, theta=theta, seed=seed)

@@ -29,10 +29,10 @@ SAMPLE = 48
 def _gen(name):
     t0 = time.time()
     if name == "conv-6.9m":
-        hg = W.config3b(progress=lambda d, n: print("generated %d/%d rows (%.0f s)" % (d, n, time.time() - t0),
+        hg = W.conv_6_9m(progress=lambda d, n: print("generated %d/%d rows (%.0f s)" % (d, n, time.time() - t0),
                                                     flush=True))
     else:
-        hg = W.CONFIGS[name]()
+        hg = W.WORKLOADS[name]()
     print("case", name, "N", hg.n_nodes, "E", hg.n_hedges, "P", hg.n_pins, flush=True)
     return hg
 

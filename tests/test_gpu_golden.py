@@ -32,7 +32,7 @@ def _golden(name):
 def test_full_size_against_oracle_digests(name):
     from paper_2605_20497_amd import Partitioner
     gold = _golden(name)
-    hg = W.CONFIGS[name]()
+    hg = W.WORKLOADS[name]()
     print("case", name, "N", hg.n_nodes, "P", hg.n_pins, flush=True)
     g = Partitioner(pi=gold["pi"], theta=gold["theta"], seed=gold["seed"])
     g.load(hg)

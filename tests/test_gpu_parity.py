@@ -95,14 +95,14 @@ def test_small_random_dense_proposal(case):
     _compare_runs(hg, omega, delta, label="dense-%d" % seed, dense=True)
 
 
-def test_dense_proposal_snn_and_config1():
+def test_dense_proposal_snn_and_rand_4k_e32():
     hg = W.random_snn(1024, 15, 3)
     _compare_runs(hg, 64, 256, label="snn-1k-dense", dense=True)
     hg = W.random_snn(4096, 95, 6)
     _compare_runs(hg, 256, 1024, label="snn-4k-e96-dense", dense=True)
     hg = W.layered_snn(4, 512, 31, 128, 0.8, seed=1)
     _compare_runs(hg, 64, 512, label="layered-2k-dense", dense=True)
-    hg = W.config1()
+    hg = W.rand_4k_e32()
     _compare_runs(hg, hg.omega, hg.delta, label="rand-4k-e32-dense", dense=True)
 
 
@@ -129,8 +129,8 @@ def test_pi_and_theta_variants():
     _compare_runs(hg, 48, 200, Pi=8, theta=6, seed=5, label="pi8")
 
 
-def test_config1_full():
-    hg = W.config1()
+def test_rand_4k_e32_full():
+    hg = W.rand_4k_e32()
     _compare_runs(hg, hg.omega, hg.delta, label="rand-4k-e32")
 
 
