@@ -62,47 +62,67 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_count(i64 n, const K* __res
 
 // Stable ranks of one tile (up to kSortTile elements from `kin`/`vin`) into
 // shared memory ordered by digit.  dstart[d] = first tile position of digit
-// d, which the caller has filled.  Shared arrays: wc[kSortWaves][kBuckets]
-// and run[kBuckets] are scratch.
+// d, which the caller has filled.  Each wave ranks its own contiguous quarter
+// of the tile, kSortChunks rounds of 64 elements against digit counters of its
+// own (wave-level ordering only, no block barrier per round); one block-wide
+// pass then offsets each wave's counts by those of the waves before it, so
+// equal digits keep their input order.  The elements stay in registers
+// between the two phases.  wc[kSortWaves][kBuckets] is scratch.
 template <typename K, typename V>
 __device__ __forceinline__ void rank_tile(i64 nt, const K* __restrict__ kin, const V* __restrict__ vin, int shift,
-                                          const u32* dstart, u32 (*wc)[kBuckets], u32* run, K* sk, V* sv) {
+                                          const u32* dstart, u32 (*wc)[kBuckets], K* sk, V* sv) {
+    static_assert(kBuckets == kSortThreads, "one thread per digit in the cross-wave pass");
     const int lane = lane_id(), wv = wave_id();
     const u64 lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    run[threadIdx.x] = 0;
-    for (int c = 0; c < kSortChunks; ++c) {
-        const i64 i = (i64)c * kSortThreads + threadIdx.x;
-        const int valid = (int)(i < nt);
-        const K k = valid ? kin[i] : (K)0;
-        const V v = valid ? vin[i] : (V)0;
-        const u32 d = digit_of(k, shift);
+    u32* mine = wc[wv];
+    for (int d = lane; d < kBuckets; d += kWave) mine[d] = 0;
+    const i64 w0 = (i64)wv * (kWave * kSortChunks) + lane;  // this lane's first element
+    K kk[kSortChunks];
+    V vv[kSortChunks];
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) wc[w][threadIdx.x] = 0;
-        __syncthreads();
+    for (int c = 0; c < kSortChunks; ++c) {
+        const i64 i = w0 + (i64)c * kWave;
+        const bool valid = i < nt;
+        kk[c] = valid ? kin[i] : (K)0;
+        vv[c] = valid ? vin[i] : (V)0;
+    }
+    wave_sync();  // counters cleared
+    u32 rr[kSortChunks];
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c) {
+        const int valid = (int)(w0 + (i64)c * kWave < nt);
+        const u32 d = digit_of(kk[c], shift);
         const u64 peers = digit_peers(d, valid);
         const u32 r = (u32)__popcll(peers & lt);
-        if (valid & (int)(r == 0)) wc[wv][d] = (u32)__popcll(peers);
-        __syncthreads();
-        {
-            // digit t: exclusive prefix over the waves, from the digit's run
-            const int t = threadIdx.x;
-            u32 acc = run[t];
-#pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
-                const u32 x = wc[w][t];
-                wc[w][t] = acc;
-                acc += x;
-            }
-            run[t] = acc;
-        }
-        __syncthreads();
-        if (valid) {
-            const u32 pos = dstart[d] + wc[wv][d] + r;
-            sk[pos] = k;
-            sv[pos] = v;
-        }
-        __syncthreads();  // wc is cleared by the next chunk
+        const u32 before = mine[d];
+        rr[c] = before + r;
+        wave_sync();  // every lane has read its digit's count before the first lane of the digit moves it
+        if (valid & (int)(r == 0)) mine[d] = before + (u32)__popcll(peers);
+        wave_sync();
     }
+    __syncthreads();
+    {
+        // digit t: exclusive prefix of the waves' counts, in wave order
+        const int t = threadIdx.x;
+        u32 acc = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            const u32 x = wc[w][t];
+            wc[w][t] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c) {
+        if (w0 + (i64)c * kWave < nt) {
+            const u32 d = digit_of(kk[c], shift);
+            const u32 pos = dstart[d] + mine[d] + rr[c];
+            sk[pos] = kk[c];
+            sv[pos] = vv[c];
+        }
+    }
+    __syncthreads();  // the tile is in shared memory, and wc is free again
 }
 
 // Exclusive scan of one value per thread over the block (256 threads).
@@ -123,7 +143,6 @@ struct SortShared {
     K sk[kSortTile];
     V sv[kSortTile];
     u32 wc[kSortWaves][kBuckets];
-    u32 run[kBuckets];
     u32 dstart[kBuckets];
     u32 gpos[kBuckets];
     u32 tmp[kSortWaves];
@@ -143,7 +162,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(i64 n, const K* __r
     sh.gpos[d] = pos[(i64)d * ntiles + blockIdx.x];
     sh.dstart[d] = block_excl_u32(c, sh.tmp);
     __syncthreads();
-    rank_tile<K, V>(nt, kin + base, vin + base, shift, sh.dstart, sh.wc, sh.run, sh.sk, sh.sv);
+    rank_tile<K, V>(nt, kin + base, vin + base, shift, sh.dstart, sh.wc, sh.sk, sh.sv);
     // each digit's run to its output position: consecutive positions of the
     // reordered tile go to consecutive addresses
     for (int j = threadIdx.x; j < nt; j += kSortThreads) {
@@ -206,7 +225,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_small(i64 n, const K* __res
         const bool to_first = (npass++ % 2) == 0;
         K* dk = to_first ? sh.sk : bk;
         V* dv = to_first ? sh.sv : bv;
-        rank_tile<K, V>(n, src_k, src_v, shift, sh.dstart, sh.wc, sh.run, dk, dv);
+        rank_tile<K, V>(n, src_k, src_v, shift, sh.dstart, sh.wc, dk, dv);
         src_k = dk;
         src_v = dv;
     }
