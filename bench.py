@@ -50,8 +50,8 @@ TRAFFIC_SOURCES = {
 }
 TRAFFIC = {  # {(kernel, sources_sha256): bytes per launch}
     # conv-6.9m, profiles/hbm_counters_conv-6.9m.txt (family averages)
-    ("k_propose", "ceba8c1d7c5e9987da1de801fab8d003ec1ebc123fc0ae3e26161dcd2f117bd4"): 16637355755,
-    ("k_gains16", "b1669d7b1659b8e798f5e16d669674602c40e91f0ae9c14ed998c7fbd72b872f"): 4290207056,
+    ("k_propose", "ceba8c1d7c5e9987da1de801fab8d003ec1ebc123fc0ae3e26161dcd2f117bd4"): 16569862888,
+    ("k_gains16", "b1669d7b1659b8e798f5e16d669674602c40e91f0ae9c14ed998c7fbd72b872f"): 4293562929,
 }
 
 
