@@ -7,10 +7,11 @@
 //  - an exclusive scan of cnt in that order, giving each (digit, tile) its
 //    first output position (all tiles' digit-0 elements first, in tile order);
 //  - k_rs_scatter: per tile, a stable rank of every element within its digit
-//    (the tile is taken 256 elements at a time in input order; inside a
-//    chunk, lanes holding the same digit are found with eight ballots), the
-//    tile reordered by digit in shared memory, then each digit's run written
-//    to its output position by consecutive threads at consecutive addresses.
+//    (each wave ranks its contiguous quarter 64 elements at a time, lanes
+//    holding the same digit found with eight ballots; one pass then orders
+//    the waves), the tile reordered by digit in shared memory, then each
+//    digit's run written to its output position by consecutive threads at
+//    consecutive addresses.
 // Up to kSortTile elements are sorted in one workgroup (k_rs_small): every
 // pass in shared memory, with the same stable ranking.
 #include "dev_util.h"
